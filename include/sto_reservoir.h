@@ -1,0 +1,173 @@
+/*
+ * sto_reservoir.h -- C ABI of the MI355X coupled spin-torque-oscillator
+ * reservoir library (libsto_reservoir.so, HIP for gfx950).
+ *
+ * The library integrates N coupled macrospins with the Landau-Lifshitz-
+ * Gilbert equation plus Slonczewski spin-transfer torque (paper, Sec. 3.1,
+ * Eq. (gov)), coupled through a dense N x N matrix (Eq. (coup)) and driven
+ * by an input series (Eq. (in)), with classic fourth-order Runge-Kutta at a
+ * fixed step (Sec. 3.2).  It records the 3N-dimensional state once per input
+ * sample (the N node states are the reservoir nodes, Sec. 3.1) and fits a
+ * ridge-regression readout (the paper trains only the readout, Sec. 1).
+ *
+ * Conventions for every entry point:
+ *   - The return value is an sto_status; 0 is success.  No exception or
+ *     C++ object crosses this boundary.  After a non-OK status,
+ *     sto_last_error() returns a message for the calling thread.
+ *   - Host pointers are plain CPU memory; "device" pointers are HIP device
+ *     memory on the current device.  The caller owns every buffer it
+ *     passes; the library never frees caller memory.
+ *   - Matrices are row-major, states are array-of-structures (x, y, z) per
+ *     node, records are [sample][node][component].
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef STO_RESERVOIR_H
+#define STO_RESERVOIR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    STO_OK = 0,
+    STO_E_INVALID = -1,      /* bad argument (size, pointer, value)          */
+    STO_E_NOMEM = -2,        /* device or host allocation failed             */
+    STO_E_DEVICE = -3,       /* a HIP call failed                            */
+    STO_E_NONFINITE = -4,    /* the state became NaN or infinite             */
+    STO_E_UNSUPPORTED = -5   /* valid request this build does not provide    */
+} sto_status;
+
+typedef enum { STO_F64 = 0, STO_F32 = 1 } sto_dtype;
+
+/* STO_COUPLE_X is Eq. (coup): only m^x couples, into e_x.
+ * STO_COUPLE_XYZ couples all three components into the matching field
+ * components (an isotropic variant the paper does not use). */
+typedef enum { STO_COUPLE_X = 0, STO_COUPLE_XYZ = 1 } sto_coupling;
+
+/* Kernel family.  AUTO picks by size; the others force one family (for
+ * testing each at any size where it applies). */
+typedef enum {
+    STO_PATH_AUTO = 0,
+    STO_PATH_SMALL = 1,     /* one workgroup holds W and the state; all steps in one launch */
+    STO_PATH_RESIDENT = 2,  /* W split across the CUs' LDS; all steps in one cooperative launch */
+    STO_PATH_STREAM = 3     /* W streamed from HBM once per RK4 stage, one launch per stage */
+} sto_path;
+
+/*
+ * Constants of Eq. (gov) in dimensionless form: time in units of t0 = 1 ns,
+ * fields in units of 1/(gamma t0) (56.689 Oe for gamma = 1.764e7 rad/(Oe s)).
+ * With b the total field of Eq. (gov) in that unit,
+ *   dm_k/dtau = -1/(1+alpha^2) m_k x b_k - alpha/(1+alpha^2) m_k x (m_k x b_k),
+ *   b_k = (h_appl + h_k m_k^z) e_z + a_cp (W m^x)_k e_x + a_in (w_in u)_k e_x
+ *         + h_s / (1 + lambda_stt m_k . p) * (p x m_k).
+ * h_k is gamma t0 (H_K - 4 pi M); h_s is gamma t0 hbar eta I / (2 e M V).
+ */
+typedef struct {
+    double alpha;        /* Gilbert damping                                    */
+    double h_appl;       /* applied field                                      */
+    double h_k;          /* anisotropy minus demagnetisation field             */
+    double h_s;          /* spin-torque field amplitude                        */
+    double lambda_stt;   /* spin-torque asymmetry                              */
+    double p[3];         /* pinned-layer direction                             */
+    double a_cp;         /* coupling amplitude                                 */
+    double a_in;         /* input amplitude                                    */
+    double dt;           /* RK4 step (0.01 = 1e-11 s)                          */
+    int32_t substeps;    /* RK4 steps per input sample (>= 1)                  */
+    int32_t renormalize; /* 1: m_k <- m_k/|m_k| after every step (default 0)   */
+    int32_t dtype;       /* sto_dtype of the device arithmetic and storage     */
+    int32_t coupling;    /* sto_coupling                                       */
+    int32_t path;        /* sto_path                                           */
+    int32_t reserved;    /* must be 0                                          */
+} sto_params;
+
+typedef struct sto_reservoir sto_reservoir;
+
+/*
+ * reservoir_create -- build a reservoir on the current HIP device.
+ *   n      number of oscillators (nodes), n >= 1
+ *   n_in   number of input channels, n_in >= 1
+ *   prm    constants (copied); dt > 0, substeps >= 1, finite values
+ *   W      host, n*n doubles, coupling matrix (Eq. (coup)), used as given
+ *          (its diagonal is not forced to zero)
+ *   w_in   host, n*n_in doubles, input weights (Eq. (in))
+ *   m0     host, n*3 doubles, initial unit magnetisations (|m0_k| = 1
+ *          within 1e-12, else STO_E_INVALID)
+ *   out    receives the handle
+ * The handle owns device copies of W, w_in and the state, converted to
+ * prm->dtype.  Errors: STO_E_INVALID, STO_E_NOMEM, STO_E_DEVICE,
+ * STO_E_UNSUPPORTED (a forced path that cannot hold this size).
+ */
+sto_status reservoir_create(int64_t n, int64_t n_in, const sto_params *prm,
+                            const double *W, const double *w_in, const double *m0,
+                            sto_reservoir **out);
+
+/*
+ * reservoir_run -- integrate steps RK4 steps from the current state.
+ *   u       host, (steps/substeps) * n_in doubles, one input vector per
+ *           sample, held for substeps steps (all four stages of a step see
+ *           the same sample)
+ *   steps   multiple of substeps (else STO_E_INVALID); 0 is a no-op
+ *   states  host, (steps/substeps) * n * 3 doubles, receives the state after
+ *           the last step of every sample; may be NULL
+ * Runs continue from the state the previous run ended in: running u[:a]
+ * then u[a:] gives bitwise the same records as running u.  Blocks until
+ * done.  On STO_E_NONFINITE the records before the first sample whose state
+ * is not finite are valid, and sto_last_error() names that sample.
+ */
+sto_status reservoir_run(sto_reservoir *r, const double *u, int64_t steps, double *states);
+
+/*
+ * reservoir_run_device -- as reservoir_run, on device buffers and a stream.
+ *   u_dev       device, (steps/substeps) * n_in doubles
+ *   states_dev  device, (steps/substeps) * n * 3 elements of the handle's
+ *               dtype (double or float); may be NULL
+ *   hip_stream  hipStream_t to enqueue on (NULL: the null stream)
+ * Work is enqueued on hip_stream; the call returns after the stream has
+ * finished the run so that a non-finite state can be reported.
+ */
+sto_status reservoir_run_device(sto_reservoir *r, const void *u_dev, int64_t steps,
+                                void *states_dev, void *hip_stream);
+
+/* reservoir_get_state / reservoir_set_state -- copy the current state
+ * (host, n*3 doubles, AoS) out of / into the handle.  set_state checks
+ * finiteness only; it does not renormalise. */
+sto_status reservoir_get_state(const sto_reservoir *r, double *m);
+sto_status reservoir_set_state(sto_reservoir *r, const double *m);
+
+/* reservoir_path -- the sto_path the handle runs (never STO_PATH_AUTO). */
+int32_t reservoir_path(const sto_reservoir *r);
+
+/* reservoir_destroy -- free the handle and its device memory; NULL is a no-op. */
+void reservoir_destroy(sto_reservoir *r);
+
+/*
+ * readout_fit -- ridge-regression readout, computed in FP64 on the GPU.
+ *   states    host, T * n * 3 doubles (the records of a run)
+ *   y         host, T doubles, target per record
+ *   washout   rows n < washout are skipped; 0 <= washout < T
+ *   lambda    ridge penalty (>= 0) on every weight, bias included
+ *   features  0: m^x of every node; 1: all three components
+ *   w_out     host, F + 1 doubles (F = n or 3n): weights, bias last
+ *   nmse_out  host, 1 double: sum (y - Phi w)^2 / sum (y - mean y)^2 over
+ *             the fitted rows
+ * Solves (Phi^T Phi + lambda I) w = Phi^T y by Cholesky when the fitted
+ * rows are at least the columns, else the equivalent dual system
+ * (Phi Phi^T + lambda I) a = y, w = Phi^T a.  Errors: STO_E_INVALID (also
+ * when the system is not positive definite), STO_E_NONFINITE (NaN inputs),
+ * STO_E_NOMEM, STO_E_DEVICE.
+ */
+sto_status readout_fit(const double *states, int64_t T, int64_t n, const double *y,
+                       int64_t washout, double lambda, int32_t features,
+                       double *w_out, double *nmse_out);
+
+/* sto_last_error -- message of the last non-OK status on this thread
+ * (empty string if none).  Valid until the next call on this thread. */
+const char *sto_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STO_RESERVOIR_H */

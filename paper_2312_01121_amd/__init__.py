@@ -1,0 +1,234 @@
+"""Python binding of libsto_reservoir.so (the MI355X coupled-STO reservoir).
+
+A thin ctypes layer over ``include/sto_reservoir.h``: the functions below
+carry the C entry points' names and only marshal arguments; every step of
+the computation runs in the library's HIP kernels.  PyTorch is used only
+for device buffers and streams (``run_device``).  Importing this package
+fails loudly if the shared library has not been built
+(``python -m paper_2312_01121_amd._build``).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+from . import params  # noqa: F401
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsto_reservoir.so")
+
+STO_OK, STO_E_INVALID, STO_E_NOMEM, STO_E_DEVICE, STO_E_NONFINITE, STO_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+STO_F64, STO_F32 = 0, 1
+STO_COUPLE_X, STO_COUPLE_XYZ = 0, 1
+PATH_AUTO, PATH_SMALL, PATH_RESIDENT, PATH_STREAM = 0, 1, 2, 3
+PATH_NAMES = {PATH_SMALL: "small", PATH_RESIDENT: "resident", PATH_STREAM: "stream"}
+_STATUS_NAMES = {STO_E_INVALID: "invalid", STO_E_NOMEM: "nomem", STO_E_DEVICE: "device",
+                 STO_E_NONFINITE: "nonfinite", STO_E_UNSUPPORTED: "unsupported"}
+
+
+class StoError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"[{_STATUS_NAMES.get(status, status)}] {message}")
+        self.status = status
+
+
+class sto_params(ctypes.Structure):
+    _fields_ = [
+        ("alpha", ctypes.c_double), ("h_appl", ctypes.c_double), ("h_k", ctypes.c_double),
+        ("h_s", ctypes.c_double), ("lambda_stt", ctypes.c_double), ("p", ctypes.c_double * 3),
+        ("a_cp", ctypes.c_double), ("a_in", ctypes.c_double), ("dt", ctypes.c_double),
+        ("substeps", ctypes.c_int32), ("renormalize", ctypes.c_int32), ("dtype", ctypes.c_int32),
+        ("coupling", ctypes.c_int32), ("path", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+def make_params(alpha, h_appl, h_k, h_s, lambda_stt, p, a_cp, a_in, dt, substeps=20,
+                renormalize=False, dtype="f64", coupling="x", path="auto") -> sto_params:
+    pr = sto_params()
+    pr.alpha, pr.h_appl, pr.h_k, pr.h_s, pr.lambda_stt = alpha, h_appl, h_k, h_s, lambda_stt
+    pr.p[0], pr.p[1], pr.p[2] = p
+    pr.a_cp, pr.a_in, pr.dt = a_cp, a_in, dt
+    pr.substeps = int(substeps)
+    pr.renormalize = int(bool(renormalize))
+    pr.dtype = {"f64": STO_F64, "f32": STO_F32}[dtype]
+    pr.coupling = {"x": STO_COUPLE_X, "xyz": STO_COUPLE_XYZ}[coupling]
+    pr.path = {"auto": PATH_AUTO, "small": PATH_SMALL, "resident": PATH_RESIDENT, "stream": PATH_STREAM}[path]
+    pr.reserved = 0
+    return pr
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2312_01121_amd._build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    dp = ctypes.POINTER(ctypes.c_double)
+    vp = ctypes.c_void_p
+    H = ctypes.c_void_p
+    lib.reservoir_create.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(sto_params), dp, dp, dp,
+                                     ctypes.POINTER(H)]
+    lib.reservoir_run.argtypes = [H, dp, ctypes.c_int64, dp]
+    lib.reservoir_run_device.argtypes = [H, vp, ctypes.c_int64, vp, vp]
+    lib.reservoir_get_state.argtypes = [H, dp]
+    lib.reservoir_set_state.argtypes = [H, dp]
+    lib.reservoir_path.argtypes = [H]
+    lib.reservoir_path.restype = ctypes.c_int32
+    lib.reservoir_destroy.argtypes = [H]
+    lib.reservoir_destroy.restype = None
+    lib.readout_fit.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, dp, ctypes.c_int64, ctypes.c_double,
+                                ctypes.c_int32, dp, dp]
+    lib.sto_last_error.restype = ctypes.c_char_p
+    for name in ("reservoir_create", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
+                 "reservoir_set_state", "readout_fit"):
+        getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+_lib = _load()
+
+EXPORTED = ("reservoir_create", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
+            "reservoir_set_state", "reservoir_path", "reservoir_destroy", "readout_fit", "sto_last_error")
+
+
+def lib():
+    return _lib
+
+
+def sto_last_error() -> str:
+    return _lib.sto_last_error().decode()
+
+
+def _check(status: int):
+    if status != STO_OK:
+        raise StoError(status, sto_last_error())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a, shape=None) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def reservoir_create(n: int, n_in: int, prm: sto_params, W, w_in, m0) -> ctypes.c_void_p:
+    W = _f64(W, (n, n))
+    w_in = _f64(w_in, (n, n_in))
+    m0 = _f64(m0, (n, 3))
+    h = ctypes.c_void_p()
+    _check(_lib.reservoir_create(n, n_in, ctypes.byref(prm), _dptr(W), _dptr(w_in), _dptr(m0), ctypes.byref(h)))
+    return h
+
+
+def reservoir_run(h, u, steps: int, states: Optional[np.ndarray] = None):
+    """u: (samples, n_in) float64; states: None or a C-contiguous float64
+    array of (samples, n, 3) that receives the records."""
+    u = _f64(u)
+    if states is not None:
+        assert states.dtype == np.float64 and states.flags.c_contiguous
+    _check(_lib.reservoir_run(h, _dptr(u), steps, _dptr(states) if states is not None else None))
+
+
+def reservoir_run_device(h, u_dev_ptr: int, steps: int, states_dev_ptr: Optional[int], stream_ptr: Optional[int]):
+    _check(_lib.reservoir_run_device(h, ctypes.c_void_p(u_dev_ptr), steps,
+                                     ctypes.c_void_p(states_dev_ptr) if states_dev_ptr else None,
+                                     ctypes.c_void_p(stream_ptr) if stream_ptr else None))
+
+
+def reservoir_get_state(h, n: int) -> np.ndarray:
+    m = np.empty((n, 3))
+    _check(_lib.reservoir_get_state(h, _dptr(m)))
+    return m
+
+
+def reservoir_set_state(h, m):
+    m = _f64(m)
+    _check(_lib.reservoir_set_state(h, _dptr(m)))
+
+
+def reservoir_path(h) -> int:
+    return int(_lib.reservoir_path(h))
+
+
+def reservoir_destroy(h):
+    if h:
+        _lib.reservoir_destroy(h)
+
+
+def readout_fit(states, y, washout: int, lam: float, features: int = 0) -> Tuple[np.ndarray, float]:
+    states = _f64(states)
+    T, n, _ = states.shape
+    y = _f64(y).ravel()
+    cols = (3 * n if features else n) + 1
+    w = np.empty(cols)
+    nmse = np.empty(1)
+    _check(_lib.readout_fit(_dptr(states), T, n, _dptr(y), washout, lam, features, _dptr(w), _dptr(nmse)))
+    return w, float(nmse[0])
+
+
+class Reservoir:
+    """Owns one library handle; every method calls the C entry point of the same name."""
+
+    def __init__(self, W, w_in, m0, prm: sto_params):
+        W = np.asarray(W)
+        self.n = W.shape[0]
+        w_in = np.asarray(w_in, dtype=np.float64).reshape(self.n, -1)
+        self.n_in = w_in.shape[1]
+        self.substeps = prm.substeps
+        self.dtype = "f64" if prm.dtype == STO_F64 else "f32"
+        self.h = reservoir_create(self.n, self.n_in, prm, W, w_in, m0)
+
+    @property
+    def path(self) -> str:
+        return PATH_NAMES[reservoir_path(self.h)]
+
+    def run(self, u, record: bool = True) -> Optional[np.ndarray]:
+        u = _f64(u).reshape(-1, self.n_in)
+        steps = len(u) * self.substeps
+        states = np.empty((len(u), self.n, 3)) if record else None
+        reservoir_run(self.h, u, steps, states)
+        return states
+
+    def run_device(self, u_dev, states_dev=None, stream=None):
+        """u_dev: CUDA float64 tensor (samples, n_in); states_dev: CUDA tensor
+        (samples, n, 3) of the handle's dtype, or None; stream: a
+        torch.cuda.Stream (default: the current stream)."""
+        import torch
+        assert u_dev.is_cuda and u_dev.dtype == torch.float64 and u_dev.is_contiguous()
+        samples = u_dev.numel() // self.n_in
+        if states_dev is not None:
+            want = torch.float64 if self.dtype == "f64" else torch.float32
+            assert states_dev.is_cuda and states_dev.dtype == want and states_dev.is_contiguous()
+            assert states_dev.numel() == samples * self.n * 3
+        s = (stream or torch.cuda.current_stream()).cuda_stream
+        reservoir_run_device(self.h, u_dev.data_ptr(), samples * self.substeps,
+                             states_dev.data_ptr() if states_dev is not None else None, s)
+
+    def get_state(self) -> np.ndarray:
+        return reservoir_get_state(self.h, self.n)
+
+    def set_state(self, m):
+        reservoir_set_state(self.h, np.asarray(m, dtype=np.float64).reshape(self.n, 3))
+
+    def close(self):
+        if getattr(self, "h", None):
+            reservoir_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,64 @@
+// Internal (C++) interface between the C-ABI runtime and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sto_device.hpp"
+
+namespace sto {
+
+// Device buffers of one reservoir, in the handle's arithmetic type T.
+//   W      n rows x ld columns, row-major; columns n..ld-1 are zero
+//   w_in   n x n_in, row-major
+//   m      current state, SoA: m[c*ld + k] for component c of node k
+//   ms[2]  RK4 stage inputs (ping-pong), same layout as m; entries k >= n
+//          stay zero, so the padded columns of W meet zeros
+//   acc    RK4 accumulator k1 + 2k2 + 2k3, same layout
+template <typename T>
+struct DevState {
+    const T* W;
+    const T* w_in;
+    T* m;
+    T* ms[2];
+    T* acc;
+    int* bad;        // first sample index whose state is not finite (INT_MAX: none)
+    int* sync;       // grid-barrier words (cooperative kernels)
+    int n, n_in;
+    int64_t ld;
+};
+
+struct RunSpec {
+    const double* u;     // device, samples x n_in
+    void* states;        // device, samples x n x 3 (T), or nullptr
+    int samples;
+    int substeps;
+    int cur;             // which ms buffer holds the current state
+    int renorm;
+    int xyz;
+    hipStream_t stream;
+};
+
+// Path launchers; each returns the HIP status of its launches.
+template <typename T> hipError_t run_stream(const DevState<T>& d, const Coef<T>& k, const RunSpec& r);
+template <typename T> hipError_t run_small(const DevState<T>& d, const Coef<T>& k, const RunSpec& r);
+template <typename T> hipError_t run_resident(const DevState<T>& d, const Coef<T>& k, const RunSpec& r);
+
+// Largest n the single-workgroup kernel holds (W in LDS).
+int small_max_n(int elem_bytes, int xyz);
+// Whether the resident kernel can hold n on this device (W split across
+// co-resident workgroups' LDS); fills the chosen grid size.
+bool resident_fits(int n, int elem_bytes, int xyz, int* grid_out);
+
+// Offset (in ints) of the abort flag in DevState::sync; non-zero after a
+// resident run means a grid barrier timed out.
+constexpr int kSyncAbortWord = 32;
+
+// Readout (FP64): see readout.hip.
+// rec_dev: rows x n x 3 records (FP64); y_dev: rows targets; w_dev: cols
+// weights.  Returns 0 on success, 1 if the normal-equation matrix is not
+// positive definite, 2 on a HIP error (message in *err).
+int readout_solve(const double* rec_dev, int rows, int n, int features, const double* y_dev, double lam,
+                  double* w_dev, double* nmse_host, hipStream_t stream, const char** err);
+
+}  // namespace sto

@@ -1,0 +1,326 @@
+// RK4 kernels for N coupled spin-torque oscillators on gfx950.
+//
+// One RK4 stage evaluates, for every node k, the coupling contraction
+// c_k = a_cp sum_i W_ki m_i^x over the stage input (paper, Eq. (coup); the
+// only O(N^2) term, Sec. 3.1 and 3.3), then the pointwise right-hand side of
+// Eq. (gov) and the classic RK4 stage bookkeeping (Sec. 3.2).  Two kernel
+// families live here:
+//
+//   k_stage  (STREAM path)  one launch per RK4 stage for any N.  Each wave
+//            owns R rows of W and streams them from HBM with 16-byte
+//            non-temporal loads; the stage input vector is read through the
+//            caches (it is N elements, shared by all rows).  The row sums are
+//            reduced across the wave and the RK4 epilogue is fused, so every
+//            stage is exactly one pass over W.
+//
+//   k_small  (SMALL path)   one workgroup runs the whole trajectory: W and
+//            the stage input live in LDS, each node's state, stage input and
+//            RK4 accumulator live in registers, and L lanes share one node's
+//            row sum.  No launch, no global memory traffic per step beyond
+//            the records.
+
+#include <climits>
+
+#include "sto_internal.hpp"
+
+namespace sto {
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Vec;
+template <> struct Vec<double> { using type = dvec2; static constexpr int n = 2; };
+template <> struct Vec<float> { using type = fvec4; static constexpr int n = 4; };
+
+// ---------------------------------------------------------------------------
+// Shared epilogue: RHS of Eq. (gov) + RK4 stage update for node `row`.
+// ---------------------------------------------------------------------------
+template <typename T, bool XYZ>
+__device__ __forceinline__ void stage_epilogue(const DevState<T>& d, const Coef<T>& k, int row,
+                                               T dot_x, T dot_y, T dot_z, T hin, const T* xin,
+                                               T* xout, int stage, int renorm, T* record,
+                                               int sample) {
+    const int64_t ld = d.ld;
+    T sx = xin[row], sy = xin[ld + row], sz = xin[2 * ld + row];
+    T cx = k.a_cp * dot_x;
+    T cy = XYZ ? k.a_cp * dot_y : T(0);
+    T cz = XYZ ? k.a_cp * dot_z : T(0);
+    T fx, fy, fz;
+    llg_rhs<T, XYZ>(k, sx, sy, sz, cx, cy, cz, hin, fx, fy, fz);
+    T mx = d.m[row], my = d.m[ld + row], mz = d.m[2 * ld + row];
+    T ax = T(0), ay = T(0), az = T(0);
+    if (stage > 0) {
+        ax = d.acc[row];
+        ay = d.acc[ld + row];
+        az = d.acc[2 * ld + row];
+    }
+    T nx = rk4_update(k, stage, mx, ax, fx);
+    T ny = rk4_update(k, stage, my, ay, fy);
+    T nz = rk4_update(k, stage, mz, az, fz);
+    if (stage == 3) {
+        if (renorm) renormalize(nx, ny, nz);
+        d.m[row] = nx;
+        d.m[ld + row] = ny;
+        d.m[2 * ld + row] = nz;
+        if (record) {
+            record[3 * (int64_t)row + 0] = nx;
+            record[3 * (int64_t)row + 1] = ny;
+            record[3 * (int64_t)row + 2] = nz;
+        }
+        if (!finite3(nx, ny, nz)) atomicMin(d.bad, sample);
+    } else {
+        d.acc[row] = ax;
+        d.acc[ld + row] = ay;
+        d.acc[2 * ld + row] = az;
+    }
+    xout[row] = nx;
+    xout[ld + row] = ny;
+    xout[2 * ld + row] = nz;
+}
+
+// ---------------------------------------------------------------------------
+// STREAM path: one RK4 stage.
+// ---------------------------------------------------------------------------
+template <typename T, bool XYZ, int R>
+__global__ void __launch_bounds__(256) k_stage(DevState<T> d, Coef<T> k, const double* __restrict__ u_s,
+                                               T* __restrict__ record, int sample, int stage, int cur,
+                                               int renorm) {
+    using A = Acc<T>;
+    using AT = typename A::type;
+    using V = typename Vec<T>::type;
+    constexpr int VN = Vec<T>::n;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int row0 = (blockIdx.x * 4 + wave) * R;
+    const int n = d.n;
+    if (row0 >= n) return;   // wave-uniform
+    const int64_t ld = d.ld;
+    const T* __restrict__ xin = d.ms[cur];
+    T* __restrict__ xout = d.ms[cur ^ 1];
+
+    const T* wrow[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) wrow[r] = d.W + (int64_t)min(row0 + r, n - 1) * ld;
+
+    AT ax[R], ay[R], az[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) ax[r] = ay[r] = az[r] = A::zero();
+
+#pragma unroll 2
+    for (int64_t c = (int64_t)lane * VN; c < ld; c += 64 * VN) {
+        V xv = *reinterpret_cast<const V*>(xin + c);
+        V yv, zv;
+        if (XYZ) {
+            yv = *reinterpret_cast<const V*>(xin + ld + c);
+            zv = *reinterpret_cast<const V*>(xin + 2 * ld + c);
+        }
+        V wv[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) wv[r] = __builtin_nontemporal_load(reinterpret_cast<const V*>(wrow[r] + c));
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+#pragma unroll
+            for (int e = 0; e < VN; ++e) {
+                A::fma(ax[r], wv[r][e], xv[e]);
+                if (XYZ) {
+                    A::fma(ay[r], wv[r][e], yv[e]);
+                    A::fma(az[r], wv[r][e], zv[e]);
+                }
+            }
+        }
+    }
+    T dx = T(0), dy = T(0), dz = T(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        AT sx = group_reduce<T>(ax[r], 64);
+        AT sy = sx, sz = sx;
+        if (XYZ) {
+            sy = group_reduce<T>(ay[r], 64);
+            sz = group_reduce<T>(az[r], 64);
+        }
+        if (lane == r) {
+            dx = A::round(sx);
+            if (XYZ) {
+                dy = A::round(sy);
+                dz = A::round(sz);
+            }
+        }
+    }
+    const int row = row0 + lane;
+    if (lane < R && row < n) {
+        T hin = input_field(k, d.w_in + (int64_t)row * d.n_in, u_s, d.n_in);
+        stage_epilogue<T, XYZ>(d, k, row, dx, dy, dz, hin, xin, xout, stage, renorm, record, sample);
+    }
+}
+
+template <typename T> constexpr int stream_rows() { return sizeof(T) == 8 ? 2 : 4; }
+
+template <typename T>
+hipError_t run_stream(const DevState<T>& d, const Coef<T>& k, const RunSpec& r) {
+    constexpr int R = stream_rows<T>();
+    const int rows_per_block = 4 * R;
+    dim3 grid((d.n + rows_per_block - 1) / rows_per_block), block(256);
+    T* states = static_cast<T*>(r.states);
+    int cur = r.cur;
+    for (int s = 0; s < r.samples; ++s) {
+        const double* u_s = r.u + (int64_t)s * d.n_in;
+        for (int sub = 0; sub < r.substeps; ++sub) {
+            for (int stage = 0; stage < 4; ++stage) {
+                T* rec = (states && stage == 3 && sub == r.substeps - 1)
+                             ? states + (int64_t)s * d.n * 3 : nullptr;
+                int c = cur ^ (stage & 1);
+                if (r.xyz)
+                    hipLaunchKernelGGL((k_stage<T, true, R>), grid, block, 0, r.stream, d, k, u_s, rec, s,
+                                       stage, c, r.renorm);
+                else
+                    hipLaunchKernelGGL((k_stage<T, false, R>), grid, block, 0, r.stream, d, k, u_s, rec, s,
+                                       stage, c, r.renorm);
+            }
+        }
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// SMALL path: the whole trajectory in one workgroup.
+// ---------------------------------------------------------------------------
+template <typename T, bool XYZ>
+__global__ void __launch_bounds__(256) k_small(DevState<T> d, Coef<T> k, const double* __restrict__ u,
+                                               T* __restrict__ states, int samples, int substeps,
+                                               int cur, int renorm, int L) {
+    using A = Acc<T>;
+    using AT = typename A::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int n = d.n;
+    const int64_t ld = d.ld;
+    T* wsh = reinterpret_cast<T*>(smem_raw);       // n x n
+    T* xs = wsh + (int64_t)n * n;                   // [2][3][n]
+    const int tid = threadIdx.x;
+    const int node = tid / L;
+    const int l = tid - node * L;
+    const bool active = node < n;
+    const int kk = active ? node : n - 1;
+
+    for (int i = tid; i < n * n; i += blockDim.x) {
+        int row = i / n;
+        wsh[i] = d.W[(int64_t)row * ld + (i - row * n)];
+    }
+    T mx = d.m[kk], my = d.m[ld + kk], mz = d.m[2 * ld + kk];
+    if (active && l == 0) {
+        xs[kk] = mx;
+        xs[n + kk] = my;
+        xs[2 * n + kk] = mz;
+    }
+    __syncthreads();
+
+    T sx = mx, sy = my, sz = mz;
+    T ax = T(0), ay = T(0), az = T(0);
+    int b = 0;
+    const T* wr = wsh + (int64_t)kk * n;
+    for (int s = 0; s < samples; ++s) {
+        const T hin = input_field(k, d.w_in + (int64_t)kk * d.n_in, u + (int64_t)s * d.n_in, d.n_in);
+        for (int sub = 0; sub < substeps; ++sub) {
+            for (int stage = 0; stage < 4; ++stage) {
+                const T* xb = xs + b * 3 * n;
+                AT vx = A::zero(), vy = A::zero(), vz = A::zero();
+                for (int j = l; j < n; j += L) {
+                    T w = wr[j];
+                    A::fma(vx, w, xb[j]);
+                    if (XYZ) {
+                        A::fma(vy, w, xb[n + j]);
+                        A::fma(vz, w, xb[2 * n + j]);
+                    }
+                }
+                vx = group_reduce<T>(vx, L);
+                T cx = k.a_cp * A::round(vx), cy = T(0), cz = T(0);
+                if (XYZ) {
+                    vy = group_reduce<T>(vy, L);
+                    vz = group_reduce<T>(vz, L);
+                    cy = k.a_cp * A::round(vy);
+                    cz = k.a_cp * A::round(vz);
+                }
+                T fx, fy, fz;
+                llg_rhs<T, XYZ>(k, sx, sy, sz, cx, cy, cz, hin, fx, fy, fz);
+                T nx = rk4_update(k, stage, mx, ax, fx);
+                T ny = rk4_update(k, stage, my, ay, fy);
+                T nz = rk4_update(k, stage, mz, az, fz);
+                if (stage == 3) {
+                    if (renorm) renormalize(nx, ny, nz);
+                    mx = nx;
+                    my = ny;
+                    mz = nz;
+                }
+                sx = nx;
+                sy = ny;
+                sz = nz;
+                if (active && l == 0) {
+                    T* xo = xs + (b ^ 1) * 3 * n;
+                    xo[kk] = nx;
+                    xo[n + kk] = ny;
+                    xo[2 * n + kk] = nz;
+                }
+                b ^= 1;
+                __syncthreads();
+            }
+        }
+        if (active && l == 0) {
+            if (states) {
+                T* rec = states + ((int64_t)s * n + kk) * 3;
+                rec[0] = mx;
+                rec[1] = my;
+                rec[2] = mz;
+            }
+            if (!finite3(mx, my, mz)) atomicMin(d.bad, s);
+        }
+    }
+    if (active && l == 0) {
+        d.m[kk] = mx;
+        d.m[ld + kk] = my;
+        d.m[2 * ld + kk] = mz;
+        T* xc = d.ms[cur];
+        xc[kk] = mx;
+        xc[ld + kk] = my;
+        xc[2 * ld + kk] = mz;
+    }
+}
+
+static size_t small_lds_bytes(int n, int elem) { return ((size_t)n * n + 6 * (size_t)n) * elem; }
+static const size_t kLdsMax = 160 * 1024;
+
+int small_max_n(int elem_bytes, int /*xyz*/) {
+    int n = 1;
+    while (n + 1 <= 256 && small_lds_bytes(n + 1, elem_bytes) <= kLdsMax) ++n;
+    return n;
+}
+
+template <typename T>
+hipError_t run_small(const DevState<T>& d, const Coef<T>& k, const RunSpec& r) {
+    const int n = d.n;
+    const int block = n <= 32 ? 64 : 256;
+    int L = 1;
+    while (L * 2 * n <= block && L * 2 <= 64) L *= 2;
+    size_t lds = small_lds_bytes(n, sizeof(T));
+    if (n > block || lds > kLdsMax) return hipErrorInvalidValue;
+    hipError_t e;
+    if (r.xyz) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small<T, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_small<T, true>), dim3(1), dim3(block), lds, r.stream, d, k, r.u,
+                           static_cast<T*>(r.states), r.samples, r.substeps, r.cur, r.renorm, L);
+    } else {
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small<T, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_small<T, false>), dim3(1), dim3(block), lds, r.stream, d, k, r.u,
+                           static_cast<T*>(r.states), r.samples, r.substeps, r.cur, r.renorm, L);
+    }
+    return hipGetLastError();
+}
+
+template hipError_t run_stream<double>(const DevState<double>&, const Coef<double>&, const RunSpec&);
+template hipError_t run_stream<float>(const DevState<float>&, const Coef<float>&, const RunSpec&);
+template hipError_t run_small<double>(const DevState<double>&, const Coef<double>&, const RunSpec&);
+template hipError_t run_small<float>(const DevState<float>&, const Coef<float>&, const RunSpec&);
+
+}  // namespace sto

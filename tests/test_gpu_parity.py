@@ -1,0 +1,318 @@
+"""GPU parity: the HIP library against the CPU oracle on the same seeded inputs.
+
+Bars (FP64): every record within 1e-10 of the oracle (the library computes
+the coupling sums to the nearest double like the oracle and evaluates the
+rest in the oracle's order, so the records are expected to be identical).
+FP32: within 1e-5 of the FP64 oracle for one step and over horizons up to
+the Lyapunov time; readout NMSE within 1e-3 where the dynamics are not
+chaotic (the paper's own coupling and input amplitudes).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from common import lib_params, oracle_params, oracle_run_cached, random_case, workload_case
+from oracle import readout, sto
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-10
+F32_TOL = 1e-5
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def stx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2312_01121_amd
+    return paper_2312_01121_amd
+
+
+def make(stx, w, w_in, m0, prm, dtype="f64", path="auto"):
+    return stx.Reservoir(w, w_in, m0, lib_params(prm, dtype=dtype, path=path))
+
+
+def maxdiff(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b)))) if np.size(a) else 0.0
+
+
+# ---------------------------------------------------------------------------
+# FP64: full horizon of the 16-node workload
+# ---------------------------------------------------------------------------
+def test_sto16_f64_full_horizon(stx):
+    wl, a, prm = workload_case("sto16")
+    say("sto16 f64 full horizon", wl.samples, "samples")
+    rec_o, fin_o = oracle_run_cached("sto16", wl.samples)
+    with make(stx, a["W"], a["w_in"], a["m0"], prm) as r:
+        assert r.path == "small"
+        rec = r.run(a["u"])
+        fin = r.get_state()
+    d = maxdiff(rec, rec_o)
+    say("max |gpu - oracle| =", d, "bitwise" if d == 0 else "")
+    assert d <= F64_TOL
+    assert maxdiff(fin, fin_o) <= F64_TOL
+    # the paper's acceptance rule: far below the |m|-1 drift of the method
+    assert d <= 1e-6 * sto.norm_drift(rec_o)
+
+
+# ---------------------------------------------------------------------------
+# FP64: every kernel family, several tiles and ragged tails
+# ---------------------------------------------------------------------------
+CASES = [(1, "small"), (1, "stream"), (16, "stream"), (16, "resident"), (37, "small"), (37, "stream"),
+         (37, "resident"), (130, "small"), (130, "stream"), (130, "resident"), (257, "stream"),
+         (257, "resident"), (700, "resident"), (700, "stream")]
+
+
+@pytest.mark.parametrize("n,path", CASES, ids=[f"n{n}-{p}" for n, p in CASES])
+def test_paths_match_oracle_f64(stx, n, path):
+    w, w_in, m0, u = random_case(n, seed=n, samples=12)
+    prm = oracle_params(a_cp=0.3)
+    say("paths f64", n, path)
+    rec_o, _ = sto.run(w, w_in, m0, u, prm)
+    with make(stx, w, w_in, m0, prm, path=path) as r:
+        assert r.path == path
+        rec = r.run(u)
+    d = maxdiff(rec, rec_o)
+    say("  max diff", d)
+    assert d <= F64_TOL
+
+
+@pytest.mark.parametrize("path", ["small", "stream", "resident"])
+def test_xyz_coupling_f64(stx, path):
+    w, w_in, m0, u = random_case(45, seed=3, samples=10)
+    prm = oracle_params(a_cp=0.3, coupling="xyz")
+    say("xyz f64", path)
+    rec_o, _ = sto.run(w, w_in, m0, u, prm)
+    with make(stx, w, w_in, m0, prm, path=path) as r:
+        rec = r.run(u)
+    assert maxdiff(rec, rec_o) <= F64_TOL
+
+
+@pytest.mark.parametrize("path", ["small", "stream", "resident"])
+def test_renormalize_and_multi_input_f64(stx, path):
+    w, w_in, m0, u = random_case(29, n_in=3, seed=4, samples=10)
+    prm = oracle_params(a_cp=0.2, a_in=0.7, renormalize=True)
+    say("renorm + n_in=3 f64", path)
+    rec_o, _ = sto.run(w, w_in, m0, u, prm)
+    with make(stx, w, w_in, m0, prm, path=path) as r:
+        rec = r.run(u)
+    assert maxdiff(rec, rec_o) <= F64_TOL
+    nrm = np.linalg.norm(rec, axis=2)
+    assert np.max(np.abs(nrm - 1.0)) < 1e-14
+
+
+@pytest.mark.parametrize("path", ["resident", "stream"])
+def test_sto1k_f64_prefix(stx, path):
+    samples = 25
+    wl, a, prm = workload_case("sto1k", samples)
+    say("sto1k f64 prefix", samples, path)
+    rec_o, _ = oracle_run_cached("sto1k", samples)
+    with make(stx, a["W"], a["w_in"], a["m0"], prm, path=path) as r:
+        rec = r.run(a["u"])
+    d = maxdiff(rec, rec_o)
+    say("  max diff", d)
+    assert d <= F64_TOL
+
+
+def test_sto10k_f64_prefix(stx):
+    samples = 1
+    wl, a, prm = workload_case("sto10k", samples)
+    say("sto10k f64 prefix", samples)
+    rec_o, _ = oracle_run_cached("sto10k", samples)
+    with make(stx, a["W"], a["w_in"], a["m0"], prm) as r:
+        assert r.path == "stream"
+        rec = r.run(a["u"])
+    d = maxdiff(rec, rec_o)
+    say("  max diff", d)
+    assert d <= F64_TOL
+
+
+# ---------------------------------------------------------------------------
+# Boundary behaviour
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("path", ["small", "stream", "resident"])
+def test_continuation_determinism_and_state(stx, path):
+    w, w_in, m0, u = random_case(33, seed=5, samples=9)
+    prm = oracle_params(a_cp=0.3)
+    say("continuation", path)
+    with make(stx, w, w_in, m0, prm, path=path) as r:
+        whole = r.run(u)
+        fin = r.get_state()
+    with make(stx, w, w_in, m0, prm, path=path) as r:
+        first = r.run(u[:4])
+        second = r.run(u[4:])
+        assert np.array_equal(r.get_state(), fin)
+        r.set_state(m0)
+        again = r.run(u)
+    assert np.array_equal(np.concatenate([first, second]), whole)
+    assert np.array_equal(again, whole)
+
+
+def test_run_device_matches_host_run(stx):
+    import torch
+    w, w_in, m0, u = random_case(300, seed=6, samples=6)
+    prm = oracle_params(a_cp=0.2)
+    say("run_device")
+    for dtype, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+        with make(stx, w, w_in, m0, prm, dtype=dtype) as r:
+            host = r.run(u)
+        with make(stx, w, w_in, m0, prm, dtype=dtype) as r:
+            u_d = torch.from_numpy(u).cuda()
+            st = torch.empty((len(u), 300, 3), dtype=tdt, device="cuda")
+            r.run_device(u_d, st)
+            torch.cuda.synchronize()
+            assert np.array_equal(st.double().cpu().numpy(), host)
+
+
+def test_nonfinite_state_is_reported(stx):
+    """lambda = -1 with m_k = p makes 1 + lambda m.p vanish: H_s is infinite."""
+    n = 3
+    m0 = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    prm = oracle_params(lam=-1.0, p=(1.0, 0.0, 0.0))
+    w, w_in, _, u = random_case(n, seed=7, samples=4)
+    say("nonfinite")
+    for path in ("small", "stream", "resident"):
+        with make(stx, w, w_in, m0, prm, path=path) as r:
+            with pytest.raises(stx.StoError) as ei:
+                r.run(u)
+            assert ei.value.status == stx.STO_E_NONFINITE
+            assert "sample 0" in str(ei.value)
+
+
+def test_steps_validation_and_noop(stx):
+    w, w_in, m0, u = random_case(8, seed=8, samples=3)
+    prm = oracle_params()
+    with make(stx, w, w_in, m0, prm) as r:
+        with pytest.raises(stx.StoError):
+            stx.reservoir_run(r.h, u, 7)
+        stx.reservoir_run(r.h, u, 0)
+        assert np.array_equal(r.get_state(), m0)
+
+
+# ---------------------------------------------------------------------------
+# FP32
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,path", [("sto16", "auto"), ("sto1k", "auto"), ("sto1k", "stream"),
+                                       ("sto10k", "auto")])
+def test_f32_one_step(stx, name, path):
+    """One RK4 step from the same FP32-representable state and matrix."""
+    wl, a, _ = workload_case(name, 1)
+    prm = oracle_params(a_cp=wl.a_cp, a_in=wl.a_in, substeps=1)
+    f32 = lambda x: np.asarray(x, dtype=np.float32).astype(np.float64)  # noqa: E731
+    say("f32 one step", name, path)
+    rec_o, _ = sto.run(f32(a["W"]), f32(a["w_in"]), f32(a["m0"]), a["u"][:1], prm)
+    with make(stx, a["W"], a["w_in"], a["m0"], prm, dtype="f32", path=path) as r:
+        rec = r.run(a["u"][:1])
+    d = maxdiff(rec, rec_o)
+    say("  max diff", d)
+    assert d <= F32_TOL
+
+
+@pytest.mark.parametrize("name", ["sto16", "sto1k"])
+def test_f32_lyapunov_horizon(stx, name):
+    """FP32 stays within 1e-5 of the FP64 oracle over one Lyapunov time.
+
+    The largest Lyapunov exponent is measured by the oracle (Benettin's twin
+    trajectories over 100 samples); about 0.46/ns at N = 16 and 0.59/ns at
+    N = 1,000, i.e. 216 and 170 steps."""
+    wl, a100, prm = workload_case(name, 100)
+    lam = sto.lyapunov_max(a100["W"], a100["w_in"], a100["m0"], a100["u"], prm)
+    assert lam > 0.0
+    samples = max(1, int(1.0 / lam / (prm.substeps * prm.dt)))
+    say("f32 horizon", name, "lambda_max", lam, "samples", samples)
+    rec_o, _ = oracle_run_cached(name, samples)
+    a = workload_case(name, samples)[1]
+    with make(stx, a["W"], a["w_in"], a["m0"], prm, dtype="f32") as r:
+        rec = r.run(a["u"])
+    err = np.max(np.abs(rec - rec_o), axis=(1, 2))
+    say("  error by sample", " ".join(f"{e:.1e}" for e in err))
+    assert np.max(err) <= F32_TOL
+
+
+def test_f32_readout_nmse_paper_amplitudes(stx):
+    """At the paper's own amplitudes (A_cp = A_in = 1 Oe = 0.01764) the
+    trajectories are not chaotic over the horizon, and the FP32 readout
+    NMSE matches the FP64 oracle's within 1e-3."""
+    wl, a, _ = workload_case("sto16")
+    samples = 1000
+    u, y = a["u"][:samples], a["y"][:samples]
+    prm = oracle_params(a_cp=0.01764, a_in=0.01764)
+    say("f32 readout nmse")
+    rec_o, _ = sto.run(a["W"], a["w_in"], a["m0"], u, prm)
+    wash = readout.default_washout(samples)
+    _, e_o = readout.readout_fit(rec_o, y, wash, wl.ridge)
+    with make(stx, a["W"], a["w_in"], a["m0"], prm, dtype="f32") as r:
+        rec = r.run(u)
+    _, e_g = stx.readout_fit(rec, y, wash, wl.ridge)
+    say("  nmse oracle", e_o, "gpu f32", e_g, "traj diff", maxdiff(rec, rec_o))
+    assert abs(e_g - e_o) <= 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Readout (FP64 on the GPU)
+# ---------------------------------------------------------------------------
+def test_readout_primal_matches_oracle(stx):
+    wl, a, _ = workload_case("sto16")
+    rec_o, _ = oracle_run_cached("sto16", wl.samples)
+    wash = readout.default_washout(wl.samples)
+    say("readout primal")
+    w_o, e_o = readout.readout_fit(rec_o, a["y"], wash, wl.ridge)
+    w_g, e_g = stx.readout_fit(rec_o, a["y"], wash, wl.ridge)
+    phi = readout.features(rec_o, wash)
+    assert abs(e_g - e_o) <= 1e-9
+    assert maxdiff(phi @ w_g, phi @ w_o) <= 1e-7
+
+
+@pytest.mark.parametrize("features", [0, 1])
+def test_readout_dual_matches_oracle(stx, features):
+    rng = np.random.default_rng(9)
+    rec = rng.standard_normal((60, 90, 3)) * 0.5
+    y = np.tanh(rng.standard_normal(60))
+    say("readout dual", features)
+    w_o, e_o = readout.readout_fit(rec, y, 6, 1e-3, components="xyz" if features else "x")
+    w_g, e_g = stx.readout_fit(rec, y, 6, 1e-3, features=features)
+    assert abs(e_g - e_o) <= 1e-9 * max(1.0, e_o)
+    np.testing.assert_allclose(w_g, w_o, rtol=1e-8, atol=1e-10)
+
+
+def test_readout_not_positive_definite(stx):
+    rec = np.zeros((20, 4, 3))
+    y = np.linspace(-1, 1, 20)
+    with pytest.raises(stx.StoError) as ei:
+        stx.readout_fit(rec, y, 5, 0.0)
+    assert ei.value.status == stx.STO_E_INVALID
+
+
+# ---------------------------------------------------------------------------
+# Full sizes, in the configuration the benchmark times: properties
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_sto10k_full_horizon_properties(stx, dtype):
+    """All 1,000 samples at N = 10,000: finite, |m|-1 drift at integrator
+    level (the oracle's own drift on the prefix sets the scale), records
+    reproducible bit for bit."""
+    import torch
+    wl, a, prm = workload_case("sto10k")
+    say("sto10k full", dtype)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    with make(stx, a["W"], a["w_in"], a["m0"], prm, dtype=dtype) as r:
+        u_d = torch.from_numpy(a["u"]).cuda()
+        st = torch.empty((wl.samples, wl.n, 3), dtype=tdt, device="cuda")
+        r.run_device(u_d, st)
+        torch.cuda.synchronize()
+        rec = st.double().cpu().numpy()
+        r.set_state(a["m0"])
+        st2 = torch.empty((50, wl.n, 3), dtype=tdt, device="cuda")
+        r.run_device(u_d[:50].contiguous(), st2)
+        torch.cuda.synchronize()
+        assert torch.equal(st2, st[:50])
+    assert np.all(np.isfinite(rec))
+    drift = sto.norm_drift(rec)
+    say("  drift", drift)
+    assert drift < (1e-4 if dtype == "f64" else 1e-3)

@@ -1,0 +1,128 @@
+"""Host-side checks of the HIP library that need no GPU.
+
+* the shared library loads and exports every function include/*.h declares;
+* invalid arguments are rejected before any device work;
+* the library's own Table 1 presets equal the oracle's constants bit for bit.
+"""
+
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def stx():
+    from paper_2312_01121_amd import _build
+    if not os.path.exists(_build.LIB):
+        _build.build()
+    import paper_2312_01121_amd
+    return paper_2312_01121_amd
+
+
+def declared_functions():
+    names = []
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                             text, flags=re.M):
+            names.append(m.group(1))
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for fn in ("reservoir_create", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
+               "reservoir_set_state", "reservoir_path", "reservoir_destroy", "readout_fit", "sto_last_error"):
+        assert fn in names
+
+
+def test_library_exports_every_declared_symbol(stx):
+    lib = ctypes.CDLL(stx.LIB_PATH)
+    for fn in declared_functions():
+        assert hasattr(lib, fn), fn
+    assert set(stx.EXPORTED) <= set(declared_functions())
+
+
+def _ok_params(stx, **kw):
+    from paper_2312_01121_amd import params
+    p = params.table1()
+    p.update(kw)
+    return stx.make_params(**p)
+
+
+def test_create_rejects_bad_arguments(stx):
+    n = 4
+    w = np.zeros((n, n))
+    w_in = np.zeros((n, 1))
+    m0 = np.tile([0.0, 0.0, 1.0], (n, 1))
+    h = ctypes.c_void_p()
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))  # noqa: E731
+    lib = stx.lib()
+    prm = _ok_params(stx)
+
+    def create(nn=n, nin=1, pr=prm, W=w, m=m0):
+        return lib.reservoir_create(nn, nin, ctypes.byref(pr), dp(W), dp(w_in), dp(m), ctypes.byref(h))
+
+    assert create(nn=0) == stx.STO_E_INVALID
+    assert create(nin=0) == stx.STO_E_INVALID
+    assert create(pr=_ok_params(stx, dt=0.0)) == stx.STO_E_INVALID
+    assert create(pr=_ok_params(stx, substeps=0)) == stx.STO_E_INVALID
+    bad = _ok_params(stx)
+    bad.dtype = 7
+    assert create(pr=bad) == stx.STO_E_INVALID
+    bad = _ok_params(stx)
+    bad.reserved = 1
+    assert create(pr=bad) == stx.STO_E_INVALID
+    m_bad = m0.copy()
+    m_bad[1] = [0.0, 0.0, 1.0 + 1e-9]
+    assert create(m=m_bad) == stx.STO_E_INVALID
+    assert "m0[1]" in stx.sto_last_error()
+    w_nan = w.copy()
+    w_nan[0, 1] = np.nan
+    assert create(W=w_nan) == stx.STO_E_NONFINITE
+    assert lib.reservoir_create(n, 1, ctypes.byref(prm), None, dp(w_in), dp(m0), ctypes.byref(h)) == stx.STO_E_INVALID
+    big = _ok_params(stx, path="small")
+    wb = np.zeros((400, 400))
+    assert lib.reservoir_create(400, 1, ctypes.byref(big), dp(wb), dp(np.zeros((400, 1))),
+                                dp(np.tile([0.0, 0.0, 1.0], (400, 1))), ctypes.byref(h)) == stx.STO_E_UNSUPPORTED
+
+
+def test_readout_rejects_bad_arguments(stx):
+    lib = stx.lib()
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))  # noqa: E731
+    rec = np.zeros((10, 3, 3))
+    y = np.zeros(10)
+    w = np.zeros(4)
+    e = np.zeros(1)
+    assert lib.readout_fit(dp(rec), 10, 3, dp(y), 10, 1e-6, 0, dp(w), dp(e)) == stx.STO_E_INVALID
+    assert lib.readout_fit(dp(rec), 10, 3, dp(y), 2, -1.0, 0, dp(w), dp(e)) == stx.STO_E_INVALID
+    assert lib.readout_fit(dp(rec), 10, 3, dp(y), 2, 1e-6, 2, dp(w), dp(e)) == stx.STO_E_INVALID
+    y[4] = np.nan
+    assert lib.readout_fit(dp(rec), 10, 3, dp(y), 2, 1e-6, 0, dp(w), dp(e)) == stx.STO_E_NONFINITE
+
+
+def test_null_handle_is_rejected(stx):
+    lib = stx.lib()
+    u = np.zeros(4)
+    assert lib.reservoir_run(None, u.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 20, None) == stx.STO_E_INVALID
+    assert lib.reservoir_path(None) == -1
+    lib.reservoir_destroy(None)
+
+
+def test_presets_equal_oracle_constants(stx):
+    """The library's Table 1 conversion and the oracle's give identical bits."""
+    from oracle import constants
+    from paper_2312_01121_amd import params
+    for cs, fs in ((1.0, 1.0), (0.7, 1.3)):
+        a = params.table1(current_scale=cs, field_scale=fs)
+        b = constants.dimensionless(current_scale=cs, field_scale=fs)
+        assert a["alpha"] == b.alpha and a["lambda_stt"] == b.lam and a["dt"] == b.dt
+        assert a["h_appl"] == b.h_appl and a["h_k"] == b.h_k and a["h_s"] == b.h_s
+        assert tuple(a["p"]) == tuple(b.p)
