@@ -1,0 +1,244 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled spin-torque-oscillator reservoir on one MI355X.
+
+One benchmark step is one whole job over the workload's synthetic input
+series, with every input already resident in HBM: all RK4 steps of every
+input sample (coupling contraction, LLG + spin-torque right-hand side,
+stage combination, one record per sample) followed by the FP64 ridge
+readout of the records.  The metric is node-steps/s = N x RK4 steps per
+second of wall time over the timed steps.
+
+Default workload: 10,000 coupled oscillators in FP32 (1,000 input samples x
+20 RK4 steps, dt = 0.01), the largest configuration, where the coupling
+matrix (400 MB) is streamed from HBM once per RK4 stage.  The JSON line
+also carries the same workload in FP64, 1,000 oscillators in FP32 and FP64
+(10,000 samples x 20 steps) and 16 oscillators in FP64 (2,000 x 20) under
+"also", the roofline of the dominant kernel, and the CPU oracle timed on a
+bounded sample of the default workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "node-steps/s at N=1e3,1e4 (FP32/FP64); batched-sweep & adjoint vs plain, % roofline"
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("sto_device.hpp", "sto_kernels.hip", "sto_resident.hip"):
+        with open(os.path.join(ROOT, "paper_2312_01121_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel: str, workload: str, dtype: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; otherwise None."""
+    path = os.path.join(PROFILES, "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    rec = data.get(f"{kernel}/{workload}/{dtype}")
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def washout_of(samples: int) -> int:
+    """Records skipped before the readout fit: max(5, ceil(samples / 10))."""
+    return max(5, int(math.ceil(0.1 * samples)))
+
+
+def run_workload(stx, torch, name: str, dtype: str, steps: int, warmup: int, arrays=None, samples=None):
+    from workloads import WORKLOADS, make_workload_arrays
+    from paper_2312_01121_amd import params
+
+    wl = WORKLOADS[name]
+    if samples is not None:
+        wl = wl.with_samples(samples)
+        if arrays is not None:
+            arrays = dict(arrays, u=arrays["u"][:samples].copy(), y=arrays["y"][:samples].copy())
+    a = arrays if arrays is not None else make_workload_arrays(wl)
+    prm = stx.make_params(**params.table1(a_cp=wl.a_cp, a_in=wl.a_in, dt=wl.dt, substeps=wl.substeps),
+                          dtype=dtype)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    elem = 8 if dtype == "f64" else 4
+    r = stx.Reservoir(a["W"], a["w_in"], a["m0"], prm)
+    path = r.path
+    u_d = torch.from_numpy(a["u"]).cuda()
+    y = a["y"].copy()
+    y[:5] = 0.0                                     # undefined targets lie inside the washout
+    y_d = torch.from_numpy(y).cuda()
+    states = torch.empty((wl.samples, wl.n, 3), dtype=tdt, device="cuda")
+    w_out = torch.empty(wl.n + 1, dtype=torch.float64, device="cuda")
+    wash = washout_of(wl.samples)
+    stream = torch.cuda.current_stream()
+
+    def one_step():
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        r.run_device(u_d, states, stream)
+        e1.record(stream)
+        _, nmse = stx.readout_fit_device(states, y_d, wash, wl.ridge, 0, w_out, stream)
+        e2.record(stream)
+        return e0, e1, e2, nmse
+
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs = [one_step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    run_ms = sum(e0.elapsed_time(e1) for e0, e1, _, _ in evs) / steps
+    fit_ms = sum(e1.elapsed_time(e2) for _, e1, e2, _ in evs) / steps
+    nmse = evs[-1][3]
+    r.close()
+    wall_s = (t1 - t0) / steps
+    node_steps = wl.n * wl.steps
+    launches = 4 * wl.steps if path == "stream" else 1
+    kernel = {"stream": "k_stage", "resident": "k_resident", "small": "k_small"}[path]
+    algo_bytes = float(wl.n) * wl.n * elem * 4 * wl.steps / launches   # W read once per RK4 stage
+    launch_s = run_ms * 1e-3 / launches
+    achieved = algo_bytes / launch_s / 1e9
+    return {
+        "workload": name, "n": wl.n, "dtype": dtype, "path": path, "samples": wl.samples,
+        "substeps": wl.substeps, "rk4_steps": wl.steps, "dt": wl.dt,
+        "value": node_steps / wall_s, "ms_per_step": wall_s * 1e3,
+        "run_ms": run_ms, "readout_ms": fit_ms, "us_per_rk4_step": run_ms * 1e3 / wl.steps,
+        "readout_nmse": nmse,
+        "kernel": kernel, "launches_per_run": launches, "avg_launch_us": launch_s * 1e6,
+        "algo_bytes_per_launch": algo_bytes, "achieved_gbs": achieved,
+        "hbm_frac": achieved / HBM_PEAK_GBS,
+    }
+
+
+def cpu_baseline(name: str, arrays, budget_s: float = 25.0):
+    """The FP64 oracle (correctly rounded coupling sums) on the first input
+    samples of the workload, on this host's cores."""
+    from oracle import _native, constants, sto
+    from workloads import WORKLOADS
+
+    wl = WORKLOADS[name]
+    prm = constants.dimensionless(a_cp=wl.a_cp, a_in=wl.a_in, dt=wl.dt, substeps=wl.substeps)
+    samples = 0
+    t0 = time.perf_counter()
+    m = arrays["m0"]
+    while True:
+        _, m = sto.run(arrays["W"], arrays["w_in"], m, arrays["u"][samples:samples + 1], prm)
+        samples += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s * 0.5 or samples >= wl.samples or el / samples * (samples + 1) > budget_s:
+            break
+    return {
+        "value": wl.n * samples * wl.substeps / el, "unit": "node-steps/s", "cores": _native.exact_threads(),
+        "kind": "oracle",
+        "sample": f"first {samples} input sample(s) = {samples * wl.substeps} RK4 steps of the {name} "
+                  f"workload (N={wl.n}), FP64 oracle with correctly rounded coupling sums, {el:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sto10k")
+    ap.add_argument("--dtype", default="f32", choices=("f32", "f64"))
+    ap.add_argument("--no-also", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--samples", type=int, default=None,
+                    help="run only the first SAMPLES input samples of the main workload (short profiled runs)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device with a plain copy kernel (scales HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the workloads here are single-GPU problems "
+              "(multi-GPU sharding is a design note, not part of this build); use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    import paper_2312_01121_amd as stx
+    from workloads import WORKLOADS, make_workload_arrays
+
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+        del src, dst
+    arrays = make_workload_arrays(WORKLOADS[args.workload])
+    log("main", args.workload, args.dtype)
+    main_res = run_workload(stx, torch, args.workload, args.dtype, args.steps, args.warmup, arrays, args.samples)
+    log(json.dumps(main_res))
+    also = []
+    if not args.no_also:
+        plan = [(args.workload, "f64" if args.dtype == "f32" else "f32", 1, 1),
+                ("sto1k", "f32", 2, 1), ("sto1k", "f64", 2, 1), ("sto16", "f64", 3, 1)]
+        for name, dt, k, w in plan:
+            log("also", name, dt)
+            res = run_workload(stx, torch, name, dt, k, w, arrays if name == args.workload else None)
+            log(json.dumps(res))
+            also.append(res)
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline")
+        cpu = cpu_baseline(args.workload, arrays)
+        log(json.dumps(cpu))
+
+    traffic = stored_traffic(main_res["kernel"], args.workload, args.dtype)
+    out = {
+        "metric": METRIC,
+        "value": main_res["value"],
+        "unit": "node-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": main_res["n"], "samples": main_res["samples"],
+                   "substeps": main_res["substeps"], "rk4_steps": main_res["rk4_steps"], "dt": main_res["dt"],
+                   "path": main_res["path"], "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": main_res["kernel"], "achieved": main_res["achieved_gbs"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": main_res["hbm_frac"], "traffic": traffic},
+        "cpu_baseline": cpu,
+        "detail": main_res,
+        "also": also,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

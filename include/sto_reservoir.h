@@ -162,6 +162,23 @@ sto_status readout_fit(const double *states, int64_t T, int64_t n, const double 
                        int64_t washout, double lambda, int32_t features,
                        double *w_out, double *nmse_out);
 
+/*
+ * readout_fit_device -- readout_fit on device buffers, in FP64 on the GPU.
+ *   states_dev  device, T * n * 3 elements of type dtype (sto_dtype), e.g.
+ *               the records written by reservoir_run_device
+ *   dtype       element type of states_dev
+ *   y_dev       device, T doubles
+ *   w_out_dev   device, F + 1 doubles (weights, bias last)
+ *   nmse_out    host, 1 double
+ *   hip_stream  hipStream_t to enqueue on (NULL: the null stream); the call
+ *               returns after the stream has finished the fit
+ * Same system, arguments and errors as readout_fit; non-finite records or
+ * targets are detected on the device (STO_E_NONFINITE).
+ */
+sto_status readout_fit_device(const void *states_dev, int32_t dtype, int64_t T, int64_t n,
+                              const void *y_dev, int64_t washout, double lambda, int32_t features,
+                              void *w_out_dev, double *nmse_out, void *hip_stream);
+
 /* sto_last_error -- message of the last non-OK status on this thread
  * (empty string if none).  Valid until the next call on this thread. */
 const char *sto_last_error(void);

@@ -46,6 +46,8 @@ def lib():
             L.exact_matvec.argtypes = [dp, ctypes.c_long, ctypes.c_long, ctypes.c_long, dp, dp]
             L.exact_sum.restype = ctypes.c_double
             L.exact_sum.argtypes = [dp, ctypes.c_long]
+            L.exact_threads.restype = ctypes.c_int
+            L.exact_threads.argtypes = []
             _lib = L
     return _lib
 
@@ -78,3 +80,8 @@ def exact_matvec(a, x) -> np.ndarray:
 def exact_sum(x) -> float:
     x = np.ascontiguousarray(x, dtype=np.float64).ravel()
     return float(lib().exact_sum(_ptr(x), x.size))
+
+
+def exact_threads() -> int:
+    """Threads the row-parallel exact matrix-vector product uses."""
+    return int(lib().exact_threads())

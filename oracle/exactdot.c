@@ -191,3 +191,7 @@ double exact_sum(const double *x, long n)
         acc_add_product(&acc, x[i], 1.0);
     return acc_round(&acc);
 }
+
+/* Number of threads exact_matvec uses (OpenMP's current maximum). */
+#include <omp.h>
+int exact_threads(void) { return omp_get_max_threads(); }

@@ -80,6 +80,9 @@ def _load():
     lib.reservoir_destroy.restype = None
     lib.readout_fit.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, dp, ctypes.c_int64, ctypes.c_double,
                                 ctypes.c_int32, dp, dp]
+    lib.readout_fit_device.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, vp, ctypes.c_int64,
+                                       ctypes.c_double, ctypes.c_int32, vp, dp, vp]
+    lib.readout_fit_device.restype = ctypes.c_int
     lib.sto_last_error.restype = ctypes.c_char_p
     for name in ("reservoir_create", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
                  "reservoir_set_state", "readout_fit"):
@@ -90,7 +93,8 @@ def _load():
 _lib = _load()
 
 EXPORTED = ("reservoir_create", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
-            "reservoir_set_state", "reservoir_path", "reservoir_destroy", "readout_fit", "sto_last_error")
+            "reservoir_set_state", "reservoir_path", "reservoir_destroy", "readout_fit", "readout_fit_device",
+            "sto_last_error")
 
 
 def lib():
@@ -170,6 +174,28 @@ def readout_fit(states, y, washout: int, lam: float, features: int = 0) -> Tuple
     nmse = np.empty(1)
     _check(_lib.readout_fit(_dptr(states), T, n, _dptr(y), washout, lam, features, _dptr(w), _dptr(nmse)))
     return w, float(nmse[0])
+
+
+def readout_fit_device(states_dev, y_dev, washout: int, lam: float, features: int = 0, w_out_dev=None,
+                       stream=None) -> float:
+    """states_dev: CUDA float32/float64 tensor (T, n, 3); y_dev: CUDA float64
+    tensor (T,); w_out_dev: CUDA float64 tensor of F + 1 weights (allocated
+    if None).  Returns (w_out_dev, nmse)."""
+    import torch
+    assert states_dev.is_cuda and states_dev.is_contiguous() and states_dev.dim() == 3
+    assert y_dev.is_cuda and y_dev.dtype == torch.float64 and y_dev.is_contiguous()
+    T, n, _ = states_dev.shape
+    cols = (3 * n if features else n) + 1
+    if w_out_dev is None:
+        w_out_dev = torch.empty(cols, dtype=torch.float64, device=states_dev.device)
+    assert w_out_dev.dtype == torch.float64 and w_out_dev.numel() == cols
+    dtype = {torch.float64: STO_F64, torch.float32: STO_F32}[states_dev.dtype]
+    nmse = np.empty(1)
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    _check(_lib.readout_fit_device(ctypes.c_void_p(states_dev.data_ptr()), dtype, T, n,
+                                   ctypes.c_void_p(y_dev.data_ptr()), washout, lam, features,
+                                   ctypes.c_void_p(w_out_dev.data_ptr()), _dptr(nmse), ctypes.c_void_p(s)))
+    return w_out_dev, float(nmse[0])
 
 
 class Reservoir:

@@ -21,9 +21,11 @@ namespace {
 constexpr int TILE = 16;
 
 // features: 0 = m^x of every node, 1 = all three components; rec is
-// rows x n x 3 (AoS records), phi is rows x cols row-major.
-__global__ void k_gather(const double* __restrict__ rec, int rows, int n, int features,
-                         double* __restrict__ phi) {
+// rows x n x 3 (AoS records, FP32 or FP64), phi is rows x cols row-major in
+// FP64.  Raises *bad if a feature or target is not finite.
+template <typename R>
+__global__ void k_gather(const R* __restrict__ rec, int rows, int n, int features, const double* __restrict__ y,
+                         double* __restrict__ phi, int* bad) {
     const int cols = (features ? 3 * n : n) + 1;
     const int64_t total = (int64_t)rows * cols;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
@@ -32,8 +34,9 @@ __global__ void k_gather(const double* __restrict__ rec, int rows, int n, int fe
         const int j = (int)(i - (int64_t)r * cols);
         double v;
         if (j == cols - 1) v = 1.0;
-        else if (features) v = rec[(int64_t)r * 3 * n + j];
-        else v = rec[((int64_t)r * n + j) * 3];
+        else if (features) v = (double)rec[(int64_t)r * 3 * n + j];
+        else v = (double)rec[((int64_t)r * n + j) * 3];
+        if (!__builtin_isfinite(v) || (j == cols - 1 && !__builtin_isfinite(y[r]))) atomicExch(bad, 1);
         phi[i] = v;
     }
 }
@@ -161,13 +164,13 @@ __global__ void k_nmse(const double* __restrict__ phi, int rows, int cols, const
 
 }  // namespace
 
-int readout_solve(const double* rec_dev, int rows, int n, int features, const double* y_dev, double lam,
-                  double* w_dev, double* nmse_host, hipStream_t stream, const char** err) {
+int readout_solve(const void* rec_dev, int rec_f32, int rows, int n, int features, const double* y_dev,
+                  double lam, double* w_dev, double* nmse_host, hipStream_t stream, const char** err) {
     const int cols = (features ? 3 * n : n) + 1;
     const bool primal = rows >= cols;
     const int m = primal ? cols : rows;
     double *phi = nullptr, *C = nullptr, *rhs = nullptr, *sums = nullptr;
-    int* flag = nullptr;
+    int* flag = nullptr;   // [0]: not positive definite, [1]: non-finite input
     int rc = 0;
     auto check = [&](hipError_t e) {
         if (e != hipSuccess && rc == 0) {
@@ -178,8 +181,13 @@ int readout_solve(const double* rec_dev, int rows, int n, int features, const do
     };
     if (check(hipMalloc(&phi, (size_t)rows * cols * 8)) && check(hipMalloc(&C, (size_t)m * m * 8)) &&
         check(hipMalloc(&rhs, (size_t)m * 8)) && check(hipMalloc(&sums, 16)) &&
-        check(hipMalloc(&flag, sizeof(int))) && check(hipMemsetAsync(flag, 0, sizeof(int), stream))) {
-        hipLaunchKernelGGL(k_gather, dim3(1024), dim3(256), 0, stream, rec_dev, rows, n, features, phi);
+        check(hipMalloc(&flag, 2 * sizeof(int))) && check(hipMemsetAsync(flag, 0, 2 * sizeof(int), stream))) {
+        if (rec_f32)
+            hipLaunchKernelGGL(k_gather<float>, dim3(1024), dim3(256), 0, stream, static_cast<const float*>(rec_dev),
+                               rows, n, features, y_dev, phi, flag + 1);
+        else
+            hipLaunchKernelGGL(k_gather<double>, dim3(1024), dim3(256), 0, stream,
+                               static_cast<const double*>(rec_dev), rows, n, features, y_dev, phi, flag + 1);
         dim3 tb(TILE, TILE), tg((m + TILE - 1) / TILE, (m + TILE - 1) / TILE);
         if (primal) {
             hipLaunchKernelGGL(k_gram<true>, tg, tb, 0, stream, phi, m, rows, lam, C);
@@ -196,11 +204,15 @@ int readout_solve(const double* rec_dev, int rows, int n, int features, const do
                 hipLaunchKernelGGL(k_chol_update, ug, ub, 0, stream, C, m, j, flag);
             }
         }
-        int hflag = 0;
+        int hflag[2] = {0, 0};
         check(hipGetLastError());
-        check(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, stream));
+        check(hipMemcpyAsync(hflag, flag, 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
         check(hipStreamSynchronize(stream));
-        if (rc == 0 && hflag) {
+        if (rc == 0 && hflag[1]) {
+            rc = 3;
+            if (err) *err = "non-finite record or target";
+        }
+        if (rc == 0 && hflag[0]) {
             rc = 1;
             if (err) *err = "normal-equation matrix is not positive definite";
         }

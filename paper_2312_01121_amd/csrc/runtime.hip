@@ -233,6 +233,23 @@ sto_status run_device_impl(sto_reservoir* r, const double* u_dev, int64_t steps,
     return STO_OK;
 }
 
+sto_status readout_check(int64_t T, int64_t n, int64_t washout, double lambda, int32_t features) {
+    if (T < 1 || n < 1) return fail(STO_E_INVALID, "T and n must be >= 1");
+    if (washout < 0 || washout >= T) return fail(STO_E_INVALID, "washout must be in [0, T)");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(STO_E_INVALID, "lambda must be >= 0");
+    if (features != 0 && features != 1) return fail(STO_E_INVALID, "features must be 0 or 1");
+    const int64_t rows = T - washout;
+    const int64_t cols = (features ? 3 * n : n) + 1;
+    if (rows > 65536 || cols > 65536) return fail(STO_E_UNSUPPORTED, "readout larger than 65536 rows or columns");
+    return STO_OK;
+}
+
+sto_status readout_status(int rc, const char* err) {
+    if (rc == 1) return fail(STO_E_INVALID, "readout: %s", err ? err : "not positive definite");
+    if (rc == 3) return fail(STO_E_NONFINITE, "readout: %s", err ? err : "non-finite input");
+    return fail(STO_E_DEVICE, "readout: %s", err ? err : "device error");
+}
+
 }  // namespace
 
 extern "C" {
@@ -401,14 +418,11 @@ sto_status reservoir_set_state(sto_reservoir* r, const double* m) {
 sto_status readout_fit(const double* states, int64_t T, int64_t n, const double* y, int64_t washout,
                        double lambda, int32_t features, double* w_out, double* nmse_out) {
     if (!states || !y || !w_out || !nmse_out) return fail(STO_E_INVALID, "NULL argument");
-    if (T < 1 || n < 1) return fail(STO_E_INVALID, "T and n must be >= 1");
-    if (washout < 0 || washout >= T) return fail(STO_E_INVALID, "washout must be in [0, T)");
-    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(STO_E_INVALID, "lambda must be >= 0");
-    if (features != 0 && features != 1) return fail(STO_E_INVALID, "features must be 0 or 1");
+    sto_status st = readout_check(T, n, washout, lambda, features);
+    if (st != STO_OK) return st;
     const int64_t rows = T - washout;
     const int64_t F = features ? 3 * n : n;
     const int64_t cols = F + 1;
-    if (rows > 65536 || cols > 65536) return fail(STO_E_UNSUPPORTED, "readout larger than 65536 rows or columns");
     if (!finite_all(states + washout * n * 3, rows * n * 3) || !finite_all(y + washout, rows))
         return fail(STO_E_NONFINITE, "non-finite states or targets");
     double *rec_dev = nullptr, *y_dev = nullptr, *w_dev = nullptr;
@@ -430,13 +444,30 @@ sto_status readout_fit(const double* states, int64_t T, int64_t n, const double*
         return hip_fail(e, "readout upload");
     }
     const char* err = nullptr;
-    int rc = sto::readout_solve(rec_dev, (int)rows, (int)n, features, y_dev, lambda, w_dev, nmse_out, nullptr, &err);
+    int rc = sto::readout_solve(rec_dev, 0, (int)rows, (int)n, features, y_dev, lambda, w_dev, nmse_out, nullptr,
+                                &err);
     if (rc == 0) e = hipMemcpy(w_out, w_dev, cols * 8, hipMemcpyDeviceToHost);
     release();
-    if (rc == 1) return fail(STO_E_INVALID, "readout: %s", err ? err : "not positive definite");
-    if (rc != 0) return fail(STO_E_DEVICE, "readout: %s", err ? err : "device error");
+    if (rc != 0) return readout_status(rc, err);
     if (e != hipSuccess) return hip_fail(e, "readout download");
     return STO_OK;
+}
+
+sto_status readout_fit_device(const void* states_dev, int32_t dtype, int64_t T, int64_t n, const void* y_dev,
+                              int64_t washout, double lambda, int32_t features, void* w_out_dev, double* nmse_out,
+                              void* hip_stream) {
+    if (!states_dev || !y_dev || !w_out_dev || !nmse_out) return fail(STO_E_INVALID, "NULL argument");
+    if (dtype != STO_F64 && dtype != STO_F32) return fail(STO_E_INVALID, "unknown dtype %d", dtype);
+    sto_status st = readout_check(T, n, washout, lambda, features);
+    if (st != STO_OK) return st;
+    const int64_t rows = T - washout;
+    const size_t elem = dtype == STO_F64 ? 8 : 4;
+    const void* rec = static_cast<const char*>(states_dev) + (size_t)washout * n * 3 * elem;
+    const double* y = static_cast<const double*>(y_dev) + washout;
+    const char* err = nullptr;
+    int rc = sto::readout_solve(rec, dtype == STO_F32, (int)rows, (int)n, features, y, lambda,
+                                static_cast<double*>(w_out_dev), nmse_out, static_cast<hipStream_t>(hip_stream), &err);
+    return rc == 0 ? STO_OK : readout_status(rc, err);
 }
 
 }  // extern "C"

@@ -55,10 +55,11 @@ bool resident_fits(int n, int elem_bytes, int xyz, int* grid_out);
 constexpr int kSyncAbortWord = 32;
 
 // Readout (FP64): see readout.hip.
-// rec_dev: rows x n x 3 records (FP64); y_dev: rows targets; w_dev: cols
-// weights.  Returns 0 on success, 1 if the normal-equation matrix is not
-// positive definite, 2 on a HIP error (message in *err).
-int readout_solve(const double* rec_dev, int rows, int n, int features, const double* y_dev, double lam,
-                  double* w_dev, double* nmse_host, hipStream_t stream, const char** err);
+// rec_dev: rows x n x 3 records of type rec_f32 ? float : double; y_dev:
+// rows targets; w_dev: cols weights.  Returns 0 on success, 1 if the
+// normal-equation matrix is not positive definite, 2 on a HIP error
+// (message in *err), 3 if a record or target is not finite.
+int readout_solve(const void* rec_dev, int rec_f32, int rows, int n, int features, const double* y_dev,
+                  double lam, double* w_dev, double* nmse_host, hipStream_t stream, const char** err);
 
 }  // namespace sto
