@@ -41,9 +41,17 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+KERNEL_SOURCES = {
+    "k_stage": ("sto_device.hpp", "sto_internal.hpp", "sto_kernels.hip"),
+    "k_small": ("sto_device.hpp", "sto_internal.hpp", "sto_kernels.hip"),
+    "k_resident": ("sto_device.hpp", "sto_internal.hpp", "sto_resident.hip"),
+}
+
+
+def kernel_source_hash(kernel: str) -> str:
+    """Hash of the sources a kernel is compiled from (stale counters are dropped)."""
     h = hashlib.sha256()
-    for f in ("sto_device.hpp", "sto_kernels.hip", "sto_resident.hip"):
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2312_01121_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -58,7 +66,7 @@ def stored_traffic(kernel: str, workload: str, dtype: str):
     with open(path) as fh:
         data = json.load(fh)
     rec = data.get(f"{kernel}/{workload}/{dtype}")
-    if not rec or rec.get("source_hash") != kernel_source_hash():
+    if not rec or rec.get("source_hash") != kernel_source_hash(kernel):
         return None
     return rec.get("hbm_bytes_per_launch")
 

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -48,7 +49,20 @@ bool finite_all(const double* p, int64_t count) {
     return true;
 }
 
+int env_flag(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    return std::atoi(v) != 0;
+}
+
 }  // namespace
+
+namespace sto {
+const Tune& tune() {
+    static const Tune t = {env_flag("STO_STREAM_ALTERNATE", 0), env_flag("STO_STREAM_NT", 1)};
+    return t;
+}
+}  // namespace sto
 
 struct sto_reservoir {
     int64_t n = 0, n_in = 0, ld = 0;
@@ -62,6 +76,7 @@ struct sto_reservoir {
     void* m = nullptr;
     void* ms[2] = {nullptr, nullptr};
     void* acc = nullptr;
+    void* xchg = nullptr;
     int* bad = nullptr;
     int* sync = nullptr;
     int cur = 0;
@@ -105,6 +120,7 @@ sto::DevState<T> dev_state(const sto_reservoir* r) {
     d.ms[0] = static_cast<T*>(r->ms[0]);
     d.ms[1] = static_cast<T*>(r->ms[1]);
     d.acc = static_cast<T*>(r->acc);
+    d.xchg = static_cast<T*>(r->xchg);
     d.bad = r->bad;
     d.sync = r->sync;
     d.n = (int)r->n;
@@ -114,7 +130,7 @@ sto::DevState<T> dev_state(const sto_reservoir* r) {
 }
 
 void free_all(sto_reservoir* r) {
-    void* ptrs[] = {r->W, r->w_in, r->m, r->ms[0], r->ms[1], r->acc, r->bad, r->sync, r->u_dev, r->states_dev};
+    void* ptrs[] = {r->W, r->w_in, r->m, r->ms[0], r->ms[1], r->acc, r->xchg, r->bad, r->sync, r->u_dev, r->states_dev};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (r->stream) (void)hipStreamDestroy(r->stream);
@@ -319,6 +335,9 @@ sto_status reservoir_create(int64_t n, int64_t n_in, const sto_params* prm, cons
     ALLOC(r->ms[0], vec);
     ALLOC(r->ms[1], vec);
     ALLOC(r->acc, vec);
+    if (path == STO_PATH_RESIDENT) {
+        ALLOC(r->xchg, 3 * vec);
+    }
     ALLOC(r->bad, sizeof(int));
     ALLOC(r->sync, 256);
 #undef ALLOC

@@ -22,6 +22,7 @@ struct DevState {
     T* m;
     T* ms[2];
     T* acc;
+    T* xchg;         // resident path: 3 rotating stage-input buffers of 3 x ld
     int* bad;        // first sample index whose state is not finite (INT_MAX: none)
     int* sync;       // grid-barrier words (cooperative kernels)
     int n, n_in;
@@ -38,6 +39,14 @@ struct RunSpec {
     int xyz;
     hipStream_t stream;
 };
+
+// Launch-shape choices, fixed defaults overridable through the environment
+// (STO_STREAM_ALTERNATE, STO_STREAM_NT: 0 or 1) for measurements.
+struct Tune {
+    int stream_alternate;    // reverse the row order of the stream kernel on odd stages
+    int stream_nontemporal;  // stream W with non-temporal loads
+};
+const Tune& tune();
 
 // Path launchers; each returns the HIP status of its launches.
 template <typename T> hipError_t run_stream(const DevState<T>& d, const Coef<T>& k, const RunSpec& r);

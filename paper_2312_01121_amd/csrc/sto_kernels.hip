@@ -81,17 +81,21 @@ __device__ __forceinline__ void stage_epilogue(const DevState<T>& d, const Coef<
 // ---------------------------------------------------------------------------
 // STREAM path: one RK4 stage.
 // ---------------------------------------------------------------------------
-template <typename T, bool XYZ, int R>
+template <typename T, bool XYZ, int R, bool NT>
 __global__ void __launch_bounds__(256) k_stage(DevState<T> d, Coef<T> k, const double* __restrict__ u_s,
                                                T* __restrict__ record, int sample, int stage, int cur,
-                                               int renorm) {
+                                               int renorm, int reverse) {
     using A = Acc<T>;
     using AT = typename A::type;
     using V = typename Vec<T>::type;
     constexpr int VN = Vec<T>::n;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int row0 = (blockIdx.x * 4 + wave) * R;
+    // On alternate stages the row blocks are visited last-to-first, so the
+    // rows streamed at the end of one stage (still in the memory-side cache)
+    // are the first ones the next stage reads.
+    const int block = reverse ? (int)(gridDim.x - 1 - blockIdx.x) : (int)blockIdx.x;
+    const int row0 = (block * 4 + wave) * R;
     const int n = d.n;
     if (row0 >= n) return;   // wave-uniform
     const int64_t ld = d.ld;
@@ -116,7 +120,10 @@ __global__ void __launch_bounds__(256) k_stage(DevState<T> d, Coef<T> k, const d
         }
         V wv[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) wv[r] = __builtin_nontemporal_load(reinterpret_cast<const V*>(wrow[r] + c));
+        for (int r = 0; r < R; ++r) {
+            const V* p = reinterpret_cast<const V*>(wrow[r] + c);
+            wv[r] = NT ? __builtin_nontemporal_load(p) : *p;
+        }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
 #pragma unroll
@@ -155,26 +162,37 @@ __global__ void __launch_bounds__(256) k_stage(DevState<T> d, Coef<T> k, const d
 
 template <typename T> constexpr int stream_rows() { return sizeof(T) == 8 ? 2 : 4; }
 
+template <typename T, bool XYZ, bool NT>
+static void launch_stage(dim3 grid, hipStream_t st, const DevState<T>& d, const Coef<T>& k, const double* u_s,
+                         T* rec, int s, int stage, int c, int renorm, int reverse) {
+    hipLaunchKernelGGL((k_stage<T, XYZ, stream_rows<T>(), NT>), grid, dim3(256), 0, st, d, k, u_s, rec, s, stage,
+                       c, renorm, reverse);
+}
+
 template <typename T>
 hipError_t run_stream(const DevState<T>& d, const Coef<T>& k, const RunSpec& r) {
     constexpr int R = stream_rows<T>();
     const int rows_per_block = 4 * R;
-    dim3 grid((d.n + rows_per_block - 1) / rows_per_block), block(256);
+    dim3 grid((d.n + rows_per_block - 1) / rows_per_block);
+    const Tune& t = tune();
     T* states = static_cast<T*>(r.states);
     int cur = r.cur;
+    int64_t sigma = 0;
     for (int s = 0; s < r.samples; ++s) {
         const double* u_s = r.u + (int64_t)s * d.n_in;
         for (int sub = 0; sub < r.substeps; ++sub) {
-            for (int stage = 0; stage < 4; ++stage) {
+            for (int stage = 0; stage < 4; ++stage, ++sigma) {
                 T* rec = (states && stage == 3 && sub == r.substeps - 1)
                              ? states + (int64_t)s * d.n * 3 : nullptr;
-                int c = cur ^ (stage & 1);
-                if (r.xyz)
-                    hipLaunchKernelGGL((k_stage<T, true, R>), grid, block, 0, r.stream, d, k, u_s, rec, s,
-                                       stage, c, r.renorm);
-                else
-                    hipLaunchKernelGGL((k_stage<T, false, R>), grid, block, 0, r.stream, d, k, u_s, rec, s,
-                                       stage, c, r.renorm);
+                const int c = cur ^ (stage & 1);
+                const int rev = t.stream_alternate ? (int)(sigma & 1) : 0;
+                if (r.xyz) {
+                    if (t.stream_nontemporal) launch_stage<T, true, true>(grid, r.stream, d, k, u_s, rec, s, stage, c, r.renorm, rev);
+                    else launch_stage<T, true, false>(grid, r.stream, d, k, u_s, rec, s, stage, c, r.renorm, rev);
+                } else {
+                    if (t.stream_nontemporal) launch_stage<T, false, true>(grid, r.stream, d, k, u_s, rec, s, stage, c, r.renorm, rev);
+                    else launch_stage<T, false, false>(grid, r.stream, d, k, u_s, rec, s, stage, c, r.renorm, rev);
+                }
             }
         }
     }

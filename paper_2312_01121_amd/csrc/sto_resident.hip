@@ -5,16 +5,34 @@
 // keeps it in LDS for the entire run; the state, stage input and RK4
 // accumulator of its rows live in registers.  Every RK4 stage needs the
 // whole stage input m^x of all nodes (Sec. 3.3: the coupling is W^cp x), so
-// stages are separated by a grid-wide barrier: each workgroup publishes its
-// rows of the next stage input to global memory, crosses the barrier, and
-// stages the full vector into LDS.
+// the stage inputs are exchanged through global memory every stage.
 //
-// The barrier is a counter plus a generation word in global memory with
-// agent-scope release/acquire.  Its wait loop is bounded: after a spin
-// limit it raises a sticky abort flag and every workgroup leaves the
-// kernel, so a grid that is not co-resident ends with an error instead of
-// a hang.  The cooperative launch itself refuses grids that cannot be
-// co-resident.
+// Exchange without a grid barrier.  The stage inputs live in three rotating
+// buffers.  The input of stage s is buffer s % 3.  An entry that has not been
+// published yet holds a sentinel bit pattern (all ones: a NaN with a payload
+// that IEEE arithmetic never generates, and the library rejects non-finite
+// inputs).  A workgroup
+//   1. polls every entry of buffer s % 3 until none is the sentinel, copying
+//      the values into LDS (this is the only wait: data and synchronisation
+//      arrive in the same load);
+//   2. computes its rows of stage s;
+//   3. re-arms its rows of buffer (s + 2) % 3 with the sentinel (every
+//      workgroup finished reading that buffer, the input of stage s - 1,
+//      before it published its stage s - 1 output, all of which step 1 has
+//      seen), waits for those stores to complete, and only then
+//   4. publishes its rows of buffer (s + 1) % 3.
+// All exchange loads and stores are agent-scope atomics, which on gfx950 are
+// coherent across the XCDs without an L2 writeback: the ordering of step 3
+// before step 4 is the store-completion wait of the publishing wave, and a
+// reader that sees a published value issues its later loads after it.
+// Agent-scope release fences per workgroup (L2 writebacks) cost ~70 ns each
+// and serialise, so a counter barrier over 256 workgroups costs 20-35 us;
+// this exchange costs about one memory round trip.
+//
+// Every wait is bounded: after a spin limit a workgroup raises a sticky
+// abort flag, and every workgroup that sees it leaves the kernel, so a grid
+// that is not co-resident ends with an error instead of a hang.  The
+// cooperative launch itself refuses grids that cannot be co-resident.
 
 #include <climits>
 
@@ -27,62 +45,92 @@ namespace {
 constexpr int kBlock = 256;              // 4 waves
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxRowsPerWave = 4;       // rows per workgroup <= 16
-constexpr int kSpinLimit = 1 << 24;      // ~0.5 s of s_sleep(1) polls
-constexpr size_t kLdsMax = 160 * 1024 - 256;   // leave room for the static barrier word
+constexpr int kSpinLimit = 1 << 20;      // poll rounds (one memory round trip each)
+constexpr size_t kLdsMax = 160 * 1024;
 
-// Barrier words (int offsets into DevState::sync, 256 bytes zeroed before
-// every launch): arrive counter, generation, abort flag on separate lines.
-constexpr int kArrive = 0, kGen = 16, kAbort = kSyncAbortWord;
+template <typename T> struct Bits;
+template <> struct Bits<double> { using type = unsigned long long; };
+template <> struct Bits<float> { using type = unsigned int; };
 
-__device__ bool grid_barrier(int* sync, int nblocks, int& gen, int* ok_lds) {
-    __threadfence();       // release this thread's global writes at agent scope
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        const int target = gen + 1;
-        const int arrived = __hip_atomic_fetch_add(sync + kArrive, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nblocks - 1) {
-            __hip_atomic_store(sync + kArrive, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(sync + kGen, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            int spins = 0;
-            while (__hip_atomic_load(sync + kGen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                if (__hip_atomic_load(sync + kAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    ok = 0;
+template <typename T>
+__device__ __forceinline__ typename Bits<T>::type sentinel() {
+    return ~typename Bits<T>::type(0);
+}
+
+template <typename T>
+__device__ __forceinline__ void publish(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ void rearm(T* p) {
+    using B = typename Bits<T>::type;
+    __hip_atomic_store(reinterpret_cast<B*>(p), sentinel<T>(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until the n entries of src are published and copy them to LDS.
+// Returns false if the wait was abandoned (spin limit or abort flag).
+template <typename T>
+__device__ bool gather_stage_input(const T* src, T* dst, int n, int* abort_flag) {
+    using B = typename Bits<T>::type;
+    const B* s = reinterpret_cast<const B*>(src);
+    bool ok = true;
+    for (int i0 = 0; i0 < n; i0 += 4 * kBlock) {
+        B v[4];
+        bool pending = true;
+        int rounds = 0;
+        while (pending) {
+            pending = false;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = i0 + q * kBlock + threadIdx.x;
+                v[q] = i < n ? __hip_atomic_load(s + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : B(0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = i0 + q * kBlock + threadIdx.x;
+                if (i < n) {
+                    if (v[q] == sentinel<T>()) pending = true;
+                    else dst[i] = __builtin_bit_cast(T, v[q]);
+                }
+            }
+            if (pending && (++rounds & 255) == 0) {
+                if (rounds > kSpinLimit) {
+                    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = false;
                     break;
                 }
-                if (++spins > kSpinLimit) {
-                    __hip_atomic_store(sync + kAbort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
+                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    ok = false;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(1);
             }
         }
-        __threadfence();   // acquire: later loads of this workgroup see the other groups' writes
-        gen = target;
-        *ok_lds = ok;
+        if (!ok) break;
     }
-    __syncthreads();
-    return *ok_lds != 0;
+    return ok;
 }
 
 template <typename T, bool XYZ>
 __global__ void __launch_bounds__(kBlock) k_resident(DevState<T> d, Coef<T> k, const double* __restrict__ u,
-                                                     T* __restrict__ states, int samples, int substeps, int cur,
-                                                     int renorm, int rows_per_block, int wld) {
+                                                     T* __restrict__ states, int samples, int substeps,
+                                                     int cur, int renorm, int rows_per_block, int wld) {
     using A = Acc<T>;
     using AT = typename A::type;
+    constexpr int C = XYZ ? 3 : 1;                           // exchanged components
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int ok_lds;
     const int n = d.n;
     const int64_t ld = d.ld;
     T* wsh = reinterpret_cast<T*>(smem_raw);                    // rows_per_block x wld
-    T* xs = wsh + (int64_t)rows_per_block * wld;                // [3][n] stage input
+    T* xs = wsh + (int64_t)rows_per_block * wld;                // [C][n] stage input
     const int row_begin = blockIdx.x * rows_per_block;
     const int nrows = max(0, min(rows_per_block, n - row_begin));
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    T* xbuf = d.xchg;                                           // [3][C][ld]
+    int* abort_flag = d.sync + kSyncAbortWord;
+    if (threadIdx.x == 0) ok_lds = 1;
 
     for (int i = threadIdx.x; i < nrows * n; i += kBlock) {
         const int r = i / n;
@@ -99,8 +147,7 @@ __global__ void __launch_bounds__(kBlock) k_resident(DevState<T> d, Coef<T> k, c
 #pragma unroll
     for (int q = 0; q < kMaxRowsPerWave; ++q) {
         const int r = wave + q * kWaves;
-        const int row = row_begin + min(r, max(nrows - 1, 0));
-        const int rr = min(row, n - 1);
+        const int rr = min(row_begin + min(r, max(nrows - 1, 0)), n - 1);
         mx[q] = sx[q] = d.m[rr];
         my[q] = sy[q] = d.m[ld + rr];
         mz[q] = sz[q] = d.m[2 * ld + rr];
@@ -108,8 +155,7 @@ __global__ void __launch_bounds__(kBlock) k_resident(DevState<T> d, Coef<T> k, c
         hin[q] = T(0);
     }
 
-    int gen = 0;
-    int b = cur;
+    int sigma = 0;   // stage counter: the input of stage sigma is xbuf[sigma % 3]
     for (int s = 0; s < samples; ++s) {
 #pragma unroll
         for (int q = 0; q < kMaxRowsPerWave; ++q) {
@@ -118,18 +164,17 @@ __global__ void __launch_bounds__(kBlock) k_resident(DevState<T> d, Coef<T> k, c
                 hin[q] = input_field(k, d.w_in + (int64_t)(row_begin + r) * d.n_in, u + (int64_t)s * d.n_in, d.n_in);
         }
         for (int sub = 0; sub < substeps; ++sub) {
-            for (int stage = 0; stage < 4; ++stage) {
-                // stage the current stage input (all nodes) into LDS
-                const T* xin = d.ms[b];
-                for (int i = threadIdx.x; i < n; i += kBlock) {
-                    xs[i] = xin[i];
-                    if (XYZ) {
-                        xs[n + i] = xin[ld + i];
-                        xs[2 * n + i] = xin[2 * ld + i];
-                    }
-                }
+            for (int stage = 0; stage < 4; ++stage, ++sigma) {
+                T* xin = xbuf + (int64_t)(sigma % 3) * C * ld;
+                T* xout = xbuf + (int64_t)((sigma + 1) % 3) * C * ld;
+                T* xold = xbuf + (int64_t)((sigma + 2) % 3) * C * ld;
+                __syncthreads();   // every wave is done with xs of the previous stage
+                bool ok = true;
+#pragma unroll
+                for (int c = 0; c < C; ++c) ok = ok && gather_stage_input<T>(xin + c * ld, xs + c * n, n, abort_flag);
+                if (!ok) ok_lds = 0;
                 __syncthreads();
-                T* xout = d.ms[b ^ 1];
+                if (ok_lds == 0) return;
 #pragma unroll
                 for (int q = 0; q < kMaxRowsPerWave; ++q) {
                     const int r = wave + q * kWaves;
@@ -168,13 +213,21 @@ __global__ void __launch_bounds__(kBlock) k_resident(DevState<T> d, Coef<T> k, c
                     sz[q] = nz;
                     if (lane == 0) {
                         const int row = row_begin + r;
-                        xout[row] = nx;
-                        xout[ld + row] = ny;
-                        xout[2 * ld + row] = nz;
+                        rearm(xold + row);
+                        if (XYZ) {
+                            rearm(xold + ld + row);
+                            rearm(xold + 2 * ld + row);
+                        }
+                        // the re-arm stores must complete before the publish;
+                        // the clobber keeps the compiler from moving either
+                        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                        publish(xout + row, nx);
+                        if (XYZ) {
+                            publish(xout + ld + row, ny);
+                            publish(xout + 2 * ld + row, nz);
+                        }
                     }
                 }
-                b ^= 1;
-                if (!grid_barrier(d.sync, gridDim.x, gen, &ok_lds)) return;
             }
         }
         if (lane == 0) {
@@ -194,14 +247,31 @@ __global__ void __launch_bounds__(kBlock) k_resident(DevState<T> d, Coef<T> k, c
         }
     }
     if (lane == 0) {
+        T* xc = d.ms[cur];
 #pragma unroll
         for (int q = 0; q < kMaxRowsPerWave; ++q) {
             const int r = wave + q * kWaves;
             if (r >= nrows) break;
             const int row = row_begin + r;
-            d.m[row] = mx[q];
-            d.m[ld + row] = my[q];
-            d.m[2 * ld + row] = mz[q];
+            d.m[row] = xc[row] = mx[q];
+            d.m[ld + row] = xc[ld + row] = my[q];
+            d.m[2 * ld + row] = xc[2 * ld + row] = mz[q];
+        }
+    }
+}
+
+__global__ void k_resident_prologue(const void* ms_cur, void* xchg, int64_t elems_per_buffer, int elem,
+                                    int64_t copy_elems) {
+    // buffer 0 <- current stage input (the state); buffers 1 and 2 <- sentinel
+    const int64_t total = 3 * elems_per_buffer;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (elem == 8) {
+            unsigned long long* x = static_cast<unsigned long long*>(xchg);
+            x[i] = i < copy_elems ? static_cast<const unsigned long long*>(ms_cur)[i] : ~0ull;
+        } else {
+            unsigned int* x = static_cast<unsigned int*>(xchg);
+            x[i] = i < copy_elems ? static_cast<const unsigned int*>(ms_cur)[i] : ~0u;
         }
     }
 }
@@ -215,18 +285,18 @@ int device_cus() {
 
 int64_t wld_of(int n) { return (n + 3) / 4 * 4; }
 
-size_t resident_lds(int n, int rows_per_block, int elem) {
-    return ((size_t)rows_per_block * wld_of(n) + 3 * (size_t)n) * elem;
+size_t resident_lds(int n, int rows_per_block, int elem, int xyz) {
+    return ((size_t)rows_per_block * wld_of(n) + (xyz ? 3 : 1) * (size_t)n) * elem;
 }
 
 }  // namespace
 
-bool resident_fits(int n, int elem_bytes, int /*xyz*/, int* grid_out) {
+bool resident_fits(int n, int elem_bytes, int xyz, int* grid_out) {
     const int cus = device_cus();
     if (cus <= 0 || n < 2) return false;
     const int rpb = (n + cus - 1) / cus;
     if (rpb > kWaves * kMaxRowsPerWave) return false;
-    if (resident_lds(n, rpb, elem_bytes) > kLdsMax) return false;
+    if (resident_lds(n, rpb, elem_bytes, xyz) + 64 > kLdsMax) return false;
     if (grid_out) *grid_out = (n + rpb - 1) / rpb;
     return true;
 }
@@ -235,17 +305,25 @@ template <typename T>
 hipError_t run_resident(const DevState<T>& d, const Coef<T>& k, const RunSpec& r) {
     int grid = 0;
     if (!resident_fits(d.n, sizeof(T), r.xyz, &grid)) return hipErrorInvalidValue;
-    const int rpb = (d.n + grid - 1) / grid;
+    int rpb = (d.n + grid - 1) / grid;
     int wld = (int)wld_of(d.n);
-    const size_t lds = resident_lds(d.n, rpb, sizeof(T));
+    const size_t lds = resident_lds(d.n, rpb, sizeof(T), r.xyz);
+    const int C = r.xyz ? 3 : 1;
     hipError_t e = hipMemsetAsync(d.sync, 0, 256, r.stream);
+    if (e != hipSuccess) return e;
+    // the exchange buffers hold C components of ld entries each; the x, y, z
+    // components of ms[cur] are contiguous blocks of ld, so the first C*ld
+    // entries of ms[cur] are exactly buffer 0
+    hipLaunchKernelGGL(k_resident_prologue, dim3(64), dim3(256), 0, r.stream, (const void*)d.ms[r.cur],
+                       (void*)d.xchg, (int64_t)C * d.ld, (int)sizeof(T), (int64_t)C * d.ld);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     DevState<T> dd = d;
     Coef<T> kk = k;
     const double* u = r.u;
     T* states = static_cast<T*>(r.states);
-    int samples = r.samples, substeps = r.substeps, cur = r.cur, renorm = r.renorm, rows = rpb;
-    void* args[] = {&dd, &kk, &u, &states, &samples, &substeps, &cur, &renorm, &rows, &wld};
+    int samples = r.samples, substeps = r.substeps, cur = r.cur, renorm = r.renorm;
+    void* args[] = {&dd, &kk, &u, &states, &samples, &substeps, &cur, &renorm, &rpb, &wld};
     const void* fn = r.xyz ? reinterpret_cast<const void*>(&k_resident<T, true>)
                            : reinterpret_cast<const void*>(&k_resident<T, false>);
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
