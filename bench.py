@@ -203,6 +203,8 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
         del src, dst
+    attainable = stx.sto_read_bandwidth(2 << 30, 5)
+    log(f"attainable HBM read bandwidth (plain streaming kernel): {attainable:.0f} GB/s")
     arrays = make_workload_arrays(WORKLOADS[args.workload])
     log("main", args.workload, args.dtype)
     main_res = run_workload(stx, torch, args.workload, args.dtype, args.steps, args.warmup, arrays, args.samples)
@@ -240,7 +242,8 @@ def main():
                    "substeps": main_res["substeps"], "rk4_steps": main_res["rk4_steps"], "dt": main_res["dt"],
                    "path": main_res["path"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": main_res["kernel"], "achieved": main_res["achieved_gbs"],
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": main_res["hbm_frac"], "traffic": traffic},
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": main_res["hbm_frac"], "traffic": traffic,
+                     "attainable": attainable, "frac_attainable": main_res["achieved_gbs"] / attainable},
         "cpu_baseline": cpu,
         "detail": main_res,
         "also": also,

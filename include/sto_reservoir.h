@@ -179,6 +179,16 @@ sto_status readout_fit_device(const void *states_dev, int32_t dtype, int64_t T, 
                               const void *y_dev, int64_t washout, double lambda, int32_t features,
                               void *w_out_dev, double *nmse_out, void *hip_stream);
 
+/*
+ * sto_read_bandwidth -- diagnostic: HBM read bandwidth this device attains
+ * with a plain streaming kernel (16-byte non-temporal loads over a buffer of
+ * `bytes`, read `reps` times), in GB/s.  Used to report the roofline of the
+ * coupling kernels against the attainable as well as the nominal peak.
+ * Allocates and frees its own buffer.  Errors: STO_E_INVALID, STO_E_NOMEM,
+ * STO_E_DEVICE.
+ */
+sto_status sto_read_bandwidth(int64_t bytes, int32_t reps, double *gbs_out);
+
 /* sto_last_error -- message of the last non-OK status on this thread
  * (empty string if none).  Valid until the next call on this thread. */
 const char *sto_last_error(void);

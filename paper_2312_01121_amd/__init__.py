@@ -83,6 +83,8 @@ def _load():
     lib.readout_fit_device.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, vp, ctypes.c_int64,
                                        ctypes.c_double, ctypes.c_int32, vp, dp, vp]
     lib.readout_fit_device.restype = ctypes.c_int
+    lib.sto_read_bandwidth.argtypes = [ctypes.c_int64, ctypes.c_int32, dp]
+    lib.sto_read_bandwidth.restype = ctypes.c_int
     lib.sto_last_error.restype = ctypes.c_char_p
     for name in ("reservoir_create", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
                  "reservoir_set_state", "readout_fit"):
@@ -94,7 +96,7 @@ _lib = _load()
 
 EXPORTED = ("reservoir_create", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
             "reservoir_set_state", "reservoir_path", "reservoir_destroy", "readout_fit", "readout_fit_device",
-            "sto_last_error")
+            "sto_read_bandwidth", "sto_last_error")
 
 
 def lib():
@@ -196,6 +198,13 @@ def readout_fit_device(states_dev, y_dev, washout: int, lam: float, features: in
                                    ctypes.c_void_p(y_dev.data_ptr()), washout, lam, features,
                                    ctypes.c_void_p(w_out_dev.data_ptr()), _dptr(nmse), ctypes.c_void_p(s)))
     return w_out_dev, float(nmse[0])
+
+
+def sto_read_bandwidth(nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """Attainable HBM read bandwidth (GB/s) of a plain streaming kernel."""
+    out = np.empty(1)
+    _check(_lib.sto_read_bandwidth(nbytes, reps, _dptr(out)))
+    return float(out[0])
 
 
 class Reservoir:

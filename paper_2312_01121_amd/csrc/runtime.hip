@@ -55,11 +55,18 @@ int env_flag(const char* name, int dflt) {
     return std::atoi(v) != 0;
 }
 
+int env_int(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    return std::atoi(v);
+}
+
 }  // namespace
 
 namespace sto {
 const Tune& tune() {
-    static const Tune t = {env_flag("STO_STREAM_ALTERNATE", 0), env_flag("STO_STREAM_NT", 1)};
+    static const Tune t = {env_flag("STO_STREAM_ALTERNATE", 0), env_flag("STO_STREAM_NT", 1),
+                           env_int("STO_STREAM_ROWS", 0), env_int("STO_STREAM_UNROLL", 0)};
     return t;
 }
 }  // namespace sto
@@ -271,6 +278,13 @@ sto_status readout_status(int rc, const char* err) {
 extern "C" {
 
 const char* sto_last_error(void) { return g_err.c_str(); }
+
+sto_status sto_read_bandwidth(int64_t bytes, int32_t reps, double* gbs_out) {
+    if (!gbs_out || bytes < (1 << 20) || reps < 1) return fail(STO_E_INVALID, "bytes >= 1 MiB, reps >= 1, gbs_out");
+    hipError_t e = sto::read_bandwidth(bytes, reps, gbs_out);
+    if (e != hipSuccess) return hip_fail(e, "read bandwidth probe");
+    return STO_OK;
+}
 
 sto_status reservoir_create(int64_t n, int64_t n_in, const sto_params* prm, const double* W,
                             const double* w_in, const double* m0, sto_reservoir** out) {

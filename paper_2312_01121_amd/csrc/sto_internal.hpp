@@ -41,10 +41,13 @@ struct RunSpec {
 };
 
 // Launch-shape choices, fixed defaults overridable through the environment
-// (STO_STREAM_ALTERNATE, STO_STREAM_NT: 0 or 1) for measurements.
+// for measurements (STO_STREAM_ALTERNATE, STO_STREAM_NT: 0 or 1;
+// STO_STREAM_ROWS, STO_STREAM_UNROLL: a compiled variant).
 struct Tune {
     int stream_alternate;    // reverse the row order of the stream kernel on odd stages
     int stream_nontemporal;  // stream W with non-temporal loads
+    int stream_rows;         // rows per wave of the stream kernel (0: default)
+    int stream_unroll;       // column-loop unroll of the stream kernel (0: default)
 };
 const Tune& tune();
 
@@ -62,6 +65,9 @@ bool resident_fits(int n, int elem_bytes, int xyz, int* grid_out);
 // Offset (in ints) of the abort flag in DevState::sync; non-zero after a
 // resident run means a grid barrier timed out.
 constexpr int kSyncAbortWord = 32;
+
+// Attainable HBM read bandwidth of a plain streaming kernel (GB/s).
+hipError_t read_bandwidth(int64_t bytes, int reps, double* gbs);
 
 // Readout (FP64): see readout.hip.
 // rec_dev: rows x n x 3 records of type rec_f32 ? float : double; y_dev:

@@ -19,6 +19,7 @@
 //            row sum.  No launch, no global memory traffic per step beyond
 //            the records.
 
+#include <algorithm>
 #include <climits>
 
 #include "sto_internal.hpp"
@@ -81,7 +82,7 @@ __device__ __forceinline__ void stage_epilogue(const DevState<T>& d, const Coef<
 // ---------------------------------------------------------------------------
 // STREAM path: one RK4 stage.
 // ---------------------------------------------------------------------------
-template <typename T, bool XYZ, int R, bool NT>
+template <typename T, bool XYZ, int R, bool NT, int U>
 __global__ void __launch_bounds__(256) k_stage(DevState<T> d, Coef<T> k, const double* __restrict__ u_s,
                                                T* __restrict__ record, int sample, int stage, int cur,
                                                int renorm, int reverse) {
@@ -110,7 +111,7 @@ __global__ void __launch_bounds__(256) k_stage(DevState<T> d, Coef<T> k, const d
 #pragma unroll
     for (int r = 0; r < R; ++r) ax[r] = ay[r] = az[r] = A::zero();
 
-#pragma unroll 2
+#pragma unroll U
     for (int64_t c = (int64_t)lane * VN; c < ld; c += 64 * VN) {
         V xv = *reinterpret_cast<const V*>(xin + c);
         V yv, zv;
@@ -160,21 +161,42 @@ __global__ void __launch_bounds__(256) k_stage(DevState<T> d, Coef<T> k, const d
     }
 }
 
-template <typename T> constexpr int stream_rows() { return sizeof(T) == 8 ? 2 : 4; }
+template <typename T, bool XYZ, bool NT, int R, int U>
+static void launch_stage(hipStream_t st, const DevState<T>& d, const Coef<T>& k, const double* u_s, T* rec, int s,
+                         int stage, int c, int renorm, int reverse) {
+    dim3 grid((d.n + 4 * R - 1) / (4 * R));
+    hipLaunchKernelGGL((k_stage<T, XYZ, R, NT, U>), grid, dim3(256), 0, st, d, k, u_s, rec, s, stage, c, renorm,
+                       reverse);
+}
 
+// Variants of the stream kernel: rows per wave R and column-loop unroll U.
 template <typename T, bool XYZ, bool NT>
-static void launch_stage(dim3 grid, hipStream_t st, const DevState<T>& d, const Coef<T>& k, const double* u_s,
-                         T* rec, int s, int stage, int c, int renorm, int reverse) {
-    hipLaunchKernelGGL((k_stage<T, XYZ, stream_rows<T>(), NT>), grid, dim3(256), 0, st, d, k, u_s, rec, s, stage,
-                       c, renorm, reverse);
+static void launch_stage_rv(int rows, int unroll, hipStream_t st, const DevState<T>& d, const Coef<T>& k,
+                            const double* u_s, T* rec, int s, int stage, int c, int renorm, int reverse) {
+#define STO_STAGE_CASE(RR, UU)                                                                   \
+    if (rows == RR && unroll == UU) {                                                            \
+        launch_stage<T, XYZ, NT, RR, UU>(st, d, k, u_s, rec, s, stage, c, renorm, reverse); \
+        return;                                                                                  \
+    }
+    STO_STAGE_CASE(1, 4)
+    STO_STAGE_CASE(2, 2)
+    STO_STAGE_CASE(2, 4)
+    STO_STAGE_CASE(4, 1)
+    STO_STAGE_CASE(4, 2)
+    STO_STAGE_CASE(4, 4)
+    STO_STAGE_CASE(8, 1)
+    STO_STAGE_CASE(8, 2)
+#undef STO_STAGE_CASE
+    launch_stage<T, XYZ, NT, sizeof(T) == 8 ? 2 : 4, 2>(st, d, k, u_s, rec, s, stage, c, renorm, reverse);
 }
 
 template <typename T>
 hipError_t run_stream(const DevState<T>& d, const Coef<T>& k, const RunSpec& r) {
-    constexpr int R = stream_rows<T>();
-    const int rows_per_block = 4 * R;
-    dim3 grid((d.n + rows_per_block - 1) / rows_per_block);
     const Tune& t = tune();
+    // defaults from a sweep at N = 10,000 (rows per wave x unroll in
+    // {1,2,4,8} x {1,2,4}): FP32 2 x 2 and FP64 2 x 4 stream W fastest
+    const int rows = t.stream_rows > 0 ? t.stream_rows : 2;
+    const int unroll = t.stream_unroll > 0 ? t.stream_unroll : (sizeof(T) == 8 ? 4 : 2);
     T* states = static_cast<T*>(r.states);
     int cur = r.cur;
     int64_t sigma = 0;
@@ -187,16 +209,109 @@ hipError_t run_stream(const DevState<T>& d, const Coef<T>& k, const RunSpec& r) 
                 const int c = cur ^ (stage & 1);
                 const int rev = t.stream_alternate ? (int)(sigma & 1) : 0;
                 if (r.xyz) {
-                    if (t.stream_nontemporal) launch_stage<T, true, true>(grid, r.stream, d, k, u_s, rec, s, stage, c, r.renorm, rev);
-                    else launch_stage<T, true, false>(grid, r.stream, d, k, u_s, rec, s, stage, c, r.renorm, rev);
+                    if (t.stream_nontemporal) launch_stage_rv<T, true, true>(rows, unroll, r.stream, d, k, u_s, rec, s, stage, c, r.renorm, rev);
+                    else launch_stage_rv<T, true, false>(rows, unroll, r.stream, d, k, u_s, rec, s, stage, c, r.renorm, rev);
                 } else {
-                    if (t.stream_nontemporal) launch_stage<T, false, true>(grid, r.stream, d, k, u_s, rec, s, stage, c, r.renorm, rev);
-                    else launch_stage<T, false, false>(grid, r.stream, d, k, u_s, rec, s, stage, c, r.renorm, rev);
+                    if (t.stream_nontemporal) launch_stage_rv<T, false, true>(rows, unroll, r.stream, d, k, u_s, rec, s, stage, c, r.renorm, rev);
+                    else launch_stage_rv<T, false, false>(rows, unroll, r.stream, d, k, u_s, rec, s, stage, c, r.renorm, rev);
                 }
             }
         }
     }
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostic: attainable HBM read bandwidth (plain streaming read).
+// ---------------------------------------------------------------------------
+template <int L>
+__global__ void __launch_bounds__(256) k_read_probe(const fvec4* __restrict__ src, int64_t nvec,
+                                                    float* __restrict__ sink) {
+    fvec4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (; i + (L - 1) * stride < nvec; i += L * stride) {
+        fvec4 v[L];
+#pragma unroll
+        for (int q = 0; q < L; ++q) v[q] = __builtin_nontemporal_load(src + i + q * stride);
+#pragma unroll
+        for (int q = 0; q < L; ++q) acc += v[q];
+    }
+    for (; i < nvec; i += stride) acc += __builtin_nontemporal_load(src + i);
+    const float v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    if (v == 12345.678f) sink[threadIdx.x] = v;   // keeps the loads alive; never true for zeros
+}
+
+// Each wave streams one contiguous segment (the access pattern of the
+// coupling kernel, whose waves each read whole rows).
+template <int L>
+__global__ void __launch_bounds__(256) k_read_probe_seg(const fvec4* __restrict__ src, int64_t nvec,
+                                                        int64_t seg, float* __restrict__ sink) {
+    fvec4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t b = wave * seg;
+    const int64_t e = b + seg < nvec ? b + seg : nvec;
+    int64_t i = b + lane;
+    for (; i + (L - 1) * 64 < e; i += L * 64) {
+        fvec4 v[L];
+#pragma unroll
+        for (int q = 0; q < L; ++q) v[q] = __builtin_nontemporal_load(src + i + q * 64);
+#pragma unroll
+        for (int q = 0; q < L; ++q) acc += v[q];
+    }
+    for (; i < e; i += 64) acc += __builtin_nontemporal_load(src + i);
+    const float v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    if (v == 12345.678f) sink[threadIdx.x] = v;
+}
+
+// Best of a few launch shapes: grid-stride with 4 or 8 loads in flight per
+// thread at 4, 8 or 16 workgroups per CU, and contiguous per-wave segments.
+hipError_t read_bandwidth(int64_t bytes, int reps, double* gbs) {
+    void* buf = nullptr;
+    float* sink = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const int64_t nvec = bytes / 16;
+    hipError_t e = hipMalloc(&buf, nvec * 16);
+    if (e == hipSuccess) e = hipMalloc(&sink, 256 * sizeof(float));
+    if (e == hipSuccess) e = hipMemset(buf, 0, nvec * 16);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int dev = 0, cus = 0;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    double best = 0.0;
+    const int per_cu[] = {4, 8, 16};
+    for (int lf = 0; lf < 4 && e == hipSuccess; ++lf) {
+        for (int pc : per_cu) {
+            const dim3 grid(cus * pc), block(256);
+            const int64_t waves = (int64_t)cus * pc * 4;
+            const int64_t seg = (nvec + waves - 1) / waves;
+            auto launch = [&]() {
+                if (lf == 0) hipLaunchKernelGGL(k_read_probe<4>, grid, block, 0, nullptr, (const fvec4*)buf, nvec, sink);
+                else if (lf == 1) hipLaunchKernelGGL(k_read_probe<8>, grid, block, 0, nullptr, (const fvec4*)buf, nvec, sink);
+                else if (lf == 2)
+                    hipLaunchKernelGGL(k_read_probe_seg<4>, grid, block, 0, nullptr, (const fvec4*)buf, nvec, seg, sink);
+                else
+                    hipLaunchKernelGGL(k_read_probe_seg<8>, grid, block, 0, nullptr, (const fvec4*)buf, nvec, seg, sink);
+            };
+            launch();   // warm-up
+            e = hipEventRecord(e0, nullptr);
+            for (int r = 0; r < reps && e == hipSuccess; ++r) launch();
+            if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && ms > 0.f) best = std::max(best, (double)nvec * 16 * reps / (ms * 1e-3) / 1e9);
+            if (e == hipSuccess) e = hipGetLastError();
+        }
+    }
+    if (e == hipSuccess) *gbs = best;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (buf) (void)hipFree(buf);
+    if (sink) (void)hipFree(sink);
+    return e;
 }
 
 // ---------------------------------------------------------------------------
