@@ -142,6 +142,155 @@ def run_workload(stx, torch, name: str, dtype: str, steps: int, warmup: int, arr
     }
 
 
+def run_streams_workload(stx, torch, name: str, steps: int, warmup: int):
+    """S input streams share one reservoir (MULTI path, FP32 MFMA coupling);
+    one step is the run of every stream plus one readout per stream.  The
+    same work through the plain single-reservoir path is timed on one stream
+    and scaled by S."""
+    from workloads import STREAMS, WORKLOADS, make_stream_arrays
+    from paper_2312_01121_amd import params
+
+    wl = WORKLOADS[name]
+    S = STREAMS[name]
+    a = make_stream_arrays(wl, S)
+    prm = stx.make_params(**params.table1(a_cp=wl.a_cp, a_in=wl.a_in, dt=wl.dt, substeps=wl.substeps), dtype="f32")
+    import numpy as np
+    m0s = np.ascontiguousarray(np.broadcast_to(a["m0"], (S, wl.n, 3)))
+    r = stx.Reservoir(a["W"], a["w_in"], m0s, prm, streams=S)
+    u_d = torch.from_numpy(a["u"]).cuda()
+    y = np.nan_to_num(a["y"], nan=0.0)
+    y_d = [torch.from_numpy(np.ascontiguousarray(y[:, st])).cuda() for st in range(S)]
+    states = torch.empty((wl.samples, S, wl.n, 3), dtype=torch.float32, device="cuda")
+    w_out = torch.empty(wl.n + 1, dtype=torch.float64, device="cuda")
+    wash = washout_of(wl.samples)
+    stream = torch.cuda.current_stream()
+
+    def one_step():
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        r.run_device(u_d, states, stream)
+        e1.record(stream)
+        nm = []
+        for st in range(S):
+            rec = states[:, st].contiguous()
+            nm.append(stx.readout_fit_device(rec, y_d[st], wash, wl.ridge, 0, w_out, stream)[1])
+        return e0, e1, nm
+
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs = [one_step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    run_ms = sum(e0.elapsed_time(e1) for e0, e1, _ in evs) / steps
+    nmse = evs[-1][2]
+    path = r.path
+    r.close()
+    # plain path: one stream through the single-reservoir kernels, x S
+    r1 = stx.Reservoir(a["W"], a["w_in"], a["m0"], prm)
+    plain_path = r1.path
+    u1 = torch.from_numpy(np.ascontiguousarray(a["u"][:, 0])).cuda()
+    st1 = torch.empty((wl.samples, wl.n, 3), dtype=torch.float32, device="cuda")
+    r1.run_device(u1, st1, stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    r1.run_device(u1, st1, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1) * S
+    r1.close()
+    wall_s = (t1 - t0) / steps
+    flops = 2.0 * wl.n * wl.n * S * 4 * wl.steps
+    return {
+        "workload": name, "n": wl.n, "streams": S, "dtype": "f32", "path": path, "samples": wl.samples,
+        "substeps": wl.substeps, "rk4_steps": wl.steps,
+        "value": S * wl.n * wl.steps / wall_s, "ms_per_step": wall_s * 1e3, "run_ms": run_ms,
+        "us_per_rk4_step": run_ms * 1e3 / wl.steps, "readout_nmse_mean": float(np.mean(nmse)),
+        "kernel": "k_multi", "mfma_tflops": flops / (run_ms * 1e-3) / 1e12,
+        "mfma_frac": flops / (run_ms * 1e-3) / 157.3e12,
+        "plain_path": plain_path, "plain_run_ms_for_all_streams": plain_ms,
+        "speedup_vs_plain": plain_ms / run_ms,
+    }
+
+
+def run_sweep_workload(stx, torch, name: str, steps: int, warmup: int, plain_samples: int = 20):
+    """Parameter sweep (SWEEP path): every reservoir's run plus one readout
+    per reservoir is one step.  The plain single-reservoir path (each
+    reservoir alone, its own auto-selected kernel) is timed on the first
+    ``plain_samples`` samples and scaled to the full series."""
+    import numpy as np
+    from workloads import SWEEPS, make_sweep_arrays
+    from paper_2312_01121_amd import params
+
+    sw_def = SWEEPS[name]
+    a = make_sweep_arrays(sw_def)
+    res = a["reservoirs"]
+    for r in res:
+        r["prm"] = stx.make_params(**params.table1(a_cp=r["a_cp"], a_in=r["a_in"], dt=sw_def.dt,
+                                                   substeps=sw_def.substeps, current_scale=r["current_scale"],
+                                                   field_scale=r["field_scale"]), dtype="f32")
+    sw = stx.Sweep(res)
+    T = sw_def.samples
+    u_d = torch.from_numpy(a["u"]).cuda()
+    y_d = torch.from_numpy(np.nan_to_num(a["y"], nan=0.0)).cuda()
+    states = torch.empty(T * sw.nodes * 3, dtype=torch.float32, device="cuda")
+    w_out = torch.empty(max(sw.ns) + 1, dtype=torch.float64, device="cuda")
+    wash = washout_of(T)
+    stream = torch.cuda.current_stream()
+
+    def one_step():
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sw.run_device(u_d, states, stream)
+        e1.record(stream)
+        nm = []
+        for i, n in enumerate(sw.ns):
+            rec = states[T * 3 * int(sw.offsets[i]): T * 3 * int(sw.offsets[i + 1])].view(T, n, 3)
+            nm.append(stx.readout_fit_device(rec, y_d, wash, sw_def.ridge, 0, w_out[: n + 1], stream)[1])
+        return e0, e1, nm
+
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs = [one_step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    run_ms = sum(e0.elapsed_time(e1) for e0, e1, _ in evs) / steps
+    nmse = np.array(evs[-1][2])
+    sw.close()
+    # plain path: each reservoir alone
+    u_p = torch.from_numpy(np.ascontiguousarray(a["u"][:plain_samples])).cuda()
+    plain_ms = 0.0
+    paths = {}
+    for r in res:
+        one = stx.Reservoir(r["W"], r["w_in"], r["m0"], r["prm"])
+        paths[one.path] = paths.get(one.path, 0) + 1
+        st1 = torch.empty((plain_samples, r["n"], 3), dtype=torch.float32, device="cuda")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        one.run_device(u_p, st1, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        plain_ms += e0.elapsed_time(e1) * T / plain_samples
+        one.close()
+    wall_s = (t1 - t0) / steps
+    launches = 4 * sw_def.steps
+    algo = float(sum(r["n"] ** 2 for r in res)) * 4
+    achieved = algo / (run_ms * 1e-3 / launches) / 1e9
+    return {
+        "workload": name, "reservoirs": len(res), "nodes": int(sw.nodes), "n_min": int(min(sw.ns)),
+        "n_max": int(max(sw.ns)), "dtype": "f32", "path": "sweep", "samples": T, "rk4_steps": sw_def.steps,
+        "value": sw.nodes * sw_def.steps / wall_s, "ms_per_step": wall_s * 1e3, "run_ms": run_ms,
+        "us_per_rk4_step": run_ms * 1e3 / sw_def.steps, "kernel": "k_sweep_stage", "launches_per_run": launches,
+        "algo_bytes_per_launch": algo, "achieved_gbs": achieved, "hbm_frac": achieved / HBM_PEAK_GBS,
+        "readout_nmse_median": float(np.median(nmse)), "readout_nmse_min": float(np.min(nmse)),
+        "plain_paths": paths, "plain_run_ms_estimate": plain_ms, "speedup_vs_plain": plain_ms / run_ms,
+    }
+
+
 def cpu_baseline(name: str, arrays, budget_s: float = 25.0):
     """The FP64 oracle (correctly rounded coupling sums) on the first input
     samples of the workload, on this host's cores."""
@@ -218,6 +367,14 @@ def main():
             res = run_workload(stx, torch, name, dt, k, w, arrays if name == args.workload else None)
             log(json.dumps(res))
             also.append(res)
+        log("also sweep256")
+        res = run_sweep_workload(stx, torch, "sweep256", 1, 1)
+        log(json.dumps(res))
+        also.append(res)
+        log("also streams64")
+        res = run_streams_workload(stx, torch, "streams64", 1, 1)
+        log(json.dumps(res))
+        also.append(res)
     cpu = None
     if not args.no_cpu:
         log("cpu baseline")

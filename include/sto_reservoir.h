@@ -52,7 +52,9 @@ typedef enum {
     STO_PATH_AUTO = 0,
     STO_PATH_SMALL = 1,     /* one workgroup holds W and the state; all steps in one launch */
     STO_PATH_RESIDENT = 2,  /* W split across the CUs' LDS; all steps in one cooperative launch */
-    STO_PATH_STREAM = 3     /* W streamed from HBM once per RK4 stage, one launch per stage */
+    STO_PATH_STREAM = 3,    /* W streamed from HBM once per RK4 stage, one launch per stage */
+    STO_PATH_MULTI = 4      /* S input streams share W: the coupling of all streams is one FP32
+                               MFMA matrix product per stage; all steps in one cooperative launch */
 } sto_path;
 
 /*
@@ -104,6 +106,24 @@ sto_status reservoir_create(int64_t n, int64_t n_in, const sto_params *prm,
                             sto_reservoir **out);
 
 /*
+ * reservoir_create_streams -- a reservoir driven by S independent input
+ * streams at once: S copies of the same oscillators (one W, w_in and set of
+ * constants), each with its own state and input series.  The coupling of
+ * all streams is the product of W with the N x S block of stage inputs
+ * (Eq. (coup) applied to every stream).
+ *   streams  S >= 1; S == 1 is reservoir_create
+ *   m0       host, S*n*3 doubles, [stream][node][xyz]
+ * For S > 1 the handle runs STO_PATH_MULTI: prm->dtype must be STO_F32,
+ * prm->coupling STO_COUPLE_X and n <= 1024, else STO_E_UNSUPPORTED (also when
+ * the S x n tiles cannot all be co-resident).  For such a handle, u and
+ * states of the run calls gain a stream axis: u is [sample][stream][n_in]
+ * and states [sample][stream][node][xyz]; get/set_state use [stream][node][xyz].
+ */
+sto_status reservoir_create_streams(int64_t n, int64_t n_in, int64_t streams, const sto_params *prm,
+                                    const double *W, const double *w_in, const double *m0,
+                                    sto_reservoir **out);
+
+/*
  * reservoir_run -- integrate steps RK4 steps from the current state.
  *   u       host, (steps/substeps) * n_in doubles, one input vector per
  *           sample, held for substeps steps (all four stages of a step see
@@ -136,11 +156,60 @@ sto_status reservoir_run_device(sto_reservoir *r, const void *u_dev, int64_t ste
 sto_status reservoir_get_state(const sto_reservoir *r, double *m);
 sto_status reservoir_set_state(sto_reservoir *r, const double *m);
 
+/* reservoir_streams -- S of the handle (1 for reservoir_create), or -1 for NULL. */
+int64_t reservoir_streams(const sto_reservoir *r);
+
 /* reservoir_path -- the sto_path the handle runs (never STO_PATH_AUTO). */
 int32_t reservoir_path(const sto_reservoir *r);
 
 /* reservoir_destroy -- free the handle and its device memory; NULL is a no-op. */
 void reservoir_destroy(sto_reservoir *r);
+
+/*
+ * Parameter sweeps: many independent reservoirs of uneven size and their own
+ * constants (the parameter-space exploration the paper motivates, Sec. 1
+ * and 2), driven by one shared input series and stepped together on the GPU.
+ */
+typedef struct sto_sweep sto_sweep;
+
+/*
+ * sweep_create -- build `count` reservoirs on the current device.
+ *   n[r]     nodes of reservoir r (>= 1)
+ *   n_in     input channels, shared (the input series is shared)
+ *   prm[r]   constants of reservoir r; dtype, coupling, substeps and
+ *            renormalize must agree across r (STO_E_INVALID otherwise);
+ *            coupling must be STO_COUPLE_X (STO_E_UNSUPPORTED otherwise);
+ *            path is ignored
+ *   W[r], w_in[r], m0[r]  host arrays as in reservoir_create
+ * The handle owns device copies of every matrix and state.
+ */
+sto_status sweep_create(int32_t count, const int64_t *n, int64_t n_in, const sto_params *prm,
+                        const double *const *W, const double *const *w_in, const double *const *m0,
+                        sto_sweep **out);
+
+/* sweep_nodes -- total nodes (sum of n[r]), or -1 for NULL. */
+int64_t sweep_nodes(const sto_sweep *s);
+
+/*
+ * sweep_run / sweep_run_device -- integrate every reservoir steps RK4 steps.
+ *   u       (steps/substeps) * n_in doubles, the shared input series (host
+ *           for sweep_run, device for sweep_run_device)
+ *   states  (steps/substeps) * sum(n) * 3 elements or NULL, laid out
+ *           [reservoir][sample][node][xyz]: reservoir r's records are one
+ *           contiguous block starting at samples * (n[0] + ... + n[r-1]) * 3
+ *           (doubles on the host; the handle's dtype on the device)
+ *   hip_stream  as in reservoir_run_device
+ * Continuation, blocking and STO_E_NONFINITE behave as in reservoir_run.
+ */
+sto_status sweep_run(sto_sweep *s, const double *u, int64_t steps, double *states);
+sto_status sweep_run_device(sto_sweep *s, const void *u_dev, int64_t steps, void *states_dev,
+                            void *hip_stream);
+
+/* sweep_get_state -- current states, host, sum(n)*3 doubles, reservoirs in order. */
+sto_status sweep_get_state(const sto_sweep *s, double *m);
+
+/* sweep_destroy -- free the handle; NULL is a no-op. */
+void sweep_destroy(sto_sweep *s);
 
 /*
  * readout_fit -- ridge-regression readout, computed in FP64 on the GPU.

@@ -24,8 +24,8 @@ LIB_PATH = os.path.join(_PKG, "libsto_reservoir.so")
 STO_OK, STO_E_INVALID, STO_E_NOMEM, STO_E_DEVICE, STO_E_NONFINITE, STO_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 STO_F64, STO_F32 = 0, 1
 STO_COUPLE_X, STO_COUPLE_XYZ = 0, 1
-PATH_AUTO, PATH_SMALL, PATH_RESIDENT, PATH_STREAM = 0, 1, 2, 3
-PATH_NAMES = {PATH_SMALL: "small", PATH_RESIDENT: "resident", PATH_STREAM: "stream"}
+PATH_AUTO, PATH_SMALL, PATH_RESIDENT, PATH_STREAM, PATH_MULTI = 0, 1, 2, 3, 4
+PATH_NAMES = {PATH_SMALL: "small", PATH_RESIDENT: "resident", PATH_STREAM: "stream", PATH_MULTI: "multi"}
 _STATUS_NAMES = {STO_E_INVALID: "invalid", STO_E_NOMEM: "nomem", STO_E_DEVICE: "device",
                  STO_E_NONFINITE: "nonfinite", STO_E_UNSUPPORTED: "unsupported"}
 
@@ -56,7 +56,8 @@ def make_params(alpha, h_appl, h_k, h_s, lambda_stt, p, a_cp, a_in, dt, substeps
     pr.renormalize = int(bool(renormalize))
     pr.dtype = {"f64": STO_F64, "f32": STO_F32}[dtype]
     pr.coupling = {"x": STO_COUPLE_X, "xyz": STO_COUPLE_XYZ}[coupling]
-    pr.path = {"auto": PATH_AUTO, "small": PATH_SMALL, "resident": PATH_RESIDENT, "stream": PATH_STREAM}[path]
+    pr.path = {"auto": PATH_AUTO, "small": PATH_SMALL, "resident": PATH_RESIDENT, "stream": PATH_STREAM,
+               "multi": PATH_MULTI}[path]
     pr.reserved = 0
     return pr
 
@@ -70,6 +71,10 @@ def _load():
     H = ctypes.c_void_p
     lib.reservoir_create.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(sto_params), dp, dp, dp,
                                      ctypes.POINTER(H)]
+    lib.reservoir_create_streams.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                             ctypes.POINTER(sto_params), dp, dp, dp, ctypes.POINTER(H)]
+    lib.reservoir_streams.argtypes = [H]
+    lib.reservoir_streams.restype = ctypes.c_int64
     lib.reservoir_run.argtypes = [H, dp, ctypes.c_int64, dp]
     lib.reservoir_run_device.argtypes = [H, vp, ctypes.c_int64, vp, vp]
     lib.reservoir_get_state.argtypes = [H, dp]
@@ -83,10 +88,24 @@ def _load():
     lib.readout_fit_device.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, vp, ctypes.c_int64,
                                        ctypes.c_double, ctypes.c_int32, vp, dp, vp]
     lib.readout_fit_device.restype = ctypes.c_int
+    pp = ctypes.POINTER(dp)
+    lib.sweep_create.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64,
+                                 ctypes.POINTER(sto_params), pp, pp, pp, ctypes.POINTER(H)]
+    lib.sweep_create.restype = ctypes.c_int
+    lib.sweep_nodes.argtypes = [H]
+    lib.sweep_nodes.restype = ctypes.c_int64
+    lib.sweep_run.argtypes = [H, dp, ctypes.c_int64, dp]
+    lib.sweep_run.restype = ctypes.c_int
+    lib.sweep_run_device.argtypes = [H, vp, ctypes.c_int64, vp, vp]
+    lib.sweep_run_device.restype = ctypes.c_int
+    lib.sweep_get_state.argtypes = [H, dp]
+    lib.sweep_get_state.restype = ctypes.c_int
+    lib.sweep_destroy.argtypes = [H]
+    lib.sweep_destroy.restype = None
     lib.sto_read_bandwidth.argtypes = [ctypes.c_int64, ctypes.c_int32, dp]
     lib.sto_read_bandwidth.restype = ctypes.c_int
     lib.sto_last_error.restype = ctypes.c_char_p
-    for name in ("reservoir_create", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
+    for name in ("reservoir_create", "reservoir_create_streams", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
                  "reservoir_set_state", "readout_fit"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
@@ -94,8 +113,9 @@ def _load():
 
 _lib = _load()
 
-EXPORTED = ("reservoir_create", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
+EXPORTED = ("reservoir_create", "reservoir_create_streams", "reservoir_streams", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
             "reservoir_set_state", "reservoir_path", "reservoir_destroy", "readout_fit", "readout_fit_device",
+            "sweep_create", "sweep_nodes", "sweep_run", "sweep_run_device", "sweep_get_state", "sweep_destroy",
             "sto_read_bandwidth", "sto_last_error")
 
 
@@ -130,6 +150,20 @@ def reservoir_create(n: int, n_in: int, prm: sto_params, W, w_in, m0) -> ctypes.
     h = ctypes.c_void_p()
     _check(_lib.reservoir_create(n, n_in, ctypes.byref(prm), _dptr(W), _dptr(w_in), _dptr(m0), ctypes.byref(h)))
     return h
+
+
+def reservoir_create_streams(n: int, n_in: int, streams: int, prm: sto_params, W, w_in, m0) -> ctypes.c_void_p:
+    W = _f64(W, (n, n))
+    w_in = _f64(w_in, (n, n_in))
+    m0 = _f64(m0, (streams, n, 3))
+    h = ctypes.c_void_p()
+    _check(_lib.reservoir_create_streams(n, n_in, streams, ctypes.byref(prm), _dptr(W), _dptr(w_in), _dptr(m0),
+                                         ctypes.byref(h)))
+    return h
+
+
+def reservoir_streams(h) -> int:
+    return int(_lib.reservoir_streams(h))
 
 
 def reservoir_run(h, u, steps: int, states: Optional[np.ndarray] = None):
@@ -208,52 +242,143 @@ def sto_read_bandwidth(nbytes: int = 1 << 30, reps: int = 10) -> float:
 
 
 class Reservoir:
-    """Owns one library handle; every method calls the C entry point of the same name."""
+    """Owns one library handle; every method calls the C entry point of the same name.
 
-    def __init__(self, W, w_in, m0, prm: sto_params):
+    With streams > 1, m0 is (streams, n, 3), u is (samples, streams, n_in)
+    and the records are (samples, streams, n, 3)."""
+
+    def __init__(self, W, w_in, m0, prm: sto_params, streams: int = 1):
         W = np.asarray(W)
         self.n = W.shape[0]
         w_in = np.asarray(w_in, dtype=np.float64).reshape(self.n, -1)
         self.n_in = w_in.shape[1]
+        self.streams = int(streams)
         self.substeps = prm.substeps
         self.dtype = "f64" if prm.dtype == STO_F64 else "f32"
-        self.h = reservoir_create(self.n, self.n_in, prm, W, w_in, m0)
+        if self.streams == 1:
+            self.h = reservoir_create(self.n, self.n_in, prm, W, w_in, m0)
+        else:
+            self.h = reservoir_create_streams(self.n, self.n_in, self.streams, prm, W, w_in, m0)
 
     @property
     def path(self) -> str:
         return PATH_NAMES[reservoir_path(self.h)]
 
+    def _record_shape(self, samples):
+        return (samples, self.n, 3) if self.streams == 1 else (samples, self.streams, self.n, 3)
+
     def run(self, u, record: bool = True) -> Optional[np.ndarray]:
-        u = _f64(u).reshape(-1, self.n_in)
+        u = _f64(u).reshape(-1, self.streams * self.n_in)
         steps = len(u) * self.substeps
-        states = np.empty((len(u), self.n, 3)) if record else None
+        states = np.empty(self._record_shape(len(u))) if record else None
         reservoir_run(self.h, u, steps, states)
         return states
 
     def run_device(self, u_dev, states_dev=None, stream=None):
-        """u_dev: CUDA float64 tensor (samples, n_in); states_dev: CUDA tensor
-        (samples, n, 3) of the handle's dtype, or None; stream: a
-        torch.cuda.Stream (default: the current stream)."""
+        """u_dev: CUDA float64 tensor (samples, [streams,] n_in); states_dev:
+        CUDA tensor (samples, [streams,] n, 3) of the handle's dtype, or None;
+        stream: a torch.cuda.Stream (default: the current stream)."""
         import torch
         assert u_dev.is_cuda and u_dev.dtype == torch.float64 and u_dev.is_contiguous()
-        samples = u_dev.numel() // self.n_in
+        samples = u_dev.numel() // (self.n_in * self.streams)
         if states_dev is not None:
             want = torch.float64 if self.dtype == "f64" else torch.float32
             assert states_dev.is_cuda and states_dev.dtype == want and states_dev.is_contiguous()
-            assert states_dev.numel() == samples * self.n * 3
+            assert states_dev.numel() == samples * self.streams * self.n * 3
         s = (stream or torch.cuda.current_stream()).cuda_stream
         reservoir_run_device(self.h, u_dev.data_ptr(), samples * self.substeps,
                              states_dev.data_ptr() if states_dev is not None else None, s)
 
     def get_state(self) -> np.ndarray:
-        return reservoir_get_state(self.h, self.n)
+        m = reservoir_get_state(self.h, self.n * self.streams)
+        return m if self.streams == 1 else m.reshape(self.streams, self.n, 3)
 
     def set_state(self, m):
-        reservoir_set_state(self.h, np.asarray(m, dtype=np.float64).reshape(self.n, 3))
+        reservoir_set_state(self.h, np.asarray(m, dtype=np.float64).reshape(self.streams * self.n, 3))
 
     def close(self):
         if getattr(self, "h", None):
             reservoir_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Sweep:
+    """Many independent reservoirs stepped together (calls the sweep_* entry points).
+
+    reservoirs: list of dicts with "W", "w_in", "m0" and a ``sto_params`` under
+    "prm".  Records come back as a list with one (samples, n_r, 3) array per
+    reservoir (host run), or as one device tensor laid out
+    [reservoir][sample][node][xyz] (device run)."""
+
+    def __init__(self, reservoirs):
+        self.count = len(reservoirs)
+        self.ns = [int(np.asarray(r["W"]).shape[0]) for r in reservoirs]
+        self.n_in = int(np.asarray(reservoirs[0]["w_in"], dtype=np.float64).reshape(self.ns[0], -1).shape[1])
+        self._keep = []
+        dp = ctypes.POINTER(ctypes.c_double)
+
+        def arr(key, shape_fn):
+            ptrs = (dp * self.count)()
+            for i, r in enumerate(reservoirs):
+                a = _f64(r[key], shape_fn(i))
+                self._keep.append(a)
+                ptrs[i] = _dptr(a)
+            return ptrs
+
+        W = arr("W", lambda i: (self.ns[i], self.ns[i]))
+        w_in = arr("w_in", lambda i: (self.ns[i], self.n_in))
+        m0 = arr("m0", lambda i: (self.ns[i], 3))
+        prms = (sto_params * self.count)(*[r["prm"] for r in reservoirs])
+        nn = (ctypes.c_int64 * self.count)(*self.ns)
+        self.substeps = prms[0].substeps
+        self.dtype = "f64" if prms[0].dtype == STO_F64 else "f32"
+        self.h = ctypes.c_void_p()
+        _check(_lib.sweep_create(self.count, nn, self.n_in, prms, W, w_in, m0, ctypes.byref(self.h)))
+        self._keep = []
+        self.nodes = int(_lib.sweep_nodes(self.h))
+        self.offsets = np.concatenate([[0], np.cumsum(self.ns)])
+
+    def run(self, u, record: bool = True):
+        u = _f64(u).reshape(-1, self.n_in)
+        samples = len(u)
+        states = np.empty(samples * self.nodes * 3) if record else None
+        _check(_lib.sweep_run(self.h, _dptr(u), samples * self.substeps, _dptr(states) if record else None))
+        if not record:
+            return None
+        return [states[samples * 3 * self.offsets[i]: samples * 3 * self.offsets[i + 1]].reshape(samples, n, 3)
+                for i, n in enumerate(self.ns)]
+
+    def run_device(self, u_dev, states_dev=None, stream=None):
+        import torch
+        assert u_dev.is_cuda and u_dev.dtype == torch.float64 and u_dev.is_contiguous()
+        samples = u_dev.numel() // self.n_in
+        if states_dev is not None:
+            assert states_dev.is_cuda and states_dev.is_contiguous() and states_dev.numel() == samples * self.nodes * 3
+        s = (stream or torch.cuda.current_stream()).cuda_stream
+        _check(_lib.sweep_run_device(self.h, ctypes.c_void_p(u_dev.data_ptr()), samples * self.substeps,
+                                     ctypes.c_void_p(states_dev.data_ptr()) if states_dev is not None else None,
+                                     ctypes.c_void_p(s)))
+
+    def get_state(self):
+        m = np.empty((self.nodes, 3))
+        _check(_lib.sweep_get_state(self.h, _dptr(m)))
+        return [m[self.offsets[i]:self.offsets[i + 1]] for i in range(self.count)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.sweep_destroy(self.h)
             self.h = None
 
     def __enter__(self):

@@ -72,7 +72,7 @@ const Tune& tune() {
 }  // namespace sto
 
 struct sto_reservoir {
-    int64_t n = 0, n_in = 0, ld = 0;
+    int64_t n = 0, n_in = 0, ld = 0, streams = 1;
     sto_params prm{};
     int dtype = STO_F64;
     int path = STO_PATH_STREAM;
@@ -171,19 +171,22 @@ sto_status upload_matrix(sto_reservoir* r, void* dst, const double* src, int64_t
     return STO_OK;
 }
 
-// Write an AoS host state into m and the current stage-input buffer.
+// Write an AoS host state ([stream][node][xyz]) into m and, for the
+// single-stream paths, the current stage-input buffer.
 sto_status upload_state(sto_reservoir* r, const double* m_aos) {
-    const int64_t n = r->n, ld = r->ld;
-    std::vector<double> soa((size_t)3 * ld, 0.0);
-    for (int64_t k = 0; k < n; ++k)
-        for (int c = 0; c < 3; ++c) soa[c * ld + k] = m_aos[3 * k + c];
+    const int64_t n = r->n, ld = r->ld, S = r->streams;
+    std::vector<double> soa((size_t)3 * ld * S, 0.0);
+    for (int64_t st = 0; st < S; ++st)
+        for (int64_t k = 0; k < n; ++k)
+            for (int c = 0; c < 3; ++c) soa[(st * 3 + c) * ld + k] = m_aos[(st * n + k) * 3 + c];
+    const size_t count = soa.size();
     if (r->dtype == STO_F64) {
-        HIP_TRY(hipMemcpy(r->m, soa.data(), 3 * ld * 8, hipMemcpyHostToDevice), "state upload");
-        HIP_TRY(hipMemcpy(r->ms[r->cur], soa.data(), 3 * ld * 8, hipMemcpyHostToDevice), "state upload");
+        HIP_TRY(hipMemcpy(r->m, soa.data(), count * 8, hipMemcpyHostToDevice), "state upload");
+        if (S == 1) HIP_TRY(hipMemcpy(r->ms[r->cur], soa.data(), count * 8, hipMemcpyHostToDevice), "state upload");
     } else {
         std::vector<float> f(soa.begin(), soa.end());
-        HIP_TRY(hipMemcpy(r->m, f.data(), 3 * ld * 4, hipMemcpyHostToDevice), "state upload");
-        HIP_TRY(hipMemcpy(r->ms[r->cur], f.data(), 3 * ld * 4, hipMemcpyHostToDevice), "state upload");
+        HIP_TRY(hipMemcpy(r->m, f.data(), count * 4, hipMemcpyHostToDevice), "state upload");
+        if (S == 1) HIP_TRY(hipMemcpy(r->ms[r->cur], f.data(), count * 4, hipMemcpyHostToDevice), "state upload");
     }
     return STO_OK;
 }
@@ -199,7 +202,7 @@ sto_status validate_params(const sto_params* p) {
     if (p->dtype != STO_F64 && p->dtype != STO_F32) return fail(STO_E_INVALID, "unknown dtype %d", p->dtype);
     if (p->coupling != STO_COUPLE_X && p->coupling != STO_COUPLE_XYZ)
         return fail(STO_E_INVALID, "unknown coupling %d", p->coupling);
-    if (p->path < STO_PATH_AUTO || p->path > STO_PATH_STREAM)
+    if (p->path < STO_PATH_AUTO || p->path > STO_PATH_MULTI)
         return fail(STO_E_INVALID, "unknown path %d", p->path);
     if (p->renormalize != 0 && p->renormalize != 1) return fail(STO_E_INVALID, "renormalize must be 0 or 1");
     if (p->reserved != 0) return fail(STO_E_INVALID, "reserved must be 0");
@@ -222,6 +225,9 @@ hipError_t dispatch(sto_reservoir* r, const double* u_dev, int samples, void* st
     switch (r->path) {
         case STO_PATH_SMALL: return sto::run_small<T>(d, k, spec);
         case STO_PATH_RESIDENT: return sto::run_resident<T>(d, k, spec);
+        case STO_PATH_MULTI:
+            if constexpr (sizeof(T) == 4) return sto::run_multi(d, k, spec, (int)r->streams);
+            return hipErrorInvalidValue;
         default: return sto::run_stream<T>(d, k, spec);
     }
 }
@@ -244,7 +250,7 @@ sto_status run_device_impl(sto_reservoir* r, const double* u_dev, int64_t steps,
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     int bad = none, abort_word = 0;
     HIP_TRY(hipMemcpyAsync(&bad, r->bad, sizeof(int), hipMemcpyDeviceToHost, stream), "flag read");
-    if (r->path == STO_PATH_RESIDENT)
+    if (r->path == STO_PATH_RESIDENT || r->path == STO_PATH_MULTI)
         HIP_TRY(hipMemcpyAsync(&abort_word, r->sync + sto::kSyncAbortWord, sizeof(int), hipMemcpyDeviceToHost,
                                stream),
                 "flag read");
@@ -253,6 +259,105 @@ sto_status run_device_impl(sto_reservoir* r, const double* u_dev, int64_t steps,
         return fail(STO_E_DEVICE, "grid barrier timed out: the resident kernel's workgroups were not co-resident");
     if (bad != none)
         return fail(STO_E_NONFINITE, "state not finite after sample %d", bad);
+    return STO_OK;
+}
+
+}  // namespace
+
+struct sto_sweep {
+    int count = 0;
+    int64_t n_in = 0, nodes = 0;
+    int dtype = STO_F64;
+    size_t elem = 8;
+    int substeps = 1, renorm = 0;
+    std::vector<sto::SweepRes> res;
+    void* W = nullptr;
+    void* w_in = nullptr;
+    void* m = nullptr;
+    void* ms[2] = {nullptr, nullptr};
+    void* acc = nullptr;
+    void* res_dev = nullptr;
+    void* coef_dev = nullptr;
+    void* task_dev = nullptr;
+    int tasks = 0;
+    int* bad = nullptr;
+    hipStream_t stream = nullptr;
+    double* u_dev = nullptr;
+    size_t u_cap = 0;
+    void* states_dev = nullptr;
+    size_t states_cap = 0;
+};
+
+namespace {
+
+void sweep_free(sto_sweep* s) {
+    void* ptrs[] = {s->W, s->w_in, s->m, s->ms[0], s->ms[1], s->acc, s->res_dev, s->coef_dev, s->task_dev, s->bad,
+                    s->u_dev, s->states_dev};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+}
+
+// Copy a rows x cols host matrix of doubles into the device at dst (element
+// pitch ld, the handle's element type).
+sto_status sweep_upload(int dtype, void* dst, const double* src, int64_t rows, int64_t cols, int64_t ld) {
+    if (dtype == STO_F64) {
+        HIP_TRY(hipMemcpy2D(dst, ld * 8, src, cols * 8, cols * 8, rows, hipMemcpyHostToDevice), "sweep upload");
+        return STO_OK;
+    }
+    std::vector<float> tmp((size_t)rows * cols);
+    for (size_t i = 0; i < tmp.size(); ++i) tmp[i] = (float)src[i];
+    HIP_TRY(hipMemcpy2D(dst, ld * 4, tmp.data(), cols * 4, cols * 4, rows, hipMemcpyHostToDevice), "sweep upload");
+    return STO_OK;
+}
+
+template <typename T>
+sto::SweepDev<T> sweep_dev(const sto_sweep* s, void* states, int64_t samples) {
+    sto::SweepDev<T> d;
+    d.W = static_cast<const T*>(s->W);
+    d.w_in = static_cast<const T*>(s->w_in);
+    d.m = static_cast<T*>(s->m);
+    d.ms[0] = static_cast<T*>(s->ms[0]);
+    d.ms[1] = static_cast<T*>(s->ms[1]);
+    d.acc = static_cast<T*>(s->acc);
+    d.states = static_cast<T*>(states);
+    d.bad = s->bad;
+    d.res = static_cast<const sto::SweepRes*>(s->res_dev);
+    d.coef = static_cast<const sto::Coef<T>*>(s->coef_dev);
+    d.task = static_cast<const int2*>(s->task_dev);
+    d.tasks = s->tasks;
+    d.n_in = (int)s->n_in;
+    d.rec_samples = samples;
+    return d;
+}
+
+sto_status sweep_run_impl(sto_sweep* s, const double* u_dev, int64_t steps, void* states_dev, hipStream_t stream) {
+    if (!s) return fail(STO_E_INVALID, "handle is NULL");
+    if (steps < 0 || steps % s->substeps != 0)
+        return fail(STO_E_INVALID, "steps (%lld) must be a non-negative multiple of substeps (%d)", (long long)steps,
+                    s->substeps);
+    const int64_t samples = steps / s->substeps;
+    if (samples == 0) return STO_OK;
+    if (samples > INT_MAX) return fail(STO_E_INVALID, "too many samples");
+    if (!u_dev) return fail(STO_E_INVALID, "u is NULL");
+    const int none = INT_MAX;
+    HIP_TRY(hipMemcpyAsync(s->bad, &none, sizeof(int), hipMemcpyHostToDevice, stream), "flag reset");
+    sto::RunSpec spec;
+    spec.u = u_dev;
+    spec.states = states_dev;
+    spec.samples = (int)samples;
+    spec.substeps = s->substeps;
+    spec.cur = 0;
+    spec.renorm = s->renorm;
+    spec.xyz = 0;
+    spec.stream = stream;
+    hipError_t e = s->dtype == STO_F64 ? sto::run_sweep<double>(sweep_dev<double>(s, states_dev, samples), spec)
+                                       : sto::run_sweep<float>(sweep_dev<float>(s, states_dev, samples), spec);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    int bad = none;
+    HIP_TRY(hipMemcpyAsync(&bad, s->bad, sizeof(int), hipMemcpyDeviceToHost, stream), "flag read");
+    HIP_TRY(hipStreamSynchronize(stream), "run");
+    if (bad != none) return fail(STO_E_NONFINITE, "state not finite after sample %d", bad);
     return STO_OK;
 }
 
@@ -288,16 +393,24 @@ sto_status sto_read_bandwidth(int64_t bytes, int32_t reps, double* gbs_out) {
 
 sto_status reservoir_create(int64_t n, int64_t n_in, const sto_params* prm, const double* W,
                             const double* w_in, const double* m0, sto_reservoir** out) {
+    return reservoir_create_streams(n, n_in, 1, prm, W, w_in, m0, out);
+}
+
+int64_t reservoir_streams(const sto_reservoir* r) { return r ? r->streams : -1; }
+
+sto_status reservoir_create_streams(int64_t n, int64_t n_in, int64_t streams, const sto_params* prm,
+                                    const double* W, const double* w_in, const double* m0, sto_reservoir** out) {
     if (!out) return fail(STO_E_INVALID, "out is NULL");
     *out = nullptr;
     if (n < 1 || n > (int64_t)INT_MAX / 4) return fail(STO_E_INVALID, "n out of range: %lld", (long long)n);
+    if (streams < 1 || streams > 65536) return fail(STO_E_INVALID, "streams out of range: %lld", (long long)streams);
     if (n_in < 1 || n_in > 65536) return fail(STO_E_INVALID, "n_in out of range: %lld", (long long)n_in);
     sto_status st = validate_params(prm);
     if (st != STO_OK) return st;
     if (!W || !w_in || !m0) return fail(STO_E_INVALID, "W, w_in and m0 must be non-NULL");
-    if (!finite_all(W, n * n) || !finite_all(w_in, n * n_in) || !finite_all(m0, 3 * n))
+    if (!finite_all(W, n * n) || !finite_all(w_in, n * n_in) || !finite_all(m0, 3 * n * streams))
         return fail(STO_E_NONFINITE, "non-finite input array");
-    for (int64_t k = 0; k < n; ++k) {
+    for (int64_t k = 0; k < n * streams; ++k) {
         const double* v = m0 + 3 * k;
         double nn = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
         if (std::fabs(nn - 1.0) > 1e-12) return fail(STO_E_INVALID, "|m0[%lld]| = %.17g is not 1", (long long)k, nn);
@@ -311,13 +424,26 @@ sto_status reservoir_create(int64_t n, int64_t n_in, const sto_params* prm, cons
     r->dtype = prm->dtype;
     r->elem = prm->dtype == STO_F64 ? 8 : 4;
     r->ld = round_up(n, 64);
+    r->streams = streams;
     const int xyz = prm->coupling == STO_COUPLE_XYZ;
 
     // path selection
     int path = prm->path;
     int grid = 0;
     const int small_n = sto::small_max_n((int)r->elem, xyz);
-    if (path == STO_PATH_AUTO) {
+    if (streams > 1 || path == STO_PATH_MULTI) {
+        const char* why = nullptr;
+        if (prm->dtype != STO_F32) why = "the multi-stream path computes in FP32";
+        else if (xyz) why = "the multi-stream path couples m^x only";
+        else if (path != STO_PATH_AUTO && path != STO_PATH_MULTI) why = "streams > 1 runs only the multi-stream path";
+        else if (!sto::multi_fits((int)n, (int)streams, nullptr, nullptr))
+            why = "n x streams does not fit the multi-stream kernel (n <= 1024, all tiles co-resident)";
+        if (why) {
+            delete r;
+            return fail(STO_E_UNSUPPORTED, "%s", why);
+        }
+        path = STO_PATH_MULTI;
+    } else if (path == STO_PATH_AUTO) {
         if (n <= small_n) path = STO_PATH_SMALL;
         else if (sto::resident_fits((int)n, (int)r->elem, xyz, &grid)) path = STO_PATH_RESIDENT;
         else path = STO_PATH_STREAM;
@@ -345,12 +471,14 @@ sto_status reservoir_create(int64_t n, int64_t n_in, const sto_params* prm, cons
     const size_t vec = (size_t)3 * r->ld * r->elem;
     ALLOC(r->W, (size_t)n * r->ld * r->elem);
     ALLOC(r->w_in, (size_t)n * n_in * r->elem);
-    ALLOC(r->m, vec);
+    ALLOC(r->m, vec * streams);
     ALLOC(r->ms[0], vec);
     ALLOC(r->ms[1], vec);
     ALLOC(r->acc, vec);
     if (path == STO_PATH_RESIDENT) {
         ALLOC(r->xchg, 3 * vec);
+    } else if (path == STO_PATH_MULTI) {
+        ALLOC(r->xchg, 3 * (size_t)streams * r->ld * r->elem);
     }
     ALLOC(r->bad, sizeof(int));
     ALLOC(r->sync, 256);
@@ -391,8 +519,8 @@ sto_status reservoir_run(sto_reservoir* r, const double* u, int64_t steps, doubl
     const int64_t samples = steps / r->prm.substeps;
     if (samples == 0) return STO_OK;
     if (!u) return fail(STO_E_INVALID, "u is NULL");
-    if (!finite_all(u, samples * r->n_in)) return fail(STO_E_NONFINITE, "non-finite input u");
-    const size_t ub = (size_t)samples * r->n_in * sizeof(double);
+    if (!finite_all(u, samples * r->streams * r->n_in)) return fail(STO_E_NONFINITE, "non-finite input u");
+    const size_t ub = (size_t)samples * r->streams * r->n_in * sizeof(double);
     if (ub > r->u_cap) {
         if (r->u_dev) (void)hipFree(r->u_dev);
         r->u_dev = nullptr;
@@ -400,7 +528,7 @@ sto_status reservoir_run(sto_reservoir* r, const double* u, int64_t steps, doubl
         HIP_TRY(hipMalloc(&r->u_dev, ub), "hipMalloc u");
         r->u_cap = ub;
     }
-    const size_t sb = (size_t)samples * r->n * 3 * r->elem;
+    const size_t sb = (size_t)samples * r->streams * r->n * 3 * r->elem;
     if (states && sb > r->states_cap) {
         if (r->states_dev) (void)hipFree(r->states_dev);
         r->states_dev = nullptr;
@@ -415,7 +543,7 @@ sto_status reservoir_run(sto_reservoir* r, const double* u, int64_t steps, doubl
         if (r->dtype == STO_F64) {
             HIP_TRY(hipMemcpy(states, r->states_dev, sb, hipMemcpyDeviceToHost), "states download");
         } else {
-            std::vector<float> f((size_t)samples * r->n * 3);
+            std::vector<float> f((size_t)samples * r->streams * r->n * 3);
             HIP_TRY(hipMemcpy(f.data(), r->states_dev, sb, hipMemcpyDeviceToHost), "states download");
             for (size_t i = 0; i < f.size(); ++i) states[i] = f[i];
         }
@@ -426,24 +554,25 @@ sto_status reservoir_run(sto_reservoir* r, const double* u, int64_t steps, doubl
 
 sto_status reservoir_get_state(const sto_reservoir* r, double* m) {
     if (!r || !m) return fail(STO_E_INVALID, "NULL argument");
-    const int64_t n = r->n, ld = r->ld;
+    const int64_t n = r->n, ld = r->ld, S = r->streams;
     HIP_TRY(hipStreamSynchronize(r->stream), "sync");
-    std::vector<double> soa((size_t)3 * ld);
+    std::vector<double> soa((size_t)3 * ld * S);
     if (r->dtype == STO_F64) {
-        HIP_TRY(hipMemcpy(soa.data(), r->m, 3 * ld * 8, hipMemcpyDeviceToHost), "state download");
+        HIP_TRY(hipMemcpy(soa.data(), r->m, soa.size() * 8, hipMemcpyDeviceToHost), "state download");
     } else {
-        std::vector<float> f((size_t)3 * ld);
-        HIP_TRY(hipMemcpy(f.data(), r->m, 3 * ld * 4, hipMemcpyDeviceToHost), "state download");
+        std::vector<float> f(soa.size());
+        HIP_TRY(hipMemcpy(f.data(), r->m, f.size() * 4, hipMemcpyDeviceToHost), "state download");
         for (size_t i = 0; i < f.size(); ++i) soa[i] = f[i];
     }
-    for (int64_t k = 0; k < n; ++k)
-        for (int c = 0; c < 3; ++c) m[3 * k + c] = soa[c * ld + k];
+    for (int64_t st = 0; st < S; ++st)
+        for (int64_t k = 0; k < n; ++k)
+            for (int c = 0; c < 3; ++c) m[(st * n + k) * 3 + c] = soa[(st * 3 + c) * ld + k];
     return STO_OK;
 }
 
 sto_status reservoir_set_state(sto_reservoir* r, const double* m) {
     if (!r || !m) return fail(STO_E_INVALID, "NULL argument");
-    if (!finite_all(m, 3 * r->n)) return fail(STO_E_NONFINITE, "non-finite state");
+    if (!finite_all(m, 3 * r->n * r->streams)) return fail(STO_E_NONFINITE, "non-finite state");
     HIP_TRY(hipStreamSynchronize(r->stream), "sync");
     return upload_state(r, m);
 }
@@ -501,6 +630,191 @@ sto_status readout_fit_device(const void* states_dev, int32_t dtype, int64_t T, 
     int rc = sto::readout_solve(rec, dtype == STO_F32, (int)rows, (int)n, features, y, lambda,
                                 static_cast<double*>(w_out_dev), nmse_out, static_cast<hipStream_t>(hip_stream), &err);
     return rc == 0 ? STO_OK : readout_status(rc, err);
+}
+
+
+sto_status sweep_create(int32_t count, const int64_t* n, int64_t n_in, const sto_params* prm, const double* const* W,
+                        const double* const* w_in, const double* const* m0, sto_sweep** out) {
+    if (!out) return fail(STO_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || !n || !prm || !W || !w_in || !m0) return fail(STO_E_INVALID, "count >= 1 and non-NULL arrays");
+    if (n_in < 1 || n_in > 65536) return fail(STO_E_INVALID, "n_in out of range");
+    for (int r = 0; r < count; ++r) {
+        sto_status st = validate_params(prm + r);
+        if (st != STO_OK) return st;
+        if (n[r] < 1 || n[r] > 65536) return fail(STO_E_INVALID, "n[%d] out of range", r);
+        if (prm[r].dtype != prm[0].dtype || prm[r].substeps != prm[0].substeps ||
+            prm[r].renormalize != prm[0].renormalize || prm[r].coupling != prm[0].coupling)
+            return fail(STO_E_INVALID, "dtype, substeps, renormalize and coupling must agree (reservoir %d)", r);
+        if (prm[r].coupling != STO_COUPLE_X) return fail(STO_E_UNSUPPORTED, "sweeps couple m^x only");
+        if (!W[r] || !w_in[r] || !m0[r]) return fail(STO_E_INVALID, "NULL array of reservoir %d", r);
+        if (!finite_all(W[r], n[r] * n[r]) || !finite_all(w_in[r], n[r] * n_in) || !finite_all(m0[r], 3 * n[r]))
+            return fail(STO_E_NONFINITE, "non-finite input array (reservoir %d)", r);
+        for (int64_t k = 0; k < n[r]; ++k) {
+            const double* v = m0[r] + 3 * k;
+            if (std::fabs(std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) - 1.0) > 1e-12)
+                return fail(STO_E_INVALID, "|m0| != 1 (reservoir %d, node %lld)", r, (long long)k);
+        }
+    }
+    sto_sweep* s = new (std::nothrow) sto_sweep();
+    if (!s) return fail(STO_E_NOMEM, "handle");
+    s->count = count;
+    s->n_in = n_in;
+    s->dtype = prm[0].dtype;
+    s->elem = s->dtype == STO_F64 ? 8 : 4;
+    s->substeps = prm[0].substeps;
+    s->renorm = prm[0].renormalize;
+    int64_t woff = 0, soff = 0, winoff = 0, noff = 0;
+    std::vector<int2> tasks;
+    const int R = sto::sweep_rows_per_task((int)s->elem);
+    for (int r = 0; r < count; ++r) {
+        sto::SweepRes x;
+        x.n = (int)n[r];
+        x.pad = 0;
+        x.ld = round_up(n[r], 64);
+        x.woff = woff;
+        x.soff = soff;
+        x.winoff = winoff;
+        x.noff = noff;
+        s->res.push_back(x);
+        woff += n[r] * x.ld;
+        soff += 3 * x.ld;
+        winoff += n[r] * n_in;
+        noff += n[r];
+        for (int row = 0; row < n[r]; row += R) tasks.push_back(make_int2(r, row));
+    }
+    s->nodes = noff;
+    s->tasks = (int)tasks.size();
+    auto cleanup = [&](sto_status st) {
+        sweep_free(s);
+        delete s;
+        return st;
+    };
+    hipError_t e;
+#define SALLOC(ptr, bytes)                                         \
+    e = hipMalloc(&(ptr), (bytes));                                \
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipMalloc")); \
+    e = hipMemset((ptr), 0, (bytes));                              \
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipMemset"));
+    SALLOC(s->W, (size_t)woff * s->elem);
+    SALLOC(s->w_in, (size_t)winoff * s->elem);
+    SALLOC(s->m, (size_t)soff * s->elem);
+    SALLOC(s->ms[0], (size_t)soff * s->elem);
+    SALLOC(s->ms[1], (size_t)soff * s->elem);
+    SALLOC(s->acc, (size_t)soff * s->elem);
+    SALLOC(s->res_dev, sizeof(sto::SweepRes) * count);
+    SALLOC(s->coef_dev, (s->dtype == STO_F64 ? sizeof(sto::Coef<double>) : sizeof(sto::Coef<float>)) * count);
+    SALLOC(s->task_dev, sizeof(int2) * tasks.size());
+    SALLOC(s->bad, sizeof(int));
+#undef SALLOC
+    e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipStreamCreate"));
+    for (int r = 0; r < count; ++r) {
+        const sto::SweepRes& x = s->res[r];
+        sto_status st = sweep_upload(s->dtype, static_cast<char*>(s->W) + x.woff * s->elem, W[r], n[r], n[r], x.ld);
+        if (st == STO_OK)
+            st = sweep_upload(s->dtype, static_cast<char*>(s->w_in) + x.winoff * s->elem, w_in[r], n[r], n_in, n_in);
+        if (st == STO_OK) {
+            // state: AoS -> SoA (x, y, z blocks of ld), into m and ms[0]
+            std::vector<double> soa((size_t)3 * x.ld, 0.0);
+            for (int64_t k = 0; k < n[r]; ++k)
+                for (int c = 0; c < 3; ++c) soa[c * x.ld + k] = m0[r][3 * k + c];
+            for (void* dst : {s->m, s->ms[0]})
+                if (st == STO_OK)
+                    st = sweep_upload(s->dtype, static_cast<char*>(dst) + x.soff * s->elem, soa.data(), 1, 3 * x.ld,
+                                      3 * x.ld);
+        }
+        if (st != STO_OK) return cleanup(st);
+    }
+    if (s->dtype == STO_F64) {
+        std::vector<sto::Coef<double>> c;
+        for (int r = 0; r < count; ++r) c.push_back(make_coef<double>(prm[r]));
+        e = hipMemcpy(s->coef_dev, c.data(), sizeof(c[0]) * count, hipMemcpyHostToDevice);
+    } else {
+        std::vector<sto::Coef<float>> c;
+        for (int r = 0; r < count; ++r) c.push_back(make_coef<float>(prm[r]));
+        e = hipMemcpy(s->coef_dev, c.data(), sizeof(c[0]) * count, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipMemcpy(s->res_dev, s->res.data(), sizeof(sto::SweepRes) * count, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->task_dev, tasks.data(), sizeof(int2) * tasks.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "sweep upload"));
+    *out = s;
+    return STO_OK;
+}
+
+int64_t sweep_nodes(const sto_sweep* s) { return s ? s->nodes : -1; }
+
+void sweep_destroy(sto_sweep* s) {
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    sweep_free(s);
+    delete s;
+}
+
+sto_status sweep_run_device(sto_sweep* s, const void* u_dev, int64_t steps, void* states_dev, void* hip_stream) {
+    return sweep_run_impl(s, static_cast<const double*>(u_dev), steps, states_dev, static_cast<hipStream_t>(hip_stream));
+}
+
+sto_status sweep_run(sto_sweep* s, const double* u, int64_t steps, double* states) {
+    if (!s) return fail(STO_E_INVALID, "handle is NULL");
+    if (steps < 0 || steps % s->substeps != 0)
+        return fail(STO_E_INVALID, "steps (%lld) must be a non-negative multiple of substeps (%d)", (long long)steps,
+                    s->substeps);
+    const int64_t samples = steps / s->substeps;
+    if (samples == 0) return STO_OK;
+    if (!u) return fail(STO_E_INVALID, "u is NULL");
+    if (!finite_all(u, samples * s->n_in)) return fail(STO_E_NONFINITE, "non-finite input u");
+    const size_t ub = (size_t)samples * s->n_in * 8;
+    if (ub > s->u_cap) {
+        if (s->u_dev) (void)hipFree(s->u_dev);
+        s->u_dev = nullptr;
+        s->u_cap = 0;
+        HIP_TRY(hipMalloc(&s->u_dev, ub), "hipMalloc u");
+        s->u_cap = ub;
+    }
+    const size_t sb = (size_t)samples * s->nodes * 3 * s->elem;
+    if (states && sb > s->states_cap) {
+        if (s->states_dev) (void)hipFree(s->states_dev);
+        s->states_dev = nullptr;
+        s->states_cap = 0;
+        HIP_TRY(hipMalloc(&s->states_dev, sb), "hipMalloc states");
+        s->states_cap = sb;
+    }
+    HIP_TRY(hipMemcpyAsync(s->u_dev, u, ub, hipMemcpyHostToDevice, s->stream), "u upload");
+    sto_status st = sweep_run_impl(s, s->u_dev, steps, states ? s->states_dev : nullptr, s->stream);
+    if (states && (st == STO_OK || st == STO_E_NONFINITE)) {
+        std::string msg = g_err;
+        if (s->dtype == STO_F64) {
+            HIP_TRY(hipMemcpy(states, s->states_dev, sb, hipMemcpyDeviceToHost), "states download");
+        } else {
+            std::vector<float> f((size_t)samples * s->nodes * 3);
+            HIP_TRY(hipMemcpy(f.data(), s->states_dev, sb, hipMemcpyDeviceToHost), "states download");
+            for (size_t i = 0; i < f.size(); ++i) states[i] = f[i];
+        }
+        g_err = msg;
+    }
+    return st;
+}
+
+sto_status sweep_get_state(const sto_sweep* s, double* m) {
+    if (!s || !m) return fail(STO_E_INVALID, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(s->stream), "sync");
+    for (int r = 0; r < s->count; ++r) {
+        const sto::SweepRes& x = s->res[r];
+        std::vector<double> soa((size_t)3 * x.ld);
+        if (s->dtype == STO_F64) {
+            HIP_TRY(hipMemcpy(soa.data(), static_cast<char*>(s->m) + x.soff * 8, soa.size() * 8, hipMemcpyDeviceToHost),
+                    "state download");
+        } else {
+            std::vector<float> f(soa.size());
+            HIP_TRY(hipMemcpy(f.data(), static_cast<char*>(s->m) + x.soff * 4, f.size() * 4, hipMemcpyDeviceToHost),
+                    "state download");
+            for (size_t i = 0; i < f.size(); ++i) soa[i] = f[i];
+        }
+        for (int64_t k = 0; k < x.n; ++k)
+            for (int c = 0; c < 3; ++c) m[(x.noff + k) * 3 + c] = soa[c * x.ld + k];
+    }
+    return STO_OK;
 }
 
 }  // extern "C"

@@ -12,6 +12,7 @@ namespace sto {
 //   W      n rows x ld columns, row-major; columns n..ld-1 are zero
 //   w_in   n x n_in, row-major
 //   m      current state, SoA: m[c*ld + k] for component c of node k
+//          (streams > 1: m[(s*3 + c)*ld + k] for stream s)
 //   ms[2]  RK4 stage inputs (ping-pong), same layout as m; entries k >= n
 //          stay zero, so the padded columns of W meet zeros
 //   acc    RK4 accumulator k1 + 2k2 + 2k3, same layout
@@ -22,11 +23,39 @@ struct DevState {
     T* m;
     T* ms[2];
     T* acc;
-    T* xchg;         // resident path: 3 rotating stage-input buffers of 3 x ld
+    T* xchg;         // resident/multi paths: 3 rotating stage-input buffers
     int* bad;        // first sample index whose state is not finite (INT_MAX: none)
     int* sync;       // grid-barrier words (cooperative kernels)
     int n, n_in;
     int64_t ld;
+};
+
+// SWEEP path: per-reservoir offsets into the concatenated device arrays.
+struct SweepRes {
+    int n;             // nodes
+    int pad;
+    int64_t ld;        // row pitch of W and of the state arrays (n rounded up to 64)
+    int64_t woff;      // element offset of W (n x ld)
+    int64_t soff;      // element offset of m, ms[], acc (3 x ld each)
+    int64_t winoff;    // element offset of w_in (n x n_in)
+    int64_t noff;      // nodes of the reservoirs before this one
+};
+
+template <typename T>
+struct SweepDev {
+    const T* W;
+    const T* w_in;
+    T* m;
+    T* ms[2];
+    T* acc;
+    T* states;         // records [reservoir][sample][node][3], or nullptr
+    int* bad;
+    const SweepRes* res;
+    const Coef<T>* coef;
+    const int2* task;  // (reservoir, first row) of every wave task
+    int tasks;
+    int n_in;
+    int64_t rec_samples;   // samples of the current run (record layout)
 };
 
 struct RunSpec {
@@ -55,6 +84,14 @@ const Tune& tune();
 template <typename T> hipError_t run_stream(const DevState<T>& d, const Coef<T>& k, const RunSpec& r);
 template <typename T> hipError_t run_small(const DevState<T>& d, const Coef<T>& k, const RunSpec& r);
 template <typename T> hipError_t run_resident(const DevState<T>& d, const Coef<T>& k, const RunSpec& r);
+
+// MULTI path (S streams, FP32 MFMA): whether n x streams fits and runs.
+bool multi_fits(int n, int streams, int* grid_x, int* grid_y);
+hipError_t run_multi(const DevState<float>& d, const Coef<float>& k, const RunSpec& r, int streams);
+
+// SWEEP path launcher (one launch per RK4 stage over every reservoir).
+template <typename T> hipError_t run_sweep(const SweepDev<T>& d, const RunSpec& r);
+int sweep_rows_per_task(int elem_bytes);
 
 // Largest n the single-workgroup kernel holds (W in LDS).
 int small_max_n(int elem_bytes, int xyz);

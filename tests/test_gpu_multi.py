@@ -1,0 +1,113 @@
+"""GPU parity of the multi-stream path (S input streams share one W; the
+coupling of all streams is one FP32 MFMA product per stage) against the
+CPU oracle run once per stream."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from common import lib_params, oracle_params, random_case
+from oracle import sto
+from workloads import STREAMS, WORKLOADS, make_stream_arrays
+
+pytestmark = pytest.mark.gpu
+F32_TOL = 1e-5
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def stx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2312_01121_amd
+    return paper_2312_01121_amd
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def stream_case(n, streams, seed, samples):
+    w, w_in, m0, _ = random_case(n, seed=seed, samples=1)
+    rng = np.random.default_rng(seed + 100)
+    u = rng.uniform(-1, 1, (samples, streams, 1))
+    return w, w_in, m0, u
+
+
+@pytest.mark.parametrize("n,streams", [(16, 2), (100, 5), (257, 17), (512, 64)])
+def test_multi_one_step_matches_oracle(stx, n, streams):
+    """One RK4 step per stream from the same FP32-representable state."""
+    w, w_in, m0, u = stream_case(n, streams, seed=n, samples=1)
+    prm = oracle_params(a_cp=0.3, substeps=1)
+    say("multi one step", n, streams)
+    m0s = np.broadcast_to(m0, (streams, n, 3)).copy()
+    with stx.Reservoir(w, w_in, m0s, lib_params(prm, dtype="f32"), streams=streams) as r:
+        assert r.path == "multi"
+        rec = r.run(u)
+    worst = 0.0
+    for s in (range(streams) if streams <= 8 else (0, 1, streams // 2, streams - 1)):
+        rec_o, _ = sto.run(f32(w), f32(w_in), f32(m0), u[:, s], prm)
+        worst = max(worst, float(np.max(np.abs(rec[:, s] - rec_o))))
+    say("  max diff", worst)
+    assert worst <= F32_TOL
+
+
+def test_multi_streams64_lyapunov_horizon(stx):
+    """The 64-stream, 512-node workload over ~one Lyapunov time (8 samples =
+    160 steps), checked per stream against the FP64 oracle."""
+    wl = WORKLOADS["streams64"]
+    S = STREAMS["streams64"]
+    a = make_stream_arrays(wl, S, samples=8)
+    prm = oracle_params(a_cp=wl.a_cp, a_in=wl.a_in)
+    m0s = np.broadcast_to(a["m0"], (S, wl.n, 3)).copy()
+    say("streams64 horizon")
+    with stx.Reservoir(a["W"], a["w_in"], m0s, lib_params(prm, dtype="f32"), streams=S) as r:
+        rec = r.run(a["u"])
+    worst = 0.0
+    for s in (0, 7, 31, 63):
+        rec_o, _ = sto.run(a["W"], a["w_in"], a["m0"], a["u"][:, s], prm)
+        worst = max(worst, float(np.max(np.abs(rec[:, s] - rec_o))))
+    say("  max diff", worst)
+    assert worst <= F32_TOL
+
+
+def test_multi_continuation_and_state(stx):
+    n, S = 70, 9
+    w, w_in, m0, u = stream_case(n, S, seed=3, samples=6)
+    prm = oracle_params(a_cp=0.3)
+    rng = np.random.default_rng(4)
+    m0s = np.empty((S, n, 3))
+    for s in range(S):
+        v = rng.standard_normal((n, 3)) * 0.05
+        v[:, 2] += 1.0
+        m0s[s] = v / np.linalg.norm(v, axis=1, keepdims=True)
+    lp = lib_params(prm, dtype="f32")
+    with stx.Reservoir(w, w_in, m0s, lp, streams=S) as r:
+        whole = r.run(u)
+        fin = r.get_state()
+    with stx.Reservoir(w, w_in, m0s, lp, streams=S) as r:
+        a = r.run(u[:2])
+        b = r.run(u[2:])
+        assert np.array_equal(r.get_state(), fin)
+        r.set_state(m0s)
+        again = r.run(u)
+    assert np.array_equal(np.concatenate([a, b]), whole)
+    assert np.array_equal(again, whole)
+    # each stream evolves on its own: stream 3 alone (FP32, single-stream path)
+    with stx.Reservoir(w, w_in, m0s[3], lp) as r1:
+        one = r1.run(u[:, 3])
+    assert np.max(np.abs(one - whole[:, 3])) <= 1e-4
+
+
+def test_multi_rejects_unsupported(stx):
+    w, w_in, m0, _ = random_case(20, seed=5, samples=1)
+    m0s = np.broadcast_to(m0, (3, 20, 3)).copy()
+    for kw in (dict(dtype="f64"), dict(dtype="f32", coupling="xyz")):
+        prm = oracle_params(coupling=kw.get("coupling", "x"))
+        with pytest.raises(stx.StoError) as ei:
+            stx.Reservoir(w, w_in, m0s, lib_params(prm, dtype=kw["dtype"]), streams=3)
+        assert ei.value.status == stx.STO_E_UNSUPPORTED

@@ -1,0 +1,111 @@
+"""GPU parity of the parameter-sweep path (many reservoirs of uneven size and
+their own constants, one shared input, one launch per RK4 stage over all of
+them) against the CPU oracle run once per reservoir."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from common import lib_params
+from oracle import constants, sto
+from workloads import SWEEPS, make_sweep_arrays
+
+pytestmark = pytest.mark.gpu
+F64_TOL = 1e-10
+F32_TOL = 1e-5
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def stx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2312_01121_amd
+    return paper_2312_01121_amd
+
+
+def oracle_prm(r, substeps=20):
+    return constants.dimensionless(a_cp=r["a_cp"], a_in=r["a_in"], current_scale=r["current_scale"],
+                                   field_scale=r["field_scale"], substeps=substeps)
+
+
+def small_sweep(sizes, seed=7):
+    rng = np.random.default_rng(seed)
+    res = []
+    for n in sizes:
+        w = rng.standard_normal((n, n)) / np.sqrt(n)
+        np.fill_diagonal(w, 0.0)
+        v = rng.standard_normal((n, 3)) * 0.05
+        v[:, 2] += 1.0
+        res.append({"n": n, "W": w, "w_in": rng.uniform(-1, 1, (n, 1)),
+                    "m0": v / np.linalg.norm(v, axis=1, keepdims=True),
+                    "current_scale": rng.uniform(0.5, 1.5), "field_scale": rng.uniform(0.5, 1.5),
+                    "a_cp": rng.uniform(0.01, 0.5), "a_in": rng.uniform(0.1, 2.0)})
+    return res
+
+
+SIZES = [1, 5, 33, 64, 65, 100, 129, 200, 257, 300, 513]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sweep_matches_oracle(stx, dtype):
+    res = small_sweep(SIZES)
+    u = np.random.default_rng(8).uniform(-1, 1, (6, 1))
+    substeps = 20 if dtype == "f64" else 1
+    samples = 6 if dtype == "f64" else 1
+    say("sweep", dtype, SIZES)
+    for r in res:
+        r["prm"] = lib_params(oracle_prm(r, substeps), dtype=dtype)
+    with stx.Sweep(res) as sw:
+        recs = sw.run(u[:samples])
+    worst = 0.0
+    f32 = (lambda x: np.asarray(x, dtype=np.float32).astype(np.float64)) if dtype == "f32" else (lambda x: x)
+    for r, rec in zip(res, recs):
+        rec_o, _ = sto.run(f32(r["W"]), f32(r["w_in"]), f32(r["m0"]), u[:samples], oracle_prm(r, substeps))
+        worst = max(worst, float(np.max(np.abs(rec - rec_o))))
+    say("  max diff", worst)
+    assert worst <= (F64_TOL if dtype == "f64" else F32_TOL)
+
+
+def test_sweep_equals_single_runs_and_continues(stx):
+    res = small_sweep([17, 90, 301], seed=9)
+    u = np.random.default_rng(10).uniform(-1, 1, (5, 1))
+    for r in res:
+        r["prm"] = lib_params(oracle_prm(r), dtype="f64")
+    with stx.Sweep(res) as sw:
+        whole = sw.run(u)
+        fin = sw.get_state()
+    with stx.Sweep(res) as sw:
+        a = sw.run(u[:2])
+        b = sw.run(u[2:])
+        assert all(np.array_equal(x, y) for x, y in zip(sw.get_state(), fin))
+    for r, wr, ar, br in zip(res, whole, a, b):
+        assert np.array_equal(np.concatenate([ar, br]), wr)
+        with stx.Reservoir(r["W"], r["w_in"], r["m0"], r["prm"]) as one:
+            assert np.array_equal(one.run(u), wr)
+
+
+def test_sweep256_prefix_matches_oracle(stx):
+    """The 256-reservoir sweep (N from 33 to 2042, FP32): one sample (20
+    steps, well inside the Lyapunov time) checked against the FP64 oracle for
+    a spread of reservoirs."""
+    sw_def = SWEEPS["sweep256"]
+    a = make_sweep_arrays(sw_def, samples=1)
+    res = a["reservoirs"]
+    for r in res:
+        r["prm"] = lib_params(oracle_prm(r), dtype="f32")
+    say("sweep256 prefix")
+    with stx.Sweep(res) as sw:
+        recs = sw.run(a["u"])
+    order = np.argsort([r["n"] for r in res])
+    worst = 0.0
+    for i in (order[0], order[64], order[128], order[192], order[-1]):
+        r = res[i]
+        rec_o, _ = sto.run(r["W"], r["w_in"], r["m0"], a["u"], oracle_prm(r))
+        worst = max(worst, float(np.max(np.abs(recs[i] - rec_o))))
+    say("  max diff", worst)
+    assert worst <= F32_TOL

@@ -9,6 +9,9 @@ inputs.
 """
 
 from .inputs import (  # noqa: F401
+    STREAMS,
+    SWEEPS,
+    Sweep,
     Workload,
     WORKLOADS,
     draw_coupling,
@@ -16,6 +19,8 @@ from .inputs import (  # noqa: F401
     draw_input_weights,
     draw_inputs,
     draw_target,
+    make_stream_arrays,
+    make_sweep_arrays,
     make_workload_arrays,
     seed_streams,
 )

@@ -63,12 +63,15 @@ class Workload:
         return dataclasses.replace(self, samples=samples)
 
 
-# The sized workloads: 16, 1,000 and 10,000 coupled oscillators.
+# The sized workloads: 16, 1,000 and 10,000 coupled oscillators, and 64
+# input streams driving one 512-node reservoir.
 WORKLOADS: Dict[str, Workload] = {
     "sto16": Workload("sto16", n=16, samples=2000, dtypes=("f64",)),
     "sto1k": Workload("sto1k", n=1000, samples=10000, dtypes=("f32", "f64")),
     "sto10k": Workload("sto10k", n=10000, samples=1000, dtypes=("f32", "f64")),
+    "streams64": Workload("streams64", n=512, samples=1000, dtypes=("f32",)),
 }
+STREAMS: Dict[str, int] = {"streams64": 64}
 
 
 def seed_streams(seed: int, key: Optional[int] = None):
@@ -160,3 +163,81 @@ def make_workload_arrays(wl: Workload, samples: Optional[int] = None,
         u = np.ascontiguousarray(u[:samples])
     y = draw_target(u)
     return {"W": w, "w_in": w_in, "m0": m0, "u": u, "y": y}
+
+
+def make_stream_arrays(wl: Workload, streams: int, samples: Optional[int] = None) -> Dict[str, np.ndarray]:
+    """One reservoir (W, w_in, m0 from ``wl.seed``) driven by ``streams``
+    independent input series: stream s draws u from SeedSequence([seed, 1000 + s]).
+
+    u has shape (samples, streams, n_in) and y (samples, streams); every
+    stream starts from the same m0.
+    """
+    base = make_workload_arrays(wl, samples=1)
+    t = wl.samples if samples is None else samples
+    us = []
+    for st in range(streams):
+        g_u = seed_streams(wl.seed, 1000 + st)[3]
+        us.append(draw_inputs(g_u, wl.samples, wl.n_in)[:t])
+    u = np.ascontiguousarray(np.stack(us, axis=1))
+    y = np.stack([draw_target(u[:, st]) for st in range(streams)], axis=1)
+    return {"W": base["W"], "w_in": base["w_in"], "m0": base["m0"], "u": u, "y": y}
+
+
+@dataclasses.dataclass(frozen=True)
+class Sweep:
+    """A parameter sweep: ``count`` reservoirs of log-uniform size in
+    [n_lo, n_hi], each with its own coupling matrix, input weights, initial
+    state and constants, driven by one shared input series."""
+
+    name: str
+    count: int
+    n_lo: int
+    n_hi: int
+    samples: int
+    substeps: int = 20
+    dt: float = 0.01
+    seed: int = 0
+    ridge: float = 1e-6
+
+    @property
+    def steps(self) -> int:
+        return self.samples * self.substeps
+
+
+SWEEPS: Dict[str, Sweep] = {
+    "sweep256": Sweep("sweep256", count=256, n_lo=32, n_hi=2048, samples=2000),
+}
+
+
+def make_sweep_arrays(sw: Sweep, samples: Optional[int] = None, count: Optional[int] = None):
+    """Per-reservoir arrays and draws of a sweep.
+
+    Reservoir r uses SeedSequence([seed, r]) for [W, w_in, m0, constants];
+    its size comes from the sweep's own stream (SeedSequence(seed) spawn[0]).
+    The draws per reservoir are plain random numbers: ``current_scale`` and
+    ``field_scale`` ~ U[0.5, 1.5] (multipliers of I and H_appl), ``a_cp`` ~
+    U[0.01, 0.5] and ``a_in`` ~ U[0.1, 2] in the dimensionless field unit.
+    The shared input u ~ U[-1, 1] and the target come from the sweep's
+    input stream (spawn[3]).
+    """
+    count = sw.count if count is None else count
+    g_size, _, _, g_u = seed_streams(sw.seed)
+    sizes = np.rint(np.exp(g_size.uniform(math.log(sw.n_lo), math.log(sw.n_hi), size=sw.count))).astype(int)
+    u = draw_inputs(g_u, sw.samples, 1)
+    if samples is not None:
+        u = np.ascontiguousarray(u[:samples])
+    res = []
+    for r in range(count):
+        g_w, g_in, g_m0, g_p = seed_streams(sw.seed, r)
+        n = int(sizes[r])
+        res.append({
+            "n": n,
+            "W": draw_coupling(g_w, n, "normal"),
+            "w_in": draw_input_weights(g_in, n, 1),
+            "m0": draw_initial(g_m0, n, "random"),
+            "current_scale": float(g_p.uniform(0.5, 1.5)),
+            "field_scale": float(g_p.uniform(0.5, 1.5)),
+            "a_cp": float(g_p.uniform(0.01, 0.5)),
+            "a_in": float(g_p.uniform(0.1, 2.0)),
+        })
+    return {"reservoirs": res, "u": u, "y": draw_target(u)}
