@@ -291,6 +291,59 @@ def run_sweep_workload(stx, torch, name: str, steps: int, warmup: int, plain_sam
     }
 
 
+# Table 2 of the paper (wall time in seconds for its stated benchmark: u = 0,
+# FP64, RK4 with a 1e-11 s step): its NumPy baseline and its GPU Torch code.
+PAPER_N = [1, 10, 100, 1000, 2500, 5000, 10000]
+PAPER_TABLE2_S = {
+    "numpy_base": [0.81, 0.93, 1.12, 5.78, 36.38, 2.79 * 60, 13.40 * 60],
+    "torch_gpu": [None, 7.47, 7.55, 7.14, 7.59, 0.22 * 60, 0.56 * 60],
+}
+
+
+def paper_table(stx, torch, steps: int):
+    """The paper's benchmark on this GPU: u = 0, FP64, dt = 1e-11 s (0.01 in
+    units of 1 ns), the paper's coupling generator (U[-1,1], zero diagonal,
+    spectral radius 1), its identical initial tilt and A_cp = A_in = 1 Oe,
+    for N = 1 ... 10^4, ``steps`` RK4 steps each."""
+    import numpy as np
+    from workloads import draw_coupling, draw_initial, draw_input_weights, seed_streams
+    from paper_2312_01121_amd import params
+
+    g = params.field_unit()
+    substeps = 20
+    samples = max(1, steps // substeps)
+    rows = []
+    for i, n in enumerate(PAPER_N):
+        g_w, g_in, g_m0, _ = seed_streams(0, 5000 + n)
+        w = draw_coupling(g_w, n, "paper")
+        w_in = draw_input_weights(g_in, n, 1)
+        m0 = draw_initial(g_m0, n, "paper")
+        prm = stx.make_params(**params.table1(a_cp=g * 1.0, a_in=g * 1.0, substeps=substeps), dtype="f64")
+        r = stx.Reservoir(w, w_in, m0, prm)
+        u_d = torch.zeros((samples, 1), dtype=torch.float64, device="cuda")
+        states = torch.empty((samples, n, 3), dtype=torch.float64, device="cuda")
+        r.run_device(u_d[:1].contiguous(), states[:1].contiguous())   # warm-up
+        r.set_state(m0)
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        r.run_device(u_d, states, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3
+        rec = states.cpu().numpy()
+        drift = float(np.max(np.abs(np.linalg.norm(rec, axis=2) - 1.0)))
+        base = PAPER_TABLE2_S["numpy_base"][i]
+        rows.append({"n": n, "path": r.path, "rk4_steps": samples * substeps, "seconds": sec,
+                     "us_per_rk4_step": sec * 1e6 / (samples * substeps),
+                     "node_steps_per_s": n * samples * substeps / sec, "max_norm_drift": drift,
+                     "paper_numpy_base_s": base, "paper_torch_gpu_s": PAPER_TABLE2_S["torch_gpu"][i]})
+        r.close()
+        log(json.dumps(rows[-1]))
+    return rows
+
+
 def cpu_baseline(name: str, arrays, budget_s: float = 25.0):
     """The FP64 oracle (correctly rounded coupling sums) on the first input
     samples of the workload, on this host's cores."""
@@ -327,6 +380,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--samples", type=int, default=None,
                     help="run only the first SAMPLES input samples of the main workload (short profiled runs)")
+    ap.add_argument("--paper-table", type=int, default=0, metavar="STEPS",
+                    help="only run the paper's benchmark (u = 0, FP64, N = 1..1e4) for STEPS RK4 steps each")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device with a plain copy kernel (scales HBM counters)")
     args = ap.parse_args()
@@ -343,6 +398,10 @@ def main():
     import paper_2312_01121_amd as stx
     from workloads import WORKLOADS, make_workload_arrays
 
+    if args.paper_table:
+        rows = paper_table(stx, torch, args.paper_table)
+        print(json.dumps({"paper_table": rows, "steps": args.paper_table}), flush=True)
+        return
     if args.calibrate_copy:
         nbytes = args.calibrate_copy << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")

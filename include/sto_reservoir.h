@@ -258,6 +258,17 @@ sto_status readout_fit_device(const void *states_dev, int32_t dtype, int64_t T, 
  */
 sto_status sto_read_bandwidth(int64_t bytes, int32_t reps, double *gbs_out);
 
+/*
+ * sto_set_stream_variant -- choose the launch shape of the streaming
+ * kernels (STO_PATH_STREAM and sweeps) for this process: rows of W per wave
+ * and unroll of the column loop.  (0, 0) restores the built-in table, which
+ * the autotuner (paper_2312_01121_amd/autotune.py) writes from measurements.
+ * Only compiled variants are accepted: rows x unroll in {1x4, 2x2, 2x4, 4x1,
+ * 4x2, 4x4, 8x1, 8x2}; STO_E_INVALID otherwise.  Not synchronised with runs
+ * in flight on other threads.
+ */
+sto_status sto_set_stream_variant(int32_t rows, int32_t unroll);
+
 /* sto_last_error -- message of the last non-OK status on this thread
  * (empty string if none).  Valid until the next call on this thread. */
 const char *sto_last_error(void);

@@ -63,6 +63,14 @@ def make_params(alpha, h_appl, h_k, h_s, lambda_stt, p, a_cp, a_in, dt, substeps
 
 
 def _load():
+    # torch's HIP libraries load their own bundled HIP runtime under the
+    # unversioned name libamdhip64.so; loading it first makes this library's
+    # libamdhip64.so.7 resolve to that same runtime instead of a second copy
+    # (two runtimes in one process cannot share the device).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2312_01121_amd._build`")
     lib = ctypes.CDLL(LIB_PATH)
@@ -102,6 +110,8 @@ def _load():
     lib.sweep_get_state.restype = ctypes.c_int
     lib.sweep_destroy.argtypes = [H]
     lib.sweep_destroy.restype = None
+    lib.sto_set_stream_variant.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.sto_set_stream_variant.restype = ctypes.c_int
     lib.sto_read_bandwidth.argtypes = [ctypes.c_int64, ctypes.c_int32, dp]
     lib.sto_read_bandwidth.restype = ctypes.c_int
     lib.sto_last_error.restype = ctypes.c_char_p
@@ -116,7 +126,7 @@ _lib = _load()
 EXPORTED = ("reservoir_create", "reservoir_create_streams", "reservoir_streams", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
             "reservoir_set_state", "reservoir_path", "reservoir_destroy", "readout_fit", "readout_fit_device",
             "sweep_create", "sweep_nodes", "sweep_run", "sweep_run_device", "sweep_get_state", "sweep_destroy",
-            "sto_read_bandwidth", "sto_last_error")
+            "sto_read_bandwidth", "sto_set_stream_variant", "sto_last_error")
 
 
 def lib():
@@ -232,6 +242,11 @@ def readout_fit_device(states_dev, y_dev, washout: int, lam: float, features: in
                                    ctypes.c_void_p(y_dev.data_ptr()), washout, lam, features,
                                    ctypes.c_void_p(w_out_dev.data_ptr()), _dptr(nmse), ctypes.c_void_p(s)))
     return w_out_dev, float(nmse[0])
+
+
+def sto_set_stream_variant(rows: int, unroll: int):
+    """Launch shape of the stream kernels for this process ((0, 0): table)."""
+    _check(_lib.sto_set_stream_variant(rows, unroll))
 
 
 def sto_read_bandwidth(nbytes: int = 1 << 30, reps: int = 10) -> float:

@@ -14,6 +14,7 @@
 
 #include "../../include/sto_reservoir.h"
 #include "sto_internal.hpp"
+#include "stream_tune.hpp"
 
 namespace {
 
@@ -64,10 +65,39 @@ int env_int(const char* name, int dflt) {
 }  // namespace
 
 namespace sto {
-const Tune& tune() {
-    static const Tune t = {env_flag("STO_STREAM_ALTERNATE", 0), env_flag("STO_STREAM_NT", 1),
-                           env_int("STO_STREAM_ROWS", 0), env_int("STO_STREAM_UNROLL", 0)};
+static Tune& tune_mut() {
+    static Tune t = {env_flag("STO_STREAM_ALTERNATE", 0), env_flag("STO_STREAM_NT", 1), env_int("STO_STREAM_ROWS", 0),
+                     env_int("STO_STREAM_UNROLL", 0)};
     return t;
+}
+const Tune& tune() { return tune_mut(); }
+
+bool set_stream_variant(int rows, int unroll) {
+    static const int ok[][2] = {{0, 0}, {1, 4}, {2, 2}, {2, 4}, {4, 1}, {4, 2}, {4, 4}, {8, 1}, {8, 2}};
+    for (const auto& v : ok)
+        if (v[0] == rows && v[1] == unroll) {
+            tune_mut().stream_rows = rows;
+            tune_mut().stream_unroll = unroll;
+            return true;
+        }
+    return false;
+}
+
+void stream_shape(int elem_bytes, int n, int* rows, int* unroll) {
+    const Tune& t = tune();
+    if (t.stream_rows > 0 && t.stream_unroll > 0) {
+        *rows = t.stream_rows;
+        *unroll = t.stream_unroll;
+        return;
+    }
+    *rows = 2;
+    *unroll = elem_bytes == 8 ? 4 : 2;
+    for (const StreamTuneEntry& e : kStreamTune)
+        if (e.elem_bytes == elem_bytes && n <= e.n_max) {
+            *rows = e.rows;
+            *unroll = e.unroll;
+            return;
+        }
 }
 }  // namespace sto
 
@@ -383,6 +413,12 @@ sto_status readout_status(int rc, const char* err) {
 extern "C" {
 
 const char* sto_last_error(void) { return g_err.c_str(); }
+
+sto_status sto_set_stream_variant(int32_t rows, int32_t unroll) {
+    if (!sto::set_stream_variant(rows, unroll))
+        return fail(STO_E_INVALID, "no compiled stream variant with rows=%d unroll=%d", rows, unroll);
+    return STO_OK;
+}
 
 sto_status sto_read_bandwidth(int64_t bytes, int32_t reps, double* gbs_out) {
     if (!gbs_out || bytes < (1 << 20) || reps < 1) return fail(STO_E_INVALID, "bytes >= 1 MiB, reps >= 1, gbs_out");

@@ -79,6 +79,10 @@ struct Tune {
     int stream_unroll;       // column-loop unroll of the stream kernel (0: default)
 };
 const Tune& tune();
+// Process-wide override of the stream kernel shape (0, 0: table).
+bool set_stream_variant(int rows, int unroll);
+// Rows per wave and unroll of the stream kernels for element size and n.
+void stream_shape(int elem_bytes, int n, int* rows, int* unroll);
 
 // Path launchers; each returns the HIP status of its launches.
 template <typename T> hipError_t run_stream(const DevState<T>& d, const Coef<T>& k, const RunSpec& r);

@@ -193,10 +193,8 @@ static void launch_stage_rv(int rows, int unroll, hipStream_t st, const DevState
 template <typename T>
 hipError_t run_stream(const DevState<T>& d, const Coef<T>& k, const RunSpec& r) {
     const Tune& t = tune();
-    // defaults from a sweep at N = 10,000 (rows per wave x unroll in
-    // {1,2,4,8} x {1,2,4}): FP32 2 x 2 and FP64 2 x 4 stream W fastest
-    const int rows = t.stream_rows > 0 ? t.stream_rows : 2;
-    const int unroll = t.stream_unroll > 0 ? t.stream_unroll : (sizeof(T) == 8 ? 4 : 2);
+    int rows = 2, unroll = 2;
+    stream_shape((int)sizeof(T), d.n, &rows, &unroll);
     T* states = static_cast<T*>(r.states);
     int cur = r.cur;
     int64_t sigma = 0;

@@ -316,3 +316,27 @@ def test_sto10k_full_horizon_properties(stx, dtype):
     drift = sto.norm_drift(rec)
     say("  drift", drift)
     assert drift < (1e-4 if dtype == "f64" else 1e-3)
+
+
+# ---------------------------------------------------------------------------
+# The paper's own benchmark setup (Sec. 3.2): u = 0, FP64, paper generator
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,steps", [(1, 5000), (10, 5000), (100, 5000), (1000, 200)])
+def test_paper_benchmark_setup_matches_oracle(stx, n, steps):
+    """u = 0, coupling U[-1,1] with spectral radius 1, identical initial tilt
+    (Eq. (initial)), A_cp = A_in = 1 Oe, dt = 1e-11 s."""
+    from workloads import draw_coupling, draw_initial, draw_input_weights, seed_streams
+    g_w, g_in, g_m0, _ = seed_streams(0, 5000 + n)
+    w = draw_coupling(g_w, n, "paper")
+    w_in = draw_input_weights(g_in, n, 1)
+    m0 = draw_initial(g_m0, n, "paper")
+    g = 1.764e7 * 1e-9
+    prm = oracle_params(a_cp=g, a_in=g)
+    u = np.zeros((steps // 20, 1))
+    say("paper setup", n, steps)
+    rec_o, _ = sto.run(w, w_in, m0, u, prm)
+    with make(stx, w, w_in, m0, prm) as r:
+        rec = r.run(u)
+    d = maxdiff(rec, rec_o)
+    say("  max diff", d)
+    assert d <= F64_TOL

@@ -85,14 +85,25 @@ def seed_streams(seed: int, key: Optional[int] = None):
 
 
 def draw_coupling(rng: np.random.Generator, n: int, kind: str = "normal") -> np.ndarray:
-    """Dense n x n coupling matrix with zero diagonal (float64, C order)."""
+    """Dense n x n coupling matrix with zero diagonal (float64, C order).
+
+    "paper": U[-1,1] entries rescaled to spectral radius 1.  The radius is
+    computed from the eigenvalues for n <= 2000; above that it is taken from
+    the circular law, rho = sqrt(n / 3) for i.i.d. entries of variance 1/3
+    (relative error O(n^-1/2); a full eigendecomposition of a 10^4 matrix
+    would take minutes and only rescales W)."""
     if kind == "normal":
         w = rng.standard_normal((n, n))
         w *= 1.0 / math.sqrt(n)
     elif kind == "paper":
         w = rng.uniform(-1.0, 1.0, size=(n, n))
         np.fill_diagonal(w, 0.0)
-        rho = float(np.max(np.abs(np.linalg.eigvals(w)))) if n > 1 else 0.0
+        if n <= 1:
+            rho = 0.0
+        elif n <= 2000:
+            rho = float(np.max(np.abs(np.linalg.eigvals(w))))
+        else:
+            rho = math.sqrt(n / 3.0)
         if rho > 0.0:
             w /= rho
     else:
