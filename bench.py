@@ -42,6 +42,8 @@ def log(*a):
 
 
 KERNEL_SOURCES = {
+    "k_sweep_stage": ("sto_device.hpp", "sto_internal.hpp", "sto_sweep.hip"),
+    "k_multi": ("sto_device.hpp", "sto_internal.hpp", "sto_multi.hip"),
     "k_stage": ("sto_device.hpp", "sto_internal.hpp", "sto_kernels.hip"),
     "k_small": ("sto_device.hpp", "sto_internal.hpp", "sto_kernels.hip"),
     "k_resident": ("sto_device.hpp", "sto_internal.hpp", "sto_resident.hip"),
@@ -215,7 +217,8 @@ def run_streams_workload(stx, torch, name: str, steps: int, warmup: int):
     }
 
 
-def run_sweep_workload(stx, torch, name: str, steps: int, warmup: int, plain_samples: int = 20):
+def run_sweep_workload(stx, torch, name: str, steps: int, warmup: int, plain_samples: int = 20,
+                       samples=None, plain: bool = True):
     """Parameter sweep (SWEEP path): every reservoir's run plus one readout
     per reservoir is one step.  The plain single-reservoir path (each
     reservoir alone, its own auto-selected kernel) is timed on the first
@@ -225,6 +228,9 @@ def run_sweep_workload(stx, torch, name: str, steps: int, warmup: int, plain_sam
     from paper_2312_01121_amd import params
 
     sw_def = SWEEPS[name]
+    if samples is not None:
+        import dataclasses
+        sw_def = dataclasses.replace(sw_def, samples=samples)
     a = make_sweep_arrays(sw_def)
     res = a["reservoirs"]
     for r in res:
@@ -262,10 +268,11 @@ def run_sweep_workload(stx, torch, name: str, steps: int, warmup: int, plain_sam
     nmse = np.array(evs[-1][2])
     sw.close()
     # plain path: each reservoir alone
+    plain_samples = min(plain_samples, T)
     u_p = torch.from_numpy(np.ascontiguousarray(a["u"][:plain_samples])).cuda()
     plain_ms = 0.0
     paths = {}
-    for r in res:
+    for r in (res if plain else []):
         one = stx.Reservoir(r["W"], r["w_in"], r["m0"], r["prm"])
         paths[one.path] = paths.get(one.path, 0) + 1
         st1 = torch.empty((plain_samples, r["n"], 3), dtype=torch.float32, device="cuda")
@@ -287,7 +294,8 @@ def run_sweep_workload(stx, torch, name: str, steps: int, warmup: int, plain_sam
         "us_per_rk4_step": run_ms * 1e3 / sw_def.steps, "kernel": "k_sweep_stage", "launches_per_run": launches,
         "algo_bytes_per_launch": algo, "achieved_gbs": achieved, "hbm_frac": achieved / HBM_PEAK_GBS,
         "readout_nmse_median": float(np.median(nmse)), "readout_nmse_min": float(np.min(nmse)),
-        "plain_paths": paths, "plain_run_ms_estimate": plain_ms, "speedup_vs_plain": plain_ms / run_ms,
+        "plain_paths": paths, "plain_run_ms_estimate": plain_ms if plain else None,
+        "speedup_vs_plain": plain_ms / run_ms if plain else None,
     }
 
 
@@ -382,6 +390,8 @@ def main():
                     help="run only the first SAMPLES input samples of the main workload (short profiled runs)")
     ap.add_argument("--paper-table", type=int, default=0, metavar="STEPS",
                     help="only run the paper's benchmark (u = 0, FP64, N = 1..1e4) for STEPS RK4 steps each")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="sweep workload: skip timing the plain single-reservoir path")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device with a plain copy kernel (scales HBM counters)")
     args = ap.parse_args()
@@ -411,6 +421,27 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
         del src, dst
+    from workloads import STREAMS, SWEEPS
+    if args.workload in SWEEPS or args.workload in STREAMS:
+        if args.workload in SWEEPS:
+            res = run_sweep_workload(stx, torch, args.workload, args.steps, args.warmup, samples=args.samples,
+                                     plain=not args.no_plain)
+            roof = {"bound": "hbm", "kernel": res["kernel"], "achieved": res["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": res["hbm_frac"], "traffic": stored_traffic("k_sweep_stage", args.workload, "f32")}
+            unit_nodes = res["nodes"]
+        else:
+            res = run_streams_workload(stx, torch, args.workload, args.steps, args.warmup)
+            roof = {"bound": "mfma", "kernel": res["kernel"], "achieved": res["mfma_tflops"], "peak": 157.3,
+                    "unit": "TFLOP/s", "frac": res["mfma_frac"], "traffic": None}
+            unit_nodes = res["n"] * res["streams"]
+        print(json.dumps({
+            "metric": METRIC, "value": res["value"], "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": args.workload, "nodes": unit_nodes, "rk4_steps": res["rk4_steps"],
+                       "path": res["path"], "parallelism": "single GPU"},
+            "roofline": roof, "cpu_baseline": None, "detail": res, "also": []}), flush=True)
+        return
     attainable = stx.sto_read_bandwidth(2 << 30, 5)
     log(f"attainable HBM read bandwidth (plain streaming kernel): {attainable:.0f} GB/s")
     arrays = make_workload_arrays(WORKLOADS[args.workload])

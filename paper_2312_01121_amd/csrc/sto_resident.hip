@@ -69,35 +69,32 @@ __device__ __forceinline__ void rearm(T* p) {
 }
 
 // Wait until the n entries of src are published and copy them to LDS.
-// Each thread keeps kQ loads in flight per round.  Returns false if the wait
-// was abandoned (spin limit or abort flag).
-constexpr int kQ = 8;
+// Returns false if the wait was abandoned (spin limit or abort flag).
 template <typename T>
 __device__ bool gather_stage_input(const T* src, T* dst, int n, int* abort_flag) {
     using B = typename Bits<T>::type;
     const B* s = reinterpret_cast<const B*>(src);
     bool ok = true;
-    for (int i0 = 0; i0 < n && ok; i0 += kQ * kBlock) {
-        B v[kQ];
-        unsigned todo = 0;
-#pragma unroll
-        for (int q = 0; q < kQ; ++q)
-            if (i0 + q * kBlock + (int)threadIdx.x < n) todo |= 1u << q;
+    for (int i0 = 0; i0 < n; i0 += 4 * kBlock) {
+        B v[4];
+        bool pending = true;
         int rounds = 0;
-        while (todo) {
+        while (pending) {
+            pending = false;
 #pragma unroll
-            for (int q = 0; q < kQ; ++q)
-                if (todo & (1u << q))
-                    v[q] = __hip_atomic_load(s + i0 + q * kBlock + threadIdx.x, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
+            for (int q = 0; q < 4; ++q) {
+                const int i = i0 + q * kBlock + threadIdx.x;
+                v[q] = i < n ? __hip_atomic_load(s + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : B(0);
+            }
 #pragma unroll
-            for (int q = 0; q < kQ; ++q) {
-                if ((todo & (1u << q)) && v[q] != sentinel<T>()) {
-                    dst[i0 + q * kBlock + threadIdx.x] = __builtin_bit_cast(T, v[q]);
-                    todo &= ~(1u << q);
+            for (int q = 0; q < 4; ++q) {
+                const int i = i0 + q * kBlock + threadIdx.x;
+                if (i < n) {
+                    if (v[q] == sentinel<T>()) pending = true;
+                    else dst[i] = __builtin_bit_cast(T, v[q]);
                 }
             }
-            if (todo && (++rounds & 255) == 0) {
+            if (pending && (++rounds & 255) == 0) {
                 if (rounds > kSpinLimit) {
                     __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     ok = false;
@@ -109,6 +106,7 @@ __device__ bool gather_stage_input(const T* src, T* dst, int n, int* abort_flag)
                 }
             }
         }
+        if (!ok) break;
     }
     return ok;
 }
