@@ -355,7 +355,7 @@ sto::SweepDev<T> sweep_dev(const sto_sweep* s, void* states, int64_t samples) {
     d.bad = s->bad;
     d.res = static_cast<const sto::SweepRes*>(s->res_dev);
     d.coef = static_cast<const sto::Coef<T>*>(s->coef_dev);
-    d.task = static_cast<const int4*>(s->task_dev);
+    d.task = static_cast<const int2*>(s->task_dev);
     d.tasks = s->tasks;
     d.n_in = (int)s->n_in;
     d.rec_samples = samples;
@@ -702,7 +702,8 @@ sto_status sweep_create(int32_t count, const int64_t* n, int64_t n_in, const sto
     s->substeps = prm[0].substeps;
     s->renorm = prm[0].renormalize;
     int64_t woff = 0, soff = 0, winoff = 0, noff = 0;
-    std::vector<int4> tasks;
+    std::vector<int2> tasks;
+    const int R = sto::sweep_rows_per_task((int)s->elem);
     for (int r = 0; r < count; ++r) {
         sto::SweepRes x;
         x.n = (int)n[r];
@@ -717,18 +718,9 @@ sto_status sweep_create(int32_t count, const int64_t* n, int64_t n_in, const sto
         soff += 3 * x.ld;
         winoff += n[r] * n_in;
         noff += n[r];
-    }
-    // wave tasks: pairs of rows, several pairs for small reservoirs; the
-    // largest reservoirs first, so the long tasks start early
-    std::vector<int> order(count);
-    for (int r = 0; r < count; ++r) order[r] = r;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
-    for (int r : order) {
-        const int pairs = sto::sweep_pairs_per_task(s->res[r].ld, (int)s->elem);
-        for (int64_t row = 0; row < n[r]; row += 2 * pairs) {
-            const int64_t left = (n[r] - row + 1) / 2;
-            tasks.push_back(make_int4(r, (int)row, (int)std::min<int64_t>(pairs, left), 0));
-        }
+        // wave tasks of R rows each, in reservoir order (measured: a
+        // largest-first order or several row groups per task were slower)
+        for (int row = 0; row < n[r]; row += R) tasks.push_back(make_int2(r, row));
     }
     s->nodes = noff;
     s->tasks = (int)tasks.size();
@@ -751,7 +743,7 @@ sto_status sweep_create(int32_t count, const int64_t* n, int64_t n_in, const sto
     SALLOC(s->acc, (size_t)soff * s->elem);
     SALLOC(s->res_dev, sizeof(sto::SweepRes) * count);
     SALLOC(s->coef_dev, (s->dtype == STO_F64 ? sizeof(sto::Coef<double>) : sizeof(sto::Coef<float>)) * count);
-    SALLOC(s->task_dev, sizeof(int4) * tasks.size());
+    SALLOC(s->task_dev, sizeof(int2) * tasks.size());
     SALLOC(s->bad, sizeof(int));
 #undef SALLOC
     e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
@@ -783,7 +775,7 @@ sto_status sweep_create(int32_t count, const int64_t* n, int64_t n_in, const sto
         e = hipMemcpy(s->coef_dev, c.data(), sizeof(c[0]) * count, hipMemcpyHostToDevice);
     }
     if (e == hipSuccess) e = hipMemcpy(s->res_dev, s->res.data(), sizeof(sto::SweepRes) * count, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(s->task_dev, tasks.data(), sizeof(int4) * tasks.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->task_dev, tasks.data(), sizeof(int2) * tasks.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return cleanup(hip_fail(e, "sweep upload"));
     *out = s;
     return STO_OK;

@@ -52,7 +52,7 @@ struct SweepDev {
     int* bad;
     const SweepRes* res;
     const Coef<T>* coef;
-    const int4* task;  // (reservoir, first row, row pairs, 0) of every wave task
+    const int2* task;  // (reservoir, first row) of every wave task
     int tasks;
     int n_in;
     int64_t rec_samples;   // samples of the current run (record layout)
@@ -95,7 +95,7 @@ hipError_t run_multi(const DevState<float>& d, const Coef<float>& k, const RunSp
 
 // SWEEP path launcher (one launch per RK4 stage over every reservoir).
 template <typename T> hipError_t run_sweep(const SweepDev<T>& d, const RunSpec& r);
-int sweep_pairs_per_task(int64_t ld, int elem_bytes);
+int sweep_rows_per_task(int elem_bytes);
 
 // Largest n the single-workgroup kernel holds (W in LDS).
 int small_max_n(int elem_bytes, int xyz);

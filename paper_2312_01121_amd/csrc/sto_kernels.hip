@@ -316,7 +316,7 @@ hipError_t read_bandwidth(int64_t bytes, int reps, double* gbs) {
 // SMALL path: the whole trajectory in one workgroup.
 // ---------------------------------------------------------------------------
 template <typename T, bool XYZ>
-__global__ void __launch_bounds__(256) k_small(DevState<T> d, Coef<T> k, const double* __restrict__ u,
+__global__ void __launch_bounds__(1024) k_small(DevState<T> d, Coef<T> k, const double* __restrict__ u,
                                                T* __restrict__ states, int samples, int substeps,
                                                int cur, int renorm, int L) {
     using A = Acc<T>;
@@ -353,14 +353,34 @@ __global__ void __launch_bounds__(256) k_small(DevState<T> d, Coef<T> k, const d
         for (int sub = 0; sub < substeps; ++sub) {
             for (int stage = 0; stage < 4; ++stage) {
                 const T* xb = xs + b * 3 * n;
+                // two independent accumulation chains per lane (even and odd
+                // terms), joined before the butterfly
                 AT vx = A::zero(), vy = A::zero(), vz = A::zero();
-                for (int j = l; j < n; j += L) {
-                    T w = wr[j];
-                    A::fma(vx, w, xb[j]);
+                AT wx = A::zero(), wy = A::zero(), wz = A::zero();
+                int j = l;
+                for (; j + L < n; j += 2 * L) {
+                    const T w0 = wr[j], w1 = wr[j + L];
+                    A::fma(vx, w0, xb[j]);
+                    A::fma(wx, w1, xb[j + L]);
                     if (XYZ) {
-                        A::fma(vy, w, xb[n + j]);
-                        A::fma(vz, w, xb[2 * n + j]);
+                        A::fma(vy, w0, xb[n + j]);
+                        A::fma(wy, w1, xb[n + j + L]);
+                        A::fma(vz, w0, xb[2 * n + j]);
+                        A::fma(wz, w1, xb[2 * n + j + L]);
                     }
+                }
+                if (j < n) {
+                    const T w0 = wr[j];
+                    A::fma(vx, w0, xb[j]);
+                    if (XYZ) {
+                        A::fma(vy, w0, xb[n + j]);
+                        A::fma(vz, w0, xb[2 * n + j]);
+                    }
+                }
+                vx = A::add(vx, wx);
+                if (XYZ) {
+                    vy = A::add(vy, wy);
+                    vz = A::add(vz, wz);
                 }
                 vx = group_reduce<T>(vx, L);
                 T cx = k.a_cp * A::round(vx), cy = T(0), cz = T(0);
@@ -420,18 +440,26 @@ static const size_t kLdsMax = 160 * 1024;
 
 int small_max_n(int elem_bytes, int /*xyz*/) {
     int n = 1;
-    while (n + 1 <= 256 && small_lds_bytes(n + 1, elem_bytes) <= kLdsMax) ++n;
+    while (n + 1 <= 1024 && small_lds_bytes(n + 1, elem_bytes) <= kLdsMax) ++n;
     return n;
+}
+
+// Lanes per node: about 4 terms of the row sum per lane (measured: longer
+// per-lane chains cost more than the extra butterfly level), at most 64 (one
+// wave) and at most 1024 threads in all.
+static int small_lanes(int n) {
+    int L = 1;
+    while (L * 2 <= 64 && L * 2 * 4 <= n && L * 2 * n <= 1024) L *= 2;
+    return L;
 }
 
 template <typename T>
 hipError_t run_small(const DevState<T>& d, const Coef<T>& k, const RunSpec& r) {
     const int n = d.n;
-    const int block = n <= 32 ? 64 : 256;
-    int L = 1;
-    while (L * 2 * n <= block && L * 2 <= 64) L *= 2;
+    const int L = small_lanes(n);
+    const int block = (L * n + 63) / 64 * 64;
     size_t lds = small_lds_bytes(n, sizeof(T));
-    if (n > block || lds > kLdsMax) return hipErrorInvalidValue;
+    if (L * n > block || block > 1024 || lds > kLdsMax) return hipErrorInvalidValue;
     hipError_t e;
     if (r.xyz) {
         e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small<T, true>),

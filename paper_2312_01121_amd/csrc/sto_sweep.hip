@@ -11,7 +11,6 @@
 // single-reservoir stream kernel does.  The sum of N_r^2 matrix elements is
 // read once per stage, so the launch is bound by HBM bandwidth.
 
-#include <algorithm>
 #include <climits>
 
 #include "sto_internal.hpp"
@@ -26,107 +25,99 @@ template <typename T> struct SVec;
 template <> struct SVec<double> { using type = dvec2; static constexpr int n = 2; };
 template <> struct SVec<float> { using type = fvec4; static constexpr int n = 4; };
 
-// One wave task: rows row0 .. row0 + 2*pairs - 1 of one reservoir, taken two
-// at a time (small reservoirs get several pairs per task so that every task
-// streams a similar number of bytes).
-template <typename T, int U>
+template <typename T, int R, int U>
 __global__ void __launch_bounds__(256) k_sweep_stage(SweepDev<T> d, const double* __restrict__ u_s, int sample,
                                                      int stage, int cur, int record, int renorm) {
     using A = Acc<T>;
     using AT = typename A::type;
     using V = typename SVec<T>::type;
     constexpr int VN = SVec<T>::n;
-    constexpr int R = 2;
     const int lane = threadIdx.x & 63;
     const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (task >= d.tasks) return;   // wave-uniform
-    const int4 tk = d.task[task];  // (reservoir, first row, row pairs, 0)
+    const int2 tk = d.task[task];
     const SweepRes res = d.res[tk.x];
     const Coef<T> k = d.coef[tk.x];
     const int n = res.n;
     const int64_t ld = res.ld;
+    const int row0 = tk.y;
     const T* W = d.W + res.woff;
     T* m = d.m + res.soff;
     T* acc = d.acc + res.soff;
     const T* xin = d.ms[cur] + res.soff;
     T* xout = d.ms[cur ^ 1] + res.soff;
 
-    for (int pr = 0; pr < tk.z; ++pr) {
-        const int row0 = tk.y + R * pr;
-        const T* wrow[R];
+    const T* wrow[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) wrow[r] = W + (int64_t)min(row0 + r, n - 1) * ld;
-        AT av[R];
+    for (int r = 0; r < R; ++r) wrow[r] = W + (int64_t)min(row0 + r, n - 1) * ld;
+    AT av[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) av[r] = A::zero();
+    for (int r = 0; r < R; ++r) av[r] = A::zero();
 #pragma unroll U
-        for (int64_t c = (int64_t)lane * VN; c < ld; c += 64 * VN) {
-            const V xv = *reinterpret_cast<const V*>(xin + c);
-            V wv[R];
+    for (int64_t c = (int64_t)lane * VN; c < ld; c += 64 * VN) {
+        const V xv = *reinterpret_cast<const V*>(xin + c);
+        V wv[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) wv[r] = __builtin_nontemporal_load(reinterpret_cast<const V*>(wrow[r] + c));
+        for (int r = 0; r < R; ++r) wv[r] = __builtin_nontemporal_load(reinterpret_cast<const V*>(wrow[r] + c));
 #pragma unroll
-            for (int r = 0; r < R; ++r)
+        for (int r = 0; r < R; ++r)
 #pragma unroll
-                for (int e = 0; e < VN; ++e) A::fma(av[r], wv[r][e], xv[e]);
-        }
-        T dot = T(0);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const AT s = group_reduce<T>(av[r], 64);
-            if (lane == r) dot = A::round(s);
-        }
-        const int row = row0 + lane;
-        if (lane >= R || row >= n) continue;
-        const T hin = input_field(k, d.w_in + res.winoff + (int64_t)row * d.n_in, u_s, d.n_in);
-        const T sx = xin[row], sy = xin[ld + row], sz = xin[2 * ld + row];
-        T fx, fy, fz;
-        llg_rhs<T, false>(k, sx, sy, sz, k.a_cp * dot, T(0), T(0), hin, fx, fy, fz);
-        T mx = m[row], my = m[ld + row], mz = m[2 * ld + row];
-        T ax = T(0), ay = T(0), az = T(0);
-        if (stage > 0) {
-            ax = acc[row];
-            ay = acc[ld + row];
-            az = acc[2 * ld + row];
-        }
-        T nx = rk4_update(k, stage, mx, ax, fx);
-        T ny = rk4_update(k, stage, my, ay, fy);
-        T nz = rk4_update(k, stage, mz, az, fz);
-        if (stage == 3) {
-            if (renorm) renormalize(nx, ny, nz);
-            m[row] = nx;
-            m[ld + row] = ny;
-            m[2 * ld + row] = nz;
-            if (record && d.states) {
-                T* rec = d.states + (d.rec_samples * res.noff + (int64_t)sample * n + row) * 3;
-                rec[0] = nx;
-                rec[1] = ny;
-                rec[2] = nz;
-            }
-            if (!finite3(nx, ny, nz)) atomicMin(d.bad, sample);
-        } else {
-            acc[row] = ax;
-            acc[ld + row] = ay;
-            acc[2 * ld + row] = az;
-        }
-        xout[row] = nx;
-        xout[ld + row] = ny;
-        xout[2 * ld + row] = nz;
+            for (int e = 0; e < VN; ++e) A::fma(av[r], wv[r][e], xv[e]);
     }
+    T dot = T(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const AT s = group_reduce<T>(av[r], 64);
+        if (lane == r) dot = A::round(s);
+    }
+    const int row = row0 + lane;
+    if (lane >= R || row >= n) return;
+    const T hin = input_field(k, d.w_in + res.winoff + (int64_t)row * d.n_in, u_s, d.n_in);
+    const T sx = xin[row], sy = xin[ld + row], sz = xin[2 * ld + row];
+    T fx, fy, fz;
+    llg_rhs<T, false>(k, sx, sy, sz, k.a_cp * dot, T(0), T(0), hin, fx, fy, fz);
+    T mx = m[row], my = m[ld + row], mz = m[2 * ld + row];
+    T ax = T(0), ay = T(0), az = T(0);
+    if (stage > 0) {
+        ax = acc[row];
+        ay = acc[ld + row];
+        az = acc[2 * ld + row];
+    }
+    T nx = rk4_update(k, stage, mx, ax, fx);
+    T ny = rk4_update(k, stage, my, ay, fy);
+    T nz = rk4_update(k, stage, mz, az, fz);
+    if (stage == 3) {
+        if (renorm) renormalize(nx, ny, nz);
+        m[row] = nx;
+        m[ld + row] = ny;
+        m[2 * ld + row] = nz;
+        if (record && d.states) {
+            T* rec = d.states + (d.rec_samples * res.noff + (int64_t)sample * n + row) * 3;
+            rec[0] = nx;
+            rec[1] = ny;
+            rec[2] = nz;
+        }
+        if (!finite3(nx, ny, nz)) atomicMin(d.bad, sample);
+    } else {
+        acc[row] = ax;
+        acc[ld + row] = ay;
+        acc[2 * ld + row] = az;
+    }
+    xout[row] = nx;
+    xout[ld + row] = ny;
+    xout[2 * ld + row] = nz;
 }
 
 }  // namespace
 
-int sweep_pairs_per_task(int64_t ld, int elem_bytes) {
-    // One row pair per wave task.  Several pairs per task (walked in series
-    // by one wave) were measured slower: fewer loads in flight per stage.
-    (void)ld;
+int sweep_rows_per_task(int elem_bytes) {
     (void)elem_bytes;
-    return 1;
+    return 2;
 }
 
 template <typename T>
 hipError_t run_sweep(const SweepDev<T>& d, const RunSpec& r) {
+    constexpr int R = 2;
     constexpr int U = sizeof(T) == 8 ? 4 : 2;
     const dim3 grid((d.tasks + 3) / 4), block(256);
     for (int s = 0; s < r.samples; ++s) {
@@ -134,7 +125,7 @@ hipError_t run_sweep(const SweepDev<T>& d, const RunSpec& r) {
         for (int sub = 0; sub < r.substeps; ++sub)
             for (int stage = 0; stage < 4; ++stage) {
                 const int rec = stage == 3 && sub == r.substeps - 1;
-                hipLaunchKernelGGL((k_sweep_stage<T, U>), grid, block, 0, r.stream, d, u_s, s, stage,
+                hipLaunchKernelGGL((k_sweep_stage<T, R, U>), grid, block, 0, r.stream, d, u_s, s, stage,
                                    r.cur ^ (stage & 1), rec, r.renorm);
             }
     }
