@@ -1,6 +1,7 @@
 // Host runtime behind include/sto_reservoir.h: validation, device buffers,
 // path selection and error reporting.  Every numerical step runs in the HIP
-// kernels of sto_kernels.hip, sto_resident.hip and readout.hip.
+// kernels of sto_kernels.hip, sto_small.hip, sto_resident.hip, sto_multi.hip,
+// sto_sweep.hip and readout.hip.
 
 #include <algorithm>
 #include <climits>
