@@ -74,3 +74,31 @@ def readout_fit(records: np.ndarray, y: np.ndarray, washout: int, lam: float,
     yy = np.asarray(y, dtype=np.float64)[washout:]
     w = ridge(phi, yy, lam, form)
     return w, nmse(phi, yy, w)
+
+
+def ridge_objective_grad(records: np.ndarray, y: np.ndarray, washout: int, lam: float,
+                         components: str = "x", form: str = "auto"):
+    """Ridge objective at its optimum and its gradient with respect to the records.
+
+    J = (|Phi w* - y|^2 + lambda |w*|^2) / T' with T' the number of fitted
+    rows and w* the ridge weights.  The objective is stationary in w at w*,
+    so the total derivative with respect to Phi equals the partial one
+    (envelope theorem): dJ/dPhi = (2/T') (Phi w* - y) w*^T.  The bias column
+    is constant and rows before the washout do not enter, so their gradient
+    is zero.  Returns (J, w*, dJ/d(records) with the records' shape).
+    """
+    records = np.asarray(records, dtype=np.float64)
+    t, n, _ = records.shape
+    phi = features(records, washout, components)
+    yy = np.asarray(y, dtype=np.float64)[washout:]
+    w = ridge(phi, yy, lam, form)
+    r = phi @ w - yy
+    rows = t - washout
+    j = float((r @ r + lam * (w @ w)) / rows)
+    dphi = (2.0 / rows) * np.outer(r, w)
+    grad = np.zeros_like(records)
+    if components == "x":
+        grad[washout:, :, 0] = dphi[:, :n]
+    else:
+        grad[washout:] = dphi[:, :3 * n].reshape(rows, n, 3)
+    return j, w, grad
