@@ -144,6 +144,78 @@ def run_workload(stx, torch, name: str, dtype: str, steps: int, warmup: int, arr
     }
 
 
+def run_adjoint_workload(stx, torch, name: str, dtype: str, samples: int, steps: int, warmup: int):
+    """Gradient of the ridge objective of a run with respect to W, w_in, m0
+    and the four scalars: forward run, readout fit, readout gradient and the
+    adjoint (reservoir_adjoint_device), over the first `samples` input
+    samples of the workload; the plain forward run of the same inputs is
+    timed beside it."""
+    from workloads import WORKLOADS, make_workload_arrays
+    from paper_2312_01121_amd import params
+
+    wl = WORKLOADS[name].with_samples(samples)
+    a = make_workload_arrays(wl)
+    prm = stx.make_params(**params.table1(a_cp=wl.a_cp, a_in=wl.a_in, dt=wl.dt, substeps=wl.substeps),
+                          dtype=dtype)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    elem = 8 if dtype == "f64" else 4
+    r = stx.Reservoir(a["W"], a["w_in"], a["m0"], prm)
+    u_d = torch.from_numpy(a["u"]).cuda()
+    y = a["y"].copy()
+    y[:5] = 0.0
+    y_d = torch.from_numpy(y).cuda()
+    m0_d = torch.from_numpy(a["m0"]).to("cuda", tdt).contiguous()
+    states = torch.empty((wl.samples, wl.n, 3), dtype=tdt, device="cuda")
+    wash = washout_of(wl.samples)
+    stream = torch.cuda.current_stream()
+
+    def one_step():
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        r.set_state(a["m0"])
+        ev[0].record(stream)
+        r.run_device(u_d, states, stream)
+        ev[1].record(stream)
+        w_d, _ = stx.readout_fit_device(states, y_d, wash, wl.ridge, 0, None, stream)
+        g_d, loss = stx.readout_grad_device(states, y_d, wash, wl.ridge, w_d, 0, None, stream)
+        ev[2].record(stream)
+        out = r.adjoint_device(m0_d, u_d, grad_states_dev=g_d, stream=stream)
+        ev[3].record(stream)
+        return ev, loss, out
+
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [one_step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    wall_s = (time.perf_counter() - t0) / steps
+    fwd_ms = sum(ev[0].elapsed_time(ev[1]) for ev, _, _ in runs) / steps
+    loss_ms = sum(ev[1].elapsed_time(ev[2]) for ev, _, _ in runs) / steps
+    adj_ms = sum(ev[2].elapsed_time(ev[3]) for ev, _, _ in runs) / steps
+    path = r.path
+    out = runs[-1][2]
+    finite = bool(torch.isfinite(out["W"]).all()) and bool(torch.isfinite(out["scalars"]).all())
+    r.close()
+    # passes over W (or its transpose) the adjoint makes: the forward with
+    # checkpoints, the recompute of every segment but the last, the reverse
+    ld = (wl.n + 63) // 64 * 64
+    per_step = (4 * (3 + 2) + 1) * ld * elem
+    seg = max(1, min(wl.steps, (4 << 30) // per_step))
+    last = wl.steps - (wl.steps - 1) // seg * seg
+    stage_passes = 4 * (wl.steps + (wl.steps - last) + wl.steps)
+    algo = stage_passes * float(wl.n) * wl.n * elem
+    return {
+        "workload": f"adjoint/{name}", "n": wl.n, "dtype": dtype, "samples": wl.samples,
+        "rk4_steps": wl.steps, "forward_path": path, "checkpoint_every": seg,
+        "value": wl.n * wl.steps / (adj_ms * 1e-3), "unit": "node-steps/s (gradient)",
+        "ms_per_step": wall_s * 1e3, "forward_ms": fwd_ms, "loss_ms": loss_ms, "adjoint_ms": adj_ms,
+        "adjoint_over_forward": adj_ms / fwd_ms, "us_per_rk4_step": adj_ms * 1e3 / wl.steps,
+        "stage_passes_over_W": stage_passes, "algo_bytes": algo,
+        "effective_gbs": algo / (adj_ms * 1e-3) / 1e9, "hbm_frac": algo / (adj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "ridge_objective": runs[-1][1], "gradients_finite": finite,
+    }
+
+
 def run_streams_workload(stx, torch, name: str, steps: int, warmup: int):
     """S input streams share one reservoir (MULTI path, FP32 MFMA coupling);
     one step is the run of every stream plus one readout per stream.  The
@@ -385,6 +457,8 @@ def main():
     ap.add_argument("--workload", default="sto10k")
     ap.add_argument("--dtype", default="f32", choices=("f32", "f64"))
     ap.add_argument("--no-also", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--adjoint", default=None, metavar="WORKLOAD:DTYPE:SAMPLES",
+                    help="time only the adjoint line for this workload (e.g. sto10k:f32:50)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--samples", type=int, default=None,
                     help="run only the first SAMPLES input samples of the main workload (short profiled runs)")
@@ -422,6 +496,11 @@ def main():
         log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
         del src, dst
     from workloads import STREAMS, SWEEPS
+    if args.adjoint:
+        name, dt, samples = args.adjoint.split(":")
+        res = run_adjoint_workload(stx, torch, name, dt, int(samples), args.steps, args.warmup)
+        print(json.dumps({"adjoint": res}), flush=True)
+        return
     if args.workload in SWEEPS or args.workload in STREAMS:
         if args.workload in SWEEPS:
             res = run_sweep_workload(stx, torch, args.workload, args.steps, args.warmup, samples=args.samples,
@@ -465,6 +544,11 @@ def main():
         res = run_streams_workload(stx, torch, "streams64", 1, 1)
         log(json.dumps(res))
         also.append(res)
+        for name, dt, samples in (("sto10k", "f32", 50), ("sto1k", "f64", 200)):
+            log("also adjoint", name, dt, samples)
+            res = run_adjoint_workload(stx, torch, name, dt, samples, 1, 1)
+            log(json.dumps(res))
+            also.append(res)
     cpu = None
     if not args.no_cpu:
         log("cpu baseline")

@@ -150,6 +150,60 @@ sto_status reservoir_run(sto_reservoir *r, const double *u, int64_t steps, doubl
 sto_status reservoir_run_device(sto_reservoir *r, const void *u_dev, int64_t steps,
                                 void *states_dev, void *hip_stream);
 
+/*
+ * reservoir_adjoint_device -- gradients of a loss on the records of a run:
+ * the exact derivative of the discrete RK4 map of Eq. (gov) with the
+ * coupling of Eq. (coup) and the input field of Eq. (in) (paper, Sec. 3.1
+ * and 3.2), by reverse-mode differentiation of every RK4 stage.  The paper
+ * has no adjoint; the derivatives are those of its integrator.
+ *
+ * The run is recomputed from m_start over u (the handle's current state is
+ * neither used nor changed), and L enters only through its gradient:
+ *   m_start_dev      device, n*3 elements of the handle's dtype, AoS: the
+ *                    state the run starts from
+ *   u_dev            device, (steps/substeps)*n_in doubles: the run's inputs
+ *   steps            RK4 steps, a non-negative multiple of substeps
+ *   grad_states_dev  device, (steps/substeps)*n*3 dtype: dL/d(record s), the
+ *                    records being those reservoir_run writes; NULL: zero
+ *   grad_final_dev   device, n*3 dtype: dL/d(state after the run); NULL: zero
+ * Outputs (device, overwritten; each may be NULL to skip it):
+ *   grad_W_dev       n*n dtype, row-major, no padding: dL/dW
+ *   grad_w_in_dev    n*n_in dtype: dL/dw_in
+ *   grad_m0_dev      n*3 dtype, AoS: dL/dm_start
+ *   grad_scalars_dev 4 doubles: dL/da_cp, dL/da_in, dL/dh_s, dL/dh_appl
+ *                    (the dimensionless constants of sto_params)
+ *   checkpoint_every RK4 steps per recomputed segment; 0: the library
+ *                    chooses (the whole run when its stage trace fits a 4 GiB
+ *                    workspace).  Smaller segments use less memory and
+ *                    recompute more of the forward.
+ *   hip_stream       hipStream_t to enqueue on (NULL: the null stream)
+ * The forward is run from m_start and a state checkpoint kept at the start of
+ * every segment; each segment is recomputed with its stage trace and
+ * reversed.  The call allocates its workspace (about
+ * checkpoint_every * (4*(3+2C)+1) * ld elements, C = 1 or 3 coupled
+ * components, ld = n rounded up to 64) plus one transpose of W kept by the
+ * handle, and returns after the stream has finished.  FP32 handles compute
+ * the adjoint in FP32 (the scalar sums in FP64).
+ * Errors: STO_E_INVALID (arguments), STO_E_UNSUPPORTED (S > 1 streams),
+ * STO_E_NONFINITE (the recomputed state is not finite; the message names
+ * the sample), STO_E_NOMEM, STO_E_DEVICE.
+ */
+sto_status reservoir_adjoint_device(sto_reservoir *r, const void *m_start_dev, const void *u_dev, int64_t steps,
+                                    const void *grad_states_dev, const void *grad_final_dev, void *grad_W_dev,
+                                    void *grad_w_in_dev, void *grad_m0_dev, double *grad_scalars_dev,
+                                    int64_t checkpoint_every, void *hip_stream);
+
+/*
+ * reservoir_adjoint -- reservoir_adjoint_device on host arrays of doubles
+ * (m_start n*3, u (steps/substeps)*n_in, grad_states, grad_final, and the
+ * outputs grad_W n*n, grad_w_in n*n_in, grad_m0 n*3, grad_scalars 4), on the
+ * handle's stream.  Inputs are checked for finiteness (STO_E_NONFINITE).
+ */
+sto_status reservoir_adjoint(sto_reservoir *r, const double *m_start, const double *u, int64_t steps,
+                             const double *grad_states, const double *grad_final, double *grad_W,
+                             double *grad_w_in, double *grad_m0, double *grad_scalars,
+                             int64_t checkpoint_every);
+
 /* reservoir_get_state / reservoir_set_state -- copy the current state
  * (host, n*3 doubles, AoS) out of / into the handle.  set_state checks
  * finiteness only; it does not renormalise. */
@@ -247,6 +301,26 @@ sto_status readout_fit(const double *states, int64_t T, int64_t n, const double 
 sto_status readout_fit_device(const void *states_dev, int32_t dtype, int64_t T, int64_t n,
                               const void *y_dev, int64_t washout, double lambda, int32_t features,
                               void *w_out_dev, double *nmse_out, void *hip_stream);
+
+/*
+ * readout_grad_device -- the ridge objective at its optimum and its gradient
+ * with respect to the records, the loss to feed reservoir_adjoint_device.
+ *   J = (|Phi w - y|^2 + lambda |w|^2) / T', T' = T - washout fitted rows,
+ *   w the weights readout_fit_device returned for the same arguments.
+ * w minimises the objective, so its derivative in w vanishes and
+ * dJ/dPhi = (2/T') (Phi w - y) w^T exactly (envelope theorem); records
+ * before the washout and components that are not features get zero.
+ *   states_dev, dtype, T, n, y_dev, washout, lambda, features
+ *               as readout_fit_device
+ *   w_dev       device, F + 1 doubles: the fitted weights, bias last
+ *   grad_dev    device, T*n*3 elements of dtype: dJ/d(records), overwritten
+ *   loss_out    host, 1 double: J (may be NULL)
+ *   hip_stream  hipStream_t to enqueue on; returns after the stream finished
+ * Errors: STO_E_INVALID, STO_E_UNSUPPORTED (as readout_fit), STO_E_DEVICE.
+ */
+sto_status readout_grad_device(const void *states_dev, int32_t dtype, int64_t T, int64_t n, const void *y_dev,
+                               int64_t washout, double lambda, int32_t features, const void *w_dev,
+                               void *grad_dev, double *loss_out, void *hip_stream);
 
 /*
  * sto_read_bandwidth -- diagnostic: HBM read bandwidth this device attains

@@ -114,6 +114,13 @@ def _load():
     lib.sto_set_stream_variant.restype = ctypes.c_int
     lib.sto_read_bandwidth.argtypes = [ctypes.c_int64, ctypes.c_int32, dp]
     lib.sto_read_bandwidth.restype = ctypes.c_int
+    lib.reservoir_adjoint.argtypes = [H, dp, dp, ctypes.c_int64, dp, dp, dp, dp, dp, dp, ctypes.c_int64]
+    lib.reservoir_adjoint.restype = ctypes.c_int
+    lib.reservoir_adjoint_device.argtypes = [H, vp, vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp, ctypes.c_int64, vp]
+    lib.reservoir_adjoint_device.restype = ctypes.c_int
+    lib.readout_grad_device.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, vp, ctypes.c_int64,
+                                        ctypes.c_double, ctypes.c_int32, vp, vp, dp, vp]
+    lib.readout_grad_device.restype = ctypes.c_int
     lib.sto_last_error.restype = ctypes.c_char_p
     for name in ("reservoir_create", "reservoir_create_streams", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
                  "reservoir_set_state", "readout_fit"):
@@ -126,7 +133,10 @@ _lib = _load()
 EXPORTED = ("reservoir_create", "reservoir_create_streams", "reservoir_streams", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
             "reservoir_set_state", "reservoir_path", "reservoir_destroy", "readout_fit", "readout_fit_device",
             "sweep_create", "sweep_nodes", "sweep_run", "sweep_run_device", "sweep_get_state", "sweep_destroy",
+            "reservoir_adjoint", "reservoir_adjoint_device", "readout_grad_device",
             "sto_read_bandwidth", "sto_set_stream_variant", "sto_last_error")
+
+SCALAR_NAMES = ("a_cp", "a_in", "h_s", "h_appl")
 
 
 def lib():
@@ -244,6 +254,60 @@ def readout_fit_device(states_dev, y_dev, washout: int, lam: float, features: in
     return w_out_dev, float(nmse[0])
 
 
+def _vp(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def reservoir_adjoint(h, n: int, n_in: int, m_start, u, steps: int, grad_states=None, grad_final=None,
+                      checkpoint_every: int = 0) -> dict:
+    """Host arrays in and out (float64).  Returns {"W", "w_in", "m0", "a_cp",
+    "a_in", "h_s", "h_appl"}: the gradients of the loss whose gradient with
+    respect to the records is grad_states (and to the final state grad_final)."""
+    m_start = _f64(m_start, (n, 3))
+    u = _f64(u).reshape(-1, n_in)
+    gs = _f64(grad_states) if grad_states is not None else None
+    gf = _f64(grad_final, (n, 3)) if grad_final is not None else None
+    out = {"W": np.empty((n, n)), "w_in": np.empty((n, n_in)), "m0": np.empty((n, 3))}
+    scal = np.empty(4)
+    _check(_lib.reservoir_adjoint(h, _dptr(m_start), _dptr(u), steps, _dptr(gs) if gs is not None else None,
+                                  _dptr(gf) if gf is not None else None, _dptr(out["W"]), _dptr(out["w_in"]),
+                                  _dptr(out["m0"]), _dptr(scal), checkpoint_every))
+    out.update({k: float(v) for k, v in zip(SCALAR_NAMES, scal)})
+    return out
+
+
+def reservoir_adjoint_device(h, m_start_dev, u_dev, steps: int, grad_states_dev=None, grad_final_dev=None,
+                             grad_W_dev=None, grad_w_in_dev=None, grad_m0_dev=None, grad_scalars_dev=None,
+                             checkpoint_every: int = 0, stream=None):
+    """CUDA tensors of the handle's dtype (u and the scalars float64); every
+    output tensor may be None to skip it."""
+    import torch
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    _check(_lib.reservoir_adjoint_device(h, _vp(m_start_dev), _vp(u_dev), steps, _vp(grad_states_dev),
+                                         _vp(grad_final_dev), _vp(grad_W_dev), _vp(grad_w_in_dev), _vp(grad_m0_dev),
+                                         _vp(grad_scalars_dev), checkpoint_every, ctypes.c_void_p(s)))
+
+
+def readout_grad_device(states_dev, y_dev, washout: int, lam: float, w_dev, features: int = 0, grad_dev=None,
+                        stream=None):
+    """Ridge objective at its optimum J and dJ/d(records) (CUDA tensor like
+    states_dev).  Returns (grad_dev, J)."""
+    import torch
+    assert states_dev.is_cuda and states_dev.is_contiguous() and states_dev.dim() == 3
+    assert y_dev.is_cuda and y_dev.dtype == torch.float64 and y_dev.is_contiguous()
+    assert w_dev.is_cuda and w_dev.dtype == torch.float64 and w_dev.is_contiguous()
+    T, n, _ = states_dev.shape
+    if grad_dev is None:
+        grad_dev = torch.empty_like(states_dev)
+    assert grad_dev.dtype == states_dev.dtype and grad_dev.shape == states_dev.shape and grad_dev.is_contiguous()
+    dtype = {torch.float64: STO_F64, torch.float32: STO_F32}[states_dev.dtype]
+    loss = np.empty(1)
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    _check(_lib.readout_grad_device(_vp(states_dev), dtype, T, n, _vp(y_dev), washout, lam, features, _vp(w_dev),
+                                    _vp(grad_dev), _dptr(loss), ctypes.c_void_p(s)))
+    return grad_dev, float(loss[0])
+
+
 def sto_set_stream_variant(rows: int, unroll: int):
     """Launch shape of the stream kernels for this process ((0, 0): table)."""
     _check(_lib.sto_set_stream_variant(rows, unroll))
@@ -303,6 +367,33 @@ class Reservoir:
         s = (stream or torch.cuda.current_stream()).cuda_stream
         reservoir_run_device(self.h, u_dev.data_ptr(), samples * self.substeps,
                              states_dev.data_ptr() if states_dev is not None else None, s)
+
+    def adjoint(self, m_start, u, grad_states=None, grad_final=None, checkpoint_every: int = 0) -> dict:
+        """Gradients (host, float64) of the run from m_start over u; see reservoir_adjoint."""
+        u = _f64(u).reshape(-1, self.n_in)
+        return reservoir_adjoint(self.h, self.n, self.n_in, m_start, u, len(u) * self.substeps, grad_states,
+                                 grad_final, checkpoint_every)
+
+    def adjoint_device(self, m_start_dev, u_dev, grad_states_dev=None, grad_final_dev=None, want=("W", "w_in", "m0",
+                       "scalars"), checkpoint_every: int = 0, stream=None) -> dict:
+        """Gradients as CUDA tensors of the handle's dtype (scalars: float64 (4,))."""
+        import torch
+        dt = torch.float64 if self.dtype == "f64" else torch.float32
+        dev = u_dev.device
+        out = {}
+        if "W" in want:
+            out["W"] = torch.empty((self.n, self.n), dtype=dt, device=dev)
+        if "w_in" in want:
+            out["w_in"] = torch.empty((self.n, self.n_in), dtype=dt, device=dev)
+        if "m0" in want:
+            out["m0"] = torch.empty((self.n, 3), dtype=dt, device=dev)
+        if "scalars" in want:
+            out["scalars"] = torch.empty(4, dtype=torch.float64, device=dev)
+        samples = u_dev.numel() // self.n_in
+        reservoir_adjoint_device(self.h, m_start_dev, u_dev, samples * self.substeps, grad_states_dev,
+                                 grad_final_dev, out.get("W"), out.get("w_in"), out.get("m0"), out.get("scalars"),
+                                 checkpoint_every, stream)
+        return out
 
     def get_state(self) -> np.ndarray:
         m = reservoir_get_state(self.h, self.n * self.streams)

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/sto_reservoir.h"
+#include "sto_adjoint.hpp"
 #include "sto_internal.hpp"
 #include "stream_tune.hpp"
 
@@ -111,6 +112,7 @@ struct sto_reservoir {
     int resident_grid = 0;
     size_t elem = 8;
     void* W = nullptr;
+    void* Wt = nullptr;     // transpose of W, made by the first adjoint call
     void* w_in = nullptr;
     void* m = nullptr;
     void* ms[2] = {nullptr, nullptr};
@@ -169,7 +171,8 @@ sto::DevState<T> dev_state(const sto_reservoir* r) {
 }
 
 void free_all(sto_reservoir* r) {
-    void* ptrs[] = {r->W, r->w_in, r->m, r->ms[0], r->ms[1], r->acc, r->xchg, r->bad, r->sync, r->u_dev, r->states_dev};
+    void* ptrs[] = {r->W, r->Wt, r->w_in, r->m, r->ms[0], r->ms[1], r->acc, r->xchg, r->bad, r->sync, r->u_dev,
+                    r->states_dev};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (r->stream) (void)hipStreamDestroy(r->stream);
@@ -291,6 +294,117 @@ sto_status run_device_impl(sto_reservoir* r, const double* u_dev, int64_t steps,
         return fail(STO_E_DEVICE, "grid barrier timed out: the resident kernel's workgroups were not co-resident");
     if (bad != none)
         return fail(STO_E_NONFINITE, "state not finite after sample %d", bad);
+    return STO_OK;
+}
+
+// Workspace budget of the adjoint's stage trace when the caller lets the
+// library choose the segment length.
+constexpr int64_t kAdjointTraceBudget = int64_t(4) << 30;
+
+template <typename T>
+sto_status adjoint_dispatch(sto_reservoir* r, const void* m_start, const double* u, int64_t steps, const void* g_rec,
+                            const void* g_fin, void* g_W, void* g_win, void* g_m0, double* g_scal, int64_t seg,
+                            hipStream_t stream) {
+    sto::AdjArgs<T> a;
+    a.W = static_cast<const T*>(r->W);
+    a.Wt = static_cast<const T*>(r->Wt);
+    a.w_in = static_cast<const T*>(r->w_in);
+    a.n = (int)r->n;
+    a.n_in = (int)r->n_in;
+    a.ld = r->ld;
+    a.k = make_coef<T>(r->prm);
+    a.substeps = r->prm.substeps;
+    a.renorm = r->prm.renormalize;
+    a.xyz = r->prm.coupling == STO_COUPLE_XYZ;
+    a.u = u;
+    a.steps = steps;
+    a.m_start = static_cast<const T*>(m_start);
+    a.g_rec = static_cast<const T*>(g_rec);
+    a.g_fin = static_cast<const T*>(g_fin);
+    a.g_W = static_cast<T*>(g_W);
+    a.g_win = static_cast<T*>(g_win);
+    a.g_m0 = static_cast<T*>(g_m0);
+    a.g_scal = g_scal;
+    a.seg_steps = seg;
+    a.bad = r->bad;
+    a.stream = stream;
+    hipError_t e = sto::adjoint_run<T>(a);
+    if (e != hipSuccess) return hip_fail(e, "adjoint");
+    return STO_OK;
+}
+
+sto_status adjoint_device_impl(sto_reservoir* r, const void* m_start, const void* u_dev, int64_t steps,
+                               const void* g_rec, const void* g_fin, void* g_W, void* g_win, void* g_m0,
+                               double* g_scal, int64_t checkpoint_every, hipStream_t stream) {
+    if (!r) return fail(STO_E_INVALID, "handle is NULL");
+    if (r->streams != 1) return fail(STO_E_UNSUPPORTED, "the adjoint needs a single-stream reservoir");
+    if (steps < 0 || steps % r->prm.substeps != 0)
+        return fail(STO_E_INVALID, "steps (%lld) must be a non-negative multiple of substeps (%d)",
+                    (long long)steps, r->prm.substeps);
+    if (steps / r->prm.substeps > INT_MAX) return fail(STO_E_INVALID, "too many samples");
+    if (!m_start) return fail(STO_E_INVALID, "m_start is NULL");
+    if (steps > 0 && !u_dev) return fail(STO_E_INVALID, "u is NULL");
+    if (checkpoint_every < 0) return fail(STO_E_INVALID, "checkpoint_every must be >= 0");
+    int64_t seg = checkpoint_every;
+    if (seg == 0) {
+        const int64_t per = sto::adjoint_trace_bytes_per_step(r->ld, (int)r->elem, r->prm.coupling == STO_COUPLE_XYZ);
+        seg = std::max<int64_t>(1, std::min<int64_t>(std::max<int64_t>(steps, 1), kAdjointTraceBudget / per));
+    }
+    if (!r->Wt) {
+        const size_t wb = (size_t)r->n * r->ld * r->elem;
+        HIP_TRY(hipMalloc(&r->Wt, wb), "hipMalloc W^T");
+        HIP_TRY(hipMemsetAsync(r->Wt, 0, wb, stream), "W^T clear");
+        hipError_t e = r->dtype == STO_F64
+                           ? sto::transpose_matrix<double>(static_cast<const double*>(r->W),
+                                                           static_cast<double*>(r->Wt), (int)r->n, r->ld, stream)
+                           : sto::transpose_matrix<float>(static_cast<const float*>(r->W), static_cast<float*>(r->Wt),
+                                                          (int)r->n, r->ld, stream);
+        if (e != hipSuccess) {
+            (void)hipFree(r->Wt);
+            r->Wt = nullptr;
+            return hip_fail(e, "transpose");
+        }
+    }
+    const int none = INT_MAX;
+    HIP_TRY(hipMemcpyAsync(r->bad, &none, sizeof(int), hipMemcpyHostToDevice, stream), "flag reset");
+    const double* u = static_cast<const double*>(u_dev);
+    sto_status st = r->dtype == STO_F64
+                        ? adjoint_dispatch<double>(r, m_start, u, steps, g_rec, g_fin, g_W, g_win, g_m0, g_scal, seg,
+                                                   stream)
+                        : adjoint_dispatch<float>(r, m_start, u, steps, g_rec, g_fin, g_W, g_win, g_m0, g_scal, seg,
+                                                  stream);
+    if (st != STO_OK) return st;
+    int bad = none;
+    HIP_TRY(hipMemcpyAsync(&bad, r->bad, sizeof(int), hipMemcpyDeviceToHost, stream), "flag read");
+    HIP_TRY(hipStreamSynchronize(stream), "adjoint");
+    if (bad != none) return fail(STO_E_NONFINITE, "state not finite after sample %d", bad);
+    return STO_OK;
+}
+
+// Device copy of a host array of doubles in the handle's type.
+sto_status to_device(const sto_reservoir* r, const double* h, int64_t count, void** out) {
+    *out = nullptr;
+    if (!h) return STO_OK;
+    const size_t bytes = (size_t)std::max<int64_t>(count, 1) * r->elem;
+    HIP_TRY(hipMalloc(out, bytes), "hipMalloc");
+    if (r->dtype == STO_F64) {
+        HIP_TRY(hipMemcpy(*out, h, (size_t)count * 8, hipMemcpyHostToDevice), "upload");
+    } else {
+        std::vector<float> f(h, h + count);
+        HIP_TRY(hipMemcpy(*out, f.data(), (size_t)count * 4, hipMemcpyHostToDevice), "upload");
+    }
+    return STO_OK;
+}
+
+sto_status from_device(const sto_reservoir* r, const void* d, int64_t count, double* h) {
+    if (!h) return STO_OK;
+    if (r->dtype == STO_F64) {
+        HIP_TRY(hipMemcpy(h, d, (size_t)count * 8, hipMemcpyDeviceToHost), "download");
+    } else {
+        std::vector<float> f((size_t)count);
+        HIP_TRY(hipMemcpy(f.data(), d, (size_t)count * 4, hipMemcpyDeviceToHost), "download");
+        for (int64_t i = 0; i < count; ++i) h[i] = f[i];
+    }
     return STO_OK;
 }
 
@@ -588,6 +702,78 @@ sto_status reservoir_run(sto_reservoir* r, const double* u, int64_t steps, doubl
         g_err = msg;
     }
     return st;
+}
+
+sto_status reservoir_adjoint_device(sto_reservoir* r, const void* m_start_dev, const void* u_dev, int64_t steps,
+                                    const void* grad_states_dev, const void* grad_final_dev, void* grad_W_dev,
+                                    void* grad_w_in_dev, void* grad_m0_dev, double* grad_scalars_dev,
+                                    int64_t checkpoint_every, void* hip_stream) {
+    return adjoint_device_impl(r, m_start_dev, u_dev, steps, grad_states_dev, grad_final_dev, grad_W_dev,
+                               grad_w_in_dev, grad_m0_dev, grad_scalars_dev, checkpoint_every,
+                               static_cast<hipStream_t>(hip_stream));
+}
+
+sto_status reservoir_adjoint(sto_reservoir* r, const double* m_start, const double* u, int64_t steps,
+                             const double* grad_states, const double* grad_final, double* grad_W, double* grad_w_in,
+                             double* grad_m0, double* grad_scalars, int64_t checkpoint_every) {
+    if (!r) return fail(STO_E_INVALID, "handle is NULL");
+    if (r->streams != 1) return fail(STO_E_UNSUPPORTED, "the adjoint needs a single-stream reservoir");
+    if (steps < 0 || steps % r->prm.substeps != 0)
+        return fail(STO_E_INVALID, "steps (%lld) must be a non-negative multiple of substeps (%d)",
+                    (long long)steps, r->prm.substeps);
+    if (!m_start) return fail(STO_E_INVALID, "m_start is NULL");
+    const int64_t samples = steps / r->prm.substeps, n = r->n;
+    if (samples > 0 && !u) return fail(STO_E_INVALID, "u is NULL");
+    if (!finite_all(m_start, 3 * n) || (samples > 0 && !finite_all(u, samples * r->n_in)) ||
+        (grad_states && !finite_all(grad_states, samples * n * 3)) || (grad_final && !finite_all(grad_final, 3 * n)))
+        return fail(STO_E_NONFINITE, "non-finite input");
+    void *m_d = nullptr, *gr_d = nullptr, *gf_d = nullptr, *gw_d = nullptr, *gwin_d = nullptr, *gm_d = nullptr;
+    double *u_d = nullptr, *gs_d = nullptr;
+    auto release = [&]() {
+        void* ptrs[] = {m_d, gr_d, gf_d, gw_d, gwin_d, gm_d, u_d, gs_d};
+        for (void* p : ptrs)
+            if (p) (void)hipFree(p);
+    };
+    sto_status st = to_device(r, m_start, 3 * n, &m_d);
+    if (st == STO_OK) st = to_device(r, grad_states, samples * n * 3, &gr_d);
+    if (st == STO_OK) st = to_device(r, grad_final, 3 * n, &gf_d);
+    if (st == STO_OK && samples > 0) {
+        if (hipMalloc(&u_d, (size_t)samples * r->n_in * 8) != hipSuccess ||
+            hipMemcpy(u_d, u, (size_t)samples * r->n_in * 8, hipMemcpyHostToDevice) != hipSuccess)
+            st = fail(STO_E_DEVICE, "u upload");
+    }
+    if (st == STO_OK && grad_W && hipMalloc(&gw_d, (size_t)n * n * r->elem) != hipSuccess)
+        st = fail(STO_E_NOMEM, "hipMalloc dL/dW");
+    if (st == STO_OK && grad_w_in && hipMalloc(&gwin_d, (size_t)n * r->n_in * r->elem) != hipSuccess)
+        st = fail(STO_E_NOMEM, "hipMalloc dL/dw_in");
+    if (st == STO_OK && grad_m0 && hipMalloc(&gm_d, (size_t)n * 3 * r->elem) != hipSuccess)
+        st = fail(STO_E_NOMEM, "hipMalloc dL/dm0");
+    if (st == STO_OK && grad_scalars && hipMalloc(&gs_d, 4 * sizeof(double)) != hipSuccess)
+        st = fail(STO_E_NOMEM, "hipMalloc scalars");
+    if (st == STO_OK)
+        st = adjoint_device_impl(r, m_d, u_d, steps, gr_d, gf_d, gw_d, gwin_d, gm_d, gs_d, checkpoint_every,
+                                 r->stream);
+    if (st == STO_OK) st = from_device(r, gw_d, n * n, grad_W);
+    if (st == STO_OK) st = from_device(r, gwin_d, n * r->n_in, grad_w_in);
+    if (st == STO_OK) st = from_device(r, gm_d, n * 3, grad_m0);
+    if (st == STO_OK && grad_scalars && hipMemcpy(grad_scalars, gs_d, 4 * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        st = fail(STO_E_DEVICE, "download");
+    release();
+    return st;
+}
+
+sto_status readout_grad_device(const void* states_dev, int32_t dtype, int64_t T, int64_t n, const void* y_dev,
+                               int64_t washout, double lambda, int32_t features, const void* w_dev, void* grad_dev,
+                               double* loss_out, void* hip_stream) {
+    if (!states_dev || !y_dev || !w_dev || !grad_dev) return fail(STO_E_INVALID, "NULL argument");
+    if (dtype != STO_F64 && dtype != STO_F32) return fail(STO_E_INVALID, "unknown dtype %d", dtype);
+    sto_status st = readout_check(T, n, washout, lambda, features);
+    if (st != STO_OK) return st;
+    hipError_t e = sto::readout_grad(states_dev, dtype == STO_F32, (int)T, (int)washout, (int)n, features,
+                                     static_cast<const double*>(y_dev), static_cast<const double*>(w_dev), lambda,
+                                     grad_dev, loss_out, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "readout gradient");
+    return STO_OK;
 }
 
 sto_status reservoir_get_state(const sto_reservoir* r, double* m) {

@@ -1,0 +1,53 @@
+// Internal interface of the adjoint (reverse-mode gradient) of the RK4
+// trajectory: the host runtime fills an AdjArgs and calls adjoint_run.
+#pragma once
+
+#include "sto_internal.hpp"
+
+namespace sto {
+
+template <typename T>
+struct AdjArgs {
+    // reservoir (device, the handle's buffers; read only)
+    const T* W;          // n x ld, row-major, zero padding
+    const T* Wt;         // n x ld, the transpose of W, zero padding
+    const T* w_in;       // n x n_in
+    int n, n_in;
+    int64_t ld;
+    Coef<T> k;
+    int substeps, renorm, xyz;
+    // run
+    const double* u;     // device, (steps / substeps) x n_in
+    int64_t steps;
+    const T* m_start;    // device, n x 3 AoS
+    const T* g_rec;      // device, (steps / substeps) x n x 3 AoS: dL/d(record); or nullptr
+    const T* g_fin;      // device, n x 3 AoS: dL/d(final state); or nullptr
+    // outputs (device; each may be nullptr)
+    T* g_W;              // n x n, row-major, no padding
+    T* g_win;            // n x n_in
+    T* g_m0;             // n x 3 AoS
+    double* g_scal;      // 4: a_cp, a_in, h_s, h_appl
+    int64_t seg_steps;   // RK4 steps per recomputed segment (>= 1)
+    int* bad;            // device flag: first non-finite sample (INT_MAX: none)
+    hipStream_t stream;
+};
+
+// Bytes of the per-step stage trace (the workspace per step of a segment).
+int64_t adjoint_trace_bytes_per_step(int64_t ld, int elem_bytes, int xyz);
+
+template <typename T>
+hipError_t transpose_matrix(const T* W, T* Wt, int n, int64_t ld, hipStream_t st);
+
+// Runs the forward from m_start with checkpoints, then reverses it segment
+// by segment.  Allocates and frees its own workspace.
+template <typename T>
+hipError_t adjoint_run(const AdjArgs<T>& a);
+
+// Gradient of the ridge objective at its optimum with respect to the records
+// (readout.hip).  rec_dev: T x n x 3 records (FP32 if rec_f32); w_dev: the
+// fitted weights; grad_dev: T x n x 3 of the same type; loss_host may be null.
+hipError_t readout_grad(const void* rec_dev, int rec_f32, int T, int washout, int n, int features,
+                        const double* y_dev, const double* w_dev, double lambda, void* grad_dev, double* loss_host,
+                        hipStream_t stream);
+
+}  // namespace sto

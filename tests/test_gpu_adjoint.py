@@ -1,0 +1,234 @@
+"""GPU parity of the adjoint (reservoir_adjoint*) and the readout gradient
+(readout_grad_device) against the oracle's discrete adjoint, and the
+torch.autograd wrappers end to end.
+
+Tolerances.  In FP64 the forward trajectory the adjoint differentiates is
+bitwise the oracle's (exactly rounded coupling sums); the adjoint's own sums
+(W^T bbar, the dL/dW product, the scalar sums) are plain FP64 in an order
+of their own.  Each of them carries a relative rounding error of a few
+units of 2^-53 times the number of terms, amplified along the reversed
+trajectory by at most the growth of the tangent dynamics over the horizon
+(a factor e^(lambda_max t) < 2 over the 20-60 steps used here), so the
+bound written below, 1e-9 of the largest gradient entry, leaves a margin of
+more than 10^3.  FP32 computes the whole adjoint in FP32 (scalar sums in
+FP64): relative error ~ 1e-7 per operation, grown over the horizon, hence
+2e-4 of the largest entry.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from common import lib_params, oracle_params, random_case
+from oracle import adjoint, readout, sto
+
+pytestmark = pytest.mark.gpu
+F64_TOL = 1e-9
+F32_TOL = 2e-4
+SCALARS = ("a_cp", "a_in", "h_s", "h_appl")
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def stx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2312_01121_amd
+    return paper_2312_01121_amd
+
+
+def rel_err(got, ref):
+    got, ref = np.asarray(got, dtype=np.float64), np.asarray(ref, dtype=np.float64)
+    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def compare(got, ref, tol, label):
+    errs = {k: rel_err(got[k], ref[k]) for k in ("W", "w_in", "m0")}
+    scal = np.array([got[k] for k in SCALARS])
+    scal_ref = np.array([ref[k] for k in SCALARS])
+    errs["scalars"] = rel_err(scal, scal_ref)
+    say(label, {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= tol, (label, k, v)
+
+
+def case(n, n_in=1, samples=4, substeps=5, seed=0, coupling="x", renormalize=False, a_cp=0.3, a_in=0.7):
+    w, w_in, m0, u = random_case(n, n_in=n_in, seed=seed, samples=samples, spread=0.3)
+    prm = oracle_params(a_cp=a_cp, a_in=a_in, substeps=substeps, coupling=coupling, renormalize=renormalize)
+    rng = np.random.default_rng(seed + 100)
+    g_rec = rng.standard_normal((samples, n, 3))
+    g_fin = rng.standard_normal((n, 3))
+    return w, w_in, m0, u, prm, g_rec, g_fin
+
+
+F64_CASES = [
+    # n, n_in, coupling, renormalize, checkpoint_every
+    (1, 1, "x", False, 0),
+    (16, 1, "x", False, 7),
+    (16, 2, "x", False, 1),
+    (37, 1, "xyz", False, 3),
+    (130, 1, "x", True, 0),
+    (130, 2, "xyz", True, 7),
+    (257, 1, "x", False, 6),
+]
+
+
+@pytest.mark.parametrize("n,n_in,coupling,renorm,seg", F64_CASES)
+def test_adjoint_matches_oracle_f64(stx, n, n_in, coupling, renorm, seg):
+    w, w_in, m0, u, prm, g_rec, g_fin = case(n, n_in=n_in, coupling=coupling, renormalize=renorm)
+    say(f"adjoint f64 n={n} n_in={n_in} coupling={coupling} renorm={renorm} seg={seg}")
+    ref = adjoint.run_adjoint(w, w_in, m0, u, prm, g_rec, g_fin)
+    with stx.Reservoir(w, w_in, m0, lib_params(prm, "f64")) as r:
+        got = r.adjoint(m0, u, g_rec, g_fin, checkpoint_every=seg)
+        # the handle's own state is neither used nor changed
+        assert np.array_equal(r.get_state(), m0)
+    compare(got, ref, F64_TOL, f"n={n}")
+
+
+@pytest.mark.parametrize("n,coupling,renorm", [(16, "x", False), (100, "xyz", True), (300, "x", False)])
+def test_adjoint_matches_oracle_f32(stx, n, coupling, renorm):
+    w, w_in, m0, u, prm, g_rec, g_fin = case(n, coupling=coupling, renormalize=renorm)
+    # the oracle differentiates the inputs as the FP32 library holds them
+    # (the library rounds m0 itself: it requires a unit-norm m0 on creation)
+    w, w_in = (np.float32(a).astype(np.float64) for a in (w, w_in))
+    g_rec, g_fin = np.float32(g_rec).astype(np.float64), np.float32(g_fin).astype(np.float64)
+    say(f"adjoint f32 n={n} coupling={coupling} renorm={renorm}")
+    ref = adjoint.run_adjoint(w, w_in, np.float32(m0).astype(np.float64), u, prm, g_rec, g_fin, dot="blas")
+    with stx.Reservoir(w, w_in, m0, lib_params(prm, "f32")) as r:
+        got = r.adjoint(m0, u, g_rec, g_fin, checkpoint_every=5)
+    compare(got, ref, F32_TOL, f"f32 n={n}")
+
+
+@pytest.mark.parametrize("n,dtype", [(1000, "f64"), (2500, "f32")])
+def test_adjoint_large_n(stx, n, dtype):
+    """Several tiles of the streaming and product kernels and a ragged tail
+    (2500 = 39 x 64 + 4), over a short horizon the oracle finishes quickly."""
+    w, w_in, m0, u, prm, g_rec, g_fin = case(n, samples=1, substeps=3, seed=5)
+    m0_ref = m0
+    if dtype == "f32":
+        w, w_in = (np.float32(a).astype(np.float64) for a in (w, w_in))
+        m0_ref = np.float32(m0).astype(np.float64)
+        g_rec, g_fin = np.float32(g_rec).astype(np.float64), np.float32(g_fin).astype(np.float64)
+    say(f"adjoint large n={n} {dtype}")
+    ref = adjoint.run_adjoint(w, w_in, m0_ref, u, prm, g_rec, g_fin, dot="blas")
+    with stx.Reservoir(w, w_in, m0, lib_params(prm, dtype)) as r:
+        got = r.adjoint(m0, u, g_rec, g_fin, checkpoint_every=2)
+    compare(got, ref, F64_TOL if dtype == "f64" else F32_TOL, f"large n={n}")
+
+
+def test_adjoint_segments_agree(stx):
+    """Segment length only changes where the forward is recomputed: dL/dm0 and
+    the scalars are bitwise the same, dL/dW equal up to the product's order."""
+    w, w_in, m0, u, prm, g_rec, g_fin = case(64, samples=3, substeps=5, seed=2)
+    say("adjoint segments 64")
+    with stx.Reservoir(w, w_in, m0, lib_params(prm, "f64")) as r:
+        outs = [r.adjoint(m0, u, g_rec, g_fin, checkpoint_every=s) for s in (0, 1, 4, 15)]
+    for o in outs[1:]:
+        assert np.array_equal(o["m0"], outs[0]["m0"])
+        assert np.array_equal(o["w_in"], outs[0]["w_in"])
+        for k in SCALARS:
+            assert o[k] == outs[0][k], k
+        assert rel_err(o["W"], outs[0]["W"]) <= 1e-13
+
+
+def test_adjoint_device_api(stx):
+    import torch
+    w, w_in, m0, u, prm, g_rec, g_fin = case(40, samples=3, substeps=4, seed=9)
+    say("adjoint device api 40")
+    ref = adjoint.run_adjoint(w, w_in, m0, u, prm, g_rec, None)
+    dev = torch.device("cuda")
+    with stx.Reservoir(w, w_in, m0, lib_params(prm, "f64")) as r:
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+        out = r.adjoint_device(t(m0), t(u), grad_states_dev=t(g_rec))
+        torch.cuda.synchronize()
+        got = {"W": out["W"].cpu().numpy(), "w_in": out["w_in"].cpu().numpy(), "m0": out["m0"].cpu().numpy()}
+        got.update({k: float(v) for k, v in zip(SCALARS, out["scalars"].cpu().numpy())})
+        compare(got, ref, F64_TOL, "device api")
+        # only the scalars requested
+        only = r.adjoint_device(t(m0), t(u), grad_states_dev=t(g_rec), want=("scalars",))
+        assert np.array_equal(only["scalars"].cpu().numpy(), out["scalars"].cpu().numpy())
+
+
+def test_adjoint_zero_steps(stx):
+    w, w_in, m0, u, prm, g_rec, g_fin = case(8, seed=4)
+    with stx.Reservoir(w, w_in, m0, lib_params(prm, "f64")) as r:
+        got = r.adjoint(m0, u[:0], None, g_fin)
+    assert np.array_equal(got["m0"], g_fin)
+    assert not np.any(got["W"]) and not np.any(got["w_in"])
+    assert all(got[k] == 0.0 for k in SCALARS)
+
+
+def test_adjoint_rejects_and_reports(stx):
+    w, w_in, m0, u, prm, g_rec, g_fin = case(8, seed=4)
+    with stx.Reservoir(w, w_in, m0, lib_params(prm, "f64")) as r:
+        with pytest.raises(stx.StoError) as e:
+            stx.reservoir_adjoint(r.h, 8, 1, m0, u, 7, None, None)      # not a multiple of substeps
+        assert e.value.status == stx.STO_E_INVALID
+        with pytest.raises(stx.StoError) as e:
+            r.adjoint(m0, u, checkpoint_every=-1)
+        assert e.value.status == stx.STO_E_INVALID
+    streams_prm = lib_params(oracle_params(), "f32")
+    with stx.Reservoir(w, w_in, np.stack([m0, m0]), streams_prm, streams=2) as r2:
+        with pytest.raises(stx.StoError) as e:
+            stx.reservoir_adjoint(r2.h, 8, 1, m0, u, 20, None, None)
+        assert e.value.status == stx.STO_E_UNSUPPORTED
+    # a state that becomes non-finite (lambda = -1 and m along p: 1 + lambda m.p = 0)
+    prm_bad = oracle_params(substeps=2).replace(lam=-1.0)
+    m_p = np.tile(np.array([[1.0, 0.0, 0.0]]), (8, 1))
+    with stx.Reservoir(np.zeros((8, 8)), w_in, m_p, lib_params(prm_bad, "f64")) as r3:
+        with pytest.raises(stx.StoError) as e:
+            r3.adjoint(m_p, u[:2], g_rec[:2])
+        assert e.value.status == stx.STO_E_NONFINITE
+
+
+@pytest.mark.parametrize("dtype,features", [("f64", 0), ("f32", 0), ("f64", 1)])
+def test_readout_grad_matches_oracle(stx, dtype, features):
+    import torch
+    rng = np.random.default_rng(3)
+    T, n, washout, lam = 60, 12, 6, 1e-4
+    rec = rng.standard_normal((T, n, 3))
+    if dtype == "f32":
+        rec = np.float32(rec).astype(np.float64)
+    y = rng.standard_normal(T)
+    comps = "xyz" if features else "x"
+    j_ref, w_ref, g_ref = readout.ridge_objective_grad(rec, y, washout, lam, comps)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    rec_d = torch.from_numpy(rec).to("cuda", tdt).contiguous()
+    y_d = torch.from_numpy(y).cuda()
+    w_d, _ = stx.readout_fit_device(rec_d, y_d, washout, lam, features)
+    g_d, j = stx.readout_grad_device(rec_d, y_d, washout, lam, w_d, features)
+    g = g_d.double().cpu().numpy()
+    tol = 1e-10 if dtype == "f64" else 1e-5
+    say(f"readout grad {dtype} features={features}", rel_err(g, g_ref), abs(j - j_ref) / j_ref)
+    assert rel_err(g, g_ref) <= tol and abs(j - j_ref) <= tol * j_ref
+
+
+def test_autograd_end_to_end(stx):
+    """loss.backward() through the ridge loss and the run equals the oracle's
+    adjoint driven by the oracle's ridge gradient."""
+    import torch
+    from paper_2312_01121_amd import autograd
+    n, samples, sub, washout, lam = 16, 30, 5, 5, 1e-3
+    w, w_in, m0, u = random_case(n, seed=8, samples=samples, spread=0.3)
+    prm = oracle_params(a_cp=0.3, a_in=0.7, substeps=sub)
+    y = np.tanh(np.convolve(u[:, 0], np.ones(5))[:samples])
+    say("autograd end to end 16")
+    rec, _ = sto.run(w, w_in, m0, u, prm)
+    j_ref, _, g_rec = readout.ridge_objective_grad(rec, y, washout, lam)
+    ref = adjoint.run_adjoint(w, w_in, m0, u, prm, g_rec, None)
+
+    leaf = lambda a: torch.tensor(a, dtype=torch.float64, requires_grad=True)  # noqa: E731
+    W, WIN, M0 = leaf(w), leaf(w_in), leaf(m0)
+    sc = [leaf(getattr(prm, k)) for k in SCALARS]
+    records = autograd.reservoir_records(W, WIN, M0, *sc, torch.from_numpy(u).cuda(), lib_params(prm, "f64"))
+    assert np.array_equal(records.detach().cpu().numpy(), rec)
+    loss = autograd.ridge_loss(records, torch.from_numpy(y).cuda(), washout, lam)
+    assert abs(float(loss) - j_ref) <= 1e-10 * j_ref
+    loss.backward()
+    got = {"W": W.grad.numpy(), "w_in": WIN.grad.numpy(), "m0": M0.grad.numpy()}
+    got.update({k: float(t.grad) for k, t in zip(SCALARS, sc)})
+    compare(got, ref, 1e-8, "autograd")

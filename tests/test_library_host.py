@@ -126,3 +126,17 @@ def test_presets_equal_oracle_constants(stx):
         assert a["alpha"] == b.alpha and a["lambda_stt"] == b.lam and a["dt"] == b.dt
         assert a["h_appl"] == b.h_appl and a["h_k"] == b.h_k and a["h_s"] == b.h_s
         assert tuple(a["p"]) == tuple(b.p)
+
+
+def test_adjoint_rejects_bad_arguments(stx):
+    """Argument errors of the adjoint and the readout gradient come back
+    before any device work."""
+    lib = stx.lib()
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))  # noqa: E731
+    m = np.zeros((4, 3))
+    u = np.zeros(4)
+    assert lib.reservoir_adjoint(None, dp(m), dp(u), 20, None, None, None, None, None, None, 0) == stx.STO_E_INVALID
+    assert lib.reservoir_adjoint_device(None, None, None, 20, None, None, None, None, None, None, 0,
+                                        None) == stx.STO_E_INVALID
+    assert lib.readout_grad_device(None, 0, 10, 3, None, 2, 1e-6, 0, None, None, None, None) == stx.STO_E_INVALID
+
