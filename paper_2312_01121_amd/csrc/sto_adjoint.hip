@@ -25,7 +25,7 @@
 // adjoint of the next stage to be reversed, so every reversed stage is one
 // pass over W^T.  The per-stage bbar vectors of the segment are kept, and
 // dL/dW = a_cp sum_stages outer(bbar, x) is one matrix product per segment
-// (k_gw).  The scalar derivatives are accumulated per node in FP64 and
+// (k_gw_mfma on the matrix cores in FP32, k_gw in FP64).  The scalar derivatives are accumulated per node in FP64 and
 // summed in a fixed order at the end.
 //
 // FP64 stage sums of the forward use the same double-double accumulation as
@@ -34,6 +34,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdlib>
 #include <vector>
 
 #include "sto_adjoint.hpp"
@@ -48,7 +49,6 @@ template <typename T> struct AVec;
 template <> struct AVec<double> { using type = dv2; static constexpr int n = 2; };
 template <> struct AVec<float> { using type = fv4; static constexpr int n = 4; };
 
-constexpr int kRows = 2;   // rows of W (or W^T) per wave
 
 // Device view of the adjoint workspace for one segment.
 template <typename T>
@@ -220,16 +220,15 @@ __device__ __forceinline__ void prep_step(const AdjDev<T>& d, const Coef<T>& k, 
 }
 
 // ---------------------------------------------------------------------------
-// Forward stage with trace (the stage kernel's shape: kRows rows of W per
-// wave, 16-byte non-temporal loads, fused epilogue).
+// Forward stage with trace (the stage kernel's shape: R rows of W per wave,
+// 16-byte non-temporal loads, fused epilogue).
 // ---------------------------------------------------------------------------
-template <typename T, bool XYZ, int U>
+template <typename T, bool XYZ, int R, int U>
 __global__ void __launch_bounds__(256) k_fwd_trace(AdjDev<T> d, Coef<T> k, int kk, int stage, int cur, int trace) {
     using A = Acc<T>;
     using AT = typename A::type;
     using V = typename AVec<T>::type;
     constexpr int VN = AVec<T>::n;
-    constexpr int R = kRows;
     constexpr int C = XYZ ? 3 : 1;
     const int lane = threadIdx.x & 63;
     const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * R;
@@ -342,11 +341,10 @@ __global__ void __launch_bounds__(256) k_fwd_trace(AdjDev<T> d, Coef<T> k, int k
 // coupled components, dL/dm += xbar, and the pointwise adjoint of the next
 // stage to reverse (or, after the first stage, the start of the previous step).
 // ---------------------------------------------------------------------------
-template <typename T, bool XYZ, int U>
+template <typename T, bool XYZ, int R, int U>
 __global__ void __launch_bounds__(256) k_adj_stage(AdjDev<T> d, Coef<T> k, int kk, int stage) {
     using V = typename AVec<T>::type;
     constexpr int VN = AVec<T>::n;
-    constexpr int R = kRows;
     constexpr int C = XYZ ? 3 : 1;
     const int lane = threadIdx.x & 63;
     const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * R;
@@ -496,6 +494,85 @@ __global__ void __launch_bounds__(256) k_gw(const T* __restrict__ S, int64_t sld
     }
 }
 
+// FP32 dL/dW on the matrix cores: G (+)= alpha * S^T X as above, with
+// v_mfma_f32_16x16x4f32 (FP32 accumulation).  A wave owns a 64 x 64 block of
+// G as 4 x 4 tiles of 16 x 16, a workgroup of four waves 128 x 128.  Per MFMA
+// step of four panel rows, lane l supplies A[l%16][l/16] = S[l0 + l/16][i]
+// and B[l/16][l%16] = X[l0 + l/16][j], so both panels are read along their
+// contiguous dimension (16 lanes cover 64 consecutive bytes); the result tile
+// holds D[4 (l/16) + r][l%16] in lane l.  Columns at or beyond ld (the panel
+// pitch) read as zero; the kernel has no barrier, so waves outside G leave early.
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_gw_mfma(const float* __restrict__ S, int64_t sld, const float* __restrict__ X,
+                                                 int64_t xld, int L, int n, int64_t ld, float alpha,
+                                                 float* __restrict__ G, int accumulate) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i0 = blockIdx.y * 128 + (wave >> 1) * 64;
+    const int j0 = blockIdx.x * 128 + (wave & 1) * 64;
+    if (i0 >= n || j0 >= n) return;   // wave-uniform
+    const int kr = lane >> 4, c16 = lane & 15;
+    bool va[4], vb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        va[q] = i0 + 16 * q + c16 < ld;
+        vb[q] = j0 + 16 * q + c16 < ld;
+    }
+    const float* sp = S + i0 + c16;
+    const float* xp = X + j0 + c16;
+    mf4 acc[4][4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mf4{0.f, 0.f, 0.f, 0.f};
+    // operands of step l0 + 4 are loaded while the MFMAs of step l0 run
+    float a[4], b[4];
+    // Loads are unconditional from clamped addresses (row L - 1, column
+    // offset 0: i0 + c16 < n <= ld), out-of-range operands are zeroed after.
+    auto load = [&](int l0, float* ra, float* rb) {
+        const int l = l0 + kr;
+        const bool vl = l < L;
+        const int64_t lc = vl ? l : L - 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float x = sp[lc * sld + (va[q] ? 16 * q : 0)];
+            const float y = xp[lc * xld + (vb[q] ? 16 * q : 0)];
+            const unsigned ma = (vl && va[q]) ? 0xffffffffu : 0u, mb = (vl && vb[q]) ? 0xffffffffu : 0u;
+            ra[q] = __uint_as_float(__float_as_uint(x) & ma);
+            rb[q] = __uint_as_float(__float_as_uint(y) & mb);
+        }
+    };
+    load(0, a, b);
+    for (int l0 = 0; l0 < L; l0 += 4) {
+        float an[4], bn[4];
+        load(l0 + 4, an, bn);
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj)
+                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a[q] = an[q];
+            b[q] = bn[q];
+        }
+    }
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = i0 + 16 * bi + 4 * kr + r;
+            if (i >= n) continue;
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) {
+                const int j = j0 + 16 * bj + c16;
+                if (j >= n) continue;
+                float* g = G + (int64_t)i * n + j;
+                *g = accumulate ? *g + alpha * acc[bi][bj][r] : alpha * acc[bi][bj][r];
+            }
+        }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_transpose(const T* __restrict__ W, T* __restrict__ Wt, int n, int64_t ld) {
     __shared__ T tile[64][65];
@@ -554,6 +631,62 @@ __global__ void __launch_bounds__(256) k_adj_scalars(const double* __restrict__ 
     }
 }
 
+// Launch shapes of the two streaming kernels (rows of W per wave x unroll
+// of the column loop); STO_ADJ_ROWS / STO_ADJ_UNROLL choose one for
+// measurements, otherwise 2 rows and unroll 2 (measured fastest at N = 10^4
+// in FP32 and FP64 among the compiled shapes).
+int env_int(const char* name, int dflt) {
+    const char* v = getenv(name);
+    return v ? atoi(v) : dflt;
+}
+
+template <typename T>
+void adj_shape(int* rows, int* unroll) {
+    static const int r = env_int("STO_ADJ_ROWS", 0), u = env_int("STO_ADJ_UNROLL", 0);
+    *rows = 2;
+    *unroll = 2;
+    const int ok[][2] = {{1, 4}, {2, 2}, {2, 4}, {4, 1}, {4, 2}};
+    for (const auto& v : ok)
+        if (v[0] == r && v[1] == u) {
+            *rows = r;
+            *unroll = u;
+        }
+}
+
+template <typename T, bool XYZ>
+void launch_fwd(int rows, int unroll, hipStream_t st, const AdjDev<T>& d, const Coef<T>& k, int kk, int stage,
+                int trace) {
+    const dim3 grid((d.n + 4 * rows - 1) / (4 * rows)), block(256);
+#define ADJ_FWD(RR, UU)                                                                                  \
+    if (rows == RR && unroll == UU) {                                                                    \
+        hipLaunchKernelGGL((k_fwd_trace<T, XYZ, RR, UU>), grid, block, 0, st, d, k, kk, stage, stage & 1, \
+                           trace);                                                                       \
+        return;                                                                                          \
+    }
+    ADJ_FWD(1, 4)
+    ADJ_FWD(2, 2)
+    ADJ_FWD(2, 4)
+    ADJ_FWD(4, 1)
+    ADJ_FWD(4, 2)
+#undef ADJ_FWD
+}
+
+template <typename T, bool XYZ>
+void launch_rev(int rows, int unroll, hipStream_t st, const AdjDev<T>& d, const Coef<T>& k, int kk, int stage) {
+    const dim3 grid((d.n + 4 * rows - 1) / (4 * rows)), block(256);
+#define ADJ_REV(RR, UU)                                                                            \
+    if (rows == RR && unroll == UU) {                                                              \
+        hipLaunchKernelGGL((k_adj_stage<T, XYZ, RR, UU>), grid, block, 0, st, d, k, kk, stage); \
+        return;                                                                                    \
+    }
+    ADJ_REV(1, 4)
+    ADJ_REV(2, 2)
+    ADJ_REV(2, 4)
+    ADJ_REV(4, 1)
+    ADJ_REV(4, 2)
+#undef ADJ_REV
+}
+
 struct DevAlloc {
     std::vector<void*> ptrs;
     ~DevAlloc() {
@@ -578,9 +711,10 @@ struct DevAlloc {
 
 template <typename T, bool XYZ>
 hipError_t adjoint_impl(const AdjArgs<T>& a) {
-    constexpr int U = sizeof(T) == 8 ? 4 : 2;
     constexpr int C = XYZ ? 3 : 1;
     const hipStream_t st = a.stream;
+    int rows = 2, unroll = 2;
+    adj_shape<T>(&rows, &unroll);
     const int n = a.n;
     const int64_t ld = a.ld, S = a.steps;
     const int64_t K = std::max<int64_t>(1, std::min<int64_t>(a.seg_steps, S));
@@ -624,16 +758,13 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
     ADJ_TRY(hipMemsetAsync(d.gwin, 0, (size_t)std::max(1, a.n_in) * ld * sizeof(double), st));
 
     const dim3 pgrid((n + 255) / 256), pblock(256);
-    const dim3 sgrid((n + 4 * kRows - 1) / (4 * kRows)), sblock(256);
     const Coef<T> k = a.k;
     // forward over local steps [0, kn) of the segment starting at j0; the
     // state is in m and ms[0] (cur = 0 between steps)
     auto forward = [&](int64_t j0, int64_t kn, int trace) -> hipError_t {
         d.j0 = j0;
         for (int64_t kk = 0; kk < kn; ++kk)
-            for (int stage = 0; stage < 4; ++stage)
-                hipLaunchKernelGGL((k_fwd_trace<T, XYZ, U>), sgrid, sblock, 0, st, d, k, (int)kk, stage, stage & 1,
-                                   trace);
+            for (int stage = 0; stage < 4; ++stage) launch_fwd<T, XYZ>(rows, unroll, st, d, k, (int)kk, stage, trace);
         return hipGetLastError();
     };
     if (S > 0) {
@@ -657,14 +788,20 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
         d.j0 = j0;
         hipLaunchKernelGGL((k_adj_prep<T, XYZ>), pgrid, pblock, 0, st, d, k, (int)(kn - 1));
         for (int64_t kk = kn - 1; kk >= 0; --kk)
-            for (int stage = 3; stage >= 0; --stage)
-                hipLaunchKernelGGL((k_adj_stage<T, XYZ, U>), sgrid, sblock, 0, st, d, k, (int)kk, stage);
+            for (int stage = 3; stage >= 0; --stage) launch_rev<T, XYZ>(rows, unroll, st, d, k, (int)kk, stage);
         ADJ_TRY(hipGetLastError());
         if (a.g_W) {
             const int L = (int)(kn * 4 * C);
-            const dim3 ggrid((n + 63) / 64, (n + 63) / 64);
-            hipLaunchKernelGGL(k_gw<T>, ggrid, dim3(256), 0, st, d.st, ld, d.xt, XYZ ? ld : 3 * ld, L, n, k.a_cp,
-                               a.g_W, gw_started);
+            const int64_t xld = XYZ ? ld : 3 * ld;
+            if constexpr (sizeof(T) == 4) {
+                const dim3 ggrid((n + 127) / 128, (n + 127) / 128);
+                hipLaunchKernelGGL(k_gw_mfma, ggrid, dim3(256), 0, st, d.st, ld, d.xt, xld, L, n, ld, k.a_cp, a.g_W,
+                                   gw_started);
+            } else {
+                const dim3 ggrid((n + 63) / 64, (n + 63) / 64);
+                hipLaunchKernelGGL(k_gw<T>, ggrid, dim3(256), 0, st, d.st, ld, d.xt, xld, L, n, k.a_cp, a.g_W,
+                                   gw_started);
+            }
             ADJ_TRY(hipGetLastError());
             gw_started = 1;
         }
