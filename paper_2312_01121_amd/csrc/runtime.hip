@@ -17,6 +17,7 @@
 #include "../../include/sto_reservoir.h"
 #include "sto_adjoint.hpp"
 #include "sto_internal.hpp"
+#include "sto_sweep.hpp"
 #include "stream_tune.hpp"
 
 namespace {
@@ -890,7 +891,6 @@ sto_status sweep_create(int32_t count, const int64_t* n, int64_t n_in, const sto
     s->renorm = prm[0].renormalize;
     int64_t woff = 0, soff = 0, winoff = 0, noff = 0;
     std::vector<int2> tasks;
-    const int R = sto::sweep_rows_per_task((int)s->elem);
     for (int r = 0; r < count; ++r) {
         sto::SweepRes x;
         x.n = (int)n[r];
@@ -905,9 +905,10 @@ sto_status sweep_create(int32_t count, const int64_t* n, int64_t n_in, const sto
         soff += 3 * x.ld;
         winoff += n[r] * n_in;
         noff += n[r];
-        // wave tasks of R rows each, in reservoir order (measured: a
-        // largest-first order or several row groups per task were slower)
-        for (int row = 0; row < n[r]; row += R) tasks.push_back(make_int2(r, row));
+        // wave tasks in reservoir order (a largest-first order was measured
+        // slower: the small tasks then form the tail)
+        const int rows = sto::sweep_task_rows(x.ld, (int)s->elem);
+        for (int row = 0; row < n[r]; row += rows) tasks.push_back(make_int2(r, row));
     }
     s->nodes = noff;
     s->tasks = (int)tasks.size();

@@ -3,17 +3,23 @@
 // by one shared input series, stepped together.
 //
 // One launch evaluates one RK4 stage of every reservoir.  Work is split into
-// wave tasks of R consecutive rows of one reservoir (a table built on the
-// host); each task streams its rows of that reservoir's coupling matrix with
-// 16-byte non-temporal loads against the reservoir's stage input, reduces
-// the row sums across the wave and applies the reservoir's own right-hand
-// side of Eq. (gov) and the RK4 bookkeeping (Sec. 3.2), exactly as the
-// single-reservoir stream kernel does.  The sum of N_r^2 matrix elements is
-// read once per stage, so the launch is bound by HBM bandwidth.
+// wave tasks (a table built on the host), each covering consecutive rows of
+// one reservoir: the wave is split into lane groups of G lanes, G the
+// largest power of two that the reservoir's row pitch fills with 16-byte
+// vectors (at most 64), and each group streams R rows of that reservoir's
+// coupling matrix with non-temporal loads against the reservoir's stage
+// input.  Short rows therefore do not leave most of a wave idle.  The row
+// sums are reduced within the group, and R lanes of each group apply the
+// reservoir's own right-hand side of Eq. (gov) and the RK4 bookkeeping
+// (Sec. 3.2), exactly as the single-reservoir stream kernel does.  The sum
+// of N_r^2 matrix elements is read once per stage, so the launch is bound by
+// HBM bandwidth.
 
 #include <climits>
+#include <cstdlib>
 
 #include "sto_internal.hpp"
+#include "sto_sweep.hpp"
 
 namespace sto {
 
@@ -25,6 +31,15 @@ template <typename T> struct SVec;
 template <> struct SVec<double> { using type = dvec2; static constexpr int n = 2; };
 template <> struct SVec<float> { using type = fvec4; static constexpr int n = 4; };
 
+// Lanes per row group for a reservoir of row pitch ld: the largest power of
+// two <= min(64, ld / VN), so that rows shorter than 64 vectors do not leave
+// most of a wave idle.  A wave task then holds 64 / G groups of R rows.
+__host__ __device__ inline int group_lanes(int64_t ld, int vn) {
+    int g = 64;
+    while (g > 1 && (int64_t)g * vn > ld) g >>= 1;
+    return g;
+}
+
 template <typename T, int R, int U>
 __global__ void __launch_bounds__(256) k_sweep_stage(SweepDev<T> d, const double* __restrict__ u_s, int sample,
                                                      int stage, int cur, int record, int renorm) {
@@ -35,12 +50,14 @@ __global__ void __launch_bounds__(256) k_sweep_stage(SweepDev<T> d, const double
     const int lane = threadIdx.x & 63;
     const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (task >= d.tasks) return;   // wave-uniform
-    const int2 tk = d.task[task];
+    const int2 tk = d.task[task];  // (reservoir, first row)
     const SweepRes res = d.res[tk.x];
     const Coef<T> k = d.coef[tk.x];
     const int n = res.n;
     const int64_t ld = res.ld;
-    const int row0 = tk.y;
+    const int G = group_lanes(ld, VN);   // wave-uniform
+    const int gl = lane & (G - 1);
+    const int rowg = tk.y + (lane / G) * R;   // first row of this lane's group
     const T* W = d.W + res.woff;
     T* m = d.m + res.soff;
     T* acc = d.acc + res.soff;
@@ -49,12 +66,12 @@ __global__ void __launch_bounds__(256) k_sweep_stage(SweepDev<T> d, const double
 
     const T* wrow[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) wrow[r] = W + (int64_t)min(row0 + r, n - 1) * ld;
+    for (int r = 0; r < R; ++r) wrow[r] = W + (int64_t)min(rowg + r, n - 1) * ld;
     AT av[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) av[r] = A::zero();
 #pragma unroll U
-    for (int64_t c = (int64_t)lane * VN; c < ld; c += 64 * VN) {
+    for (int64_t c = (int64_t)gl * VN; c < ld; c += (int64_t)G * VN) {
         const V xv = *reinterpret_cast<const V*>(xin + c);
         V wv[R];
 #pragma unroll
@@ -67,11 +84,11 @@ __global__ void __launch_bounds__(256) k_sweep_stage(SweepDev<T> d, const double
     T dot = T(0);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const AT s = group_reduce<T>(av[r], 64);
-        if (lane == r) dot = A::round(s);
+        const AT s = group_reduce<T>(av[r], G);
+        if (gl == r) dot = A::round(s);
     }
-    const int row = row0 + lane;
-    if (lane >= R || row >= n) return;
+    const int row = rowg + gl;
+    if (gl >= R || row >= n) return;
     const T hin = input_field(k, d.w_in + res.winoff + (int64_t)row * d.n_in, u_s, d.n_in);
     const T sx = xin[row], sy = xin[ld + row], sz = xin[2 * ld + row];
     T fx, fy, fz;
@@ -110,23 +127,46 @@ __global__ void __launch_bounds__(256) k_sweep_stage(SweepDev<T> d, const double
 
 }  // namespace
 
+// Rows per lane group (R): 4, measured fastest on a 256-reservoir sweep
+// (372.6 us per RK4 step against 415.3 with 2).  STO_SWEEP_ROWS (2, 4 or 8)
+// overrides it for measurements; it is read once per process, so the task
+// table and the kernel always agree.
 int sweep_rows_per_task(int elem_bytes) {
     (void)elem_bytes;
-    return 2;
+    static const int rows = [] {
+        const char* v = getenv("STO_SWEEP_ROWS");
+        const int r = v ? atoi(v) : 4;
+        return (r == 2 || r == 8) ? r : 4;
+    }();
+    return rows;
+}
+
+// Rows of one reservoir covered by one wave task: R rows per lane group
+// times the groups in a wave.
+int sweep_task_rows(int64_t ld, int elem_bytes) {
+    return sweep_rows_per_task(elem_bytes) * (64 / group_lanes(ld, 16 / elem_bytes));
 }
 
 template <typename T>
 hipError_t run_sweep(const SweepDev<T>& d, const RunSpec& r) {
-    constexpr int R = 2;
     constexpr int U = sizeof(T) == 8 ? 4 : 2;
+    const int R = sweep_rows_per_task((int)sizeof(T));
     const dim3 grid((d.tasks + 3) / 4), block(256);
     for (int s = 0; s < r.samples; ++s) {
         const double* u_s = r.u + (int64_t)s * d.n_in;
         for (int sub = 0; sub < r.substeps; ++sub)
             for (int stage = 0; stage < 4; ++stage) {
                 const int rec = stage == 3 && sub == r.substeps - 1;
-                hipLaunchKernelGGL((k_sweep_stage<T, R, U>), grid, block, 0, r.stream, d, u_s, s, stage,
-                                   r.cur ^ (stage & 1), rec, r.renorm);
+                const int c = r.cur ^ (stage & 1);
+                if (R == 4)
+                    hipLaunchKernelGGL((k_sweep_stage<T, 4, U>), grid, block, 0, r.stream, d, u_s, s, stage, c, rec,
+                                       r.renorm);
+                else if (R == 8)
+                    hipLaunchKernelGGL((k_sweep_stage<T, 8, U>), grid, block, 0, r.stream, d, u_s, s, stage, c, rec,
+                                       r.renorm);
+                else
+                    hipLaunchKernelGGL((k_sweep_stage<T, 2, U>), grid, block, 0, r.stream, d, u_s, s, stage, c, rec,
+                                       r.renorm);
             }
     }
     return hipGetLastError();
