@@ -42,7 +42,7 @@ def log(*a):
 
 
 KERNEL_SOURCES = {
-    "k_sweep_stage": ("sto_device.hpp", "sto_internal.hpp", "sto_sweep.hip"),
+    "k_sweep_stage": ("sto_device.hpp", "sto_internal.hpp", "sto_sweep.hpp", "sto_sweep.hip"),
     "k_multi": ("sto_device.hpp", "sto_internal.hpp", "sto_multi.hip"),
     "k_stage": ("sto_device.hpp", "sto_internal.hpp", "sto_kernels.hip"),
     "k_small": ("sto_device.hpp", "sto_internal.hpp", "sto_small.hip"),

@@ -316,6 +316,16 @@ def test_sto10k_full_horizon_properties(stx, dtype):
     drift = sto.norm_drift(rec)
     say("  drift", drift)
     assert drift < (1e-4 if dtype == "f64" else 1e-3)
+    # sampled records at full size: the oracle restarted from the GPU's own
+    # record t and advanced one input sample (20 steps, all 10,000 nodes)
+    # must give the GPU's record t + 1 (FP64: to 1e-10, in practice bitwise;
+    # FP32: the 1e-5 per-step bar, accumulated over 20 steps from an FP32 state)
+    tol = F64_TOL if dtype == "f64" else 1e-5
+    for t in (499, 998):
+        ref, _ = sto.run(a["W"], a["w_in"], rec[t], a["u"][t + 1:t + 2], prm)
+        d = float(np.max(np.abs(ref[0] - rec[t + 1])))
+        say(f"  record {t + 1} from the oracle restarted at record {t}: max diff {d}")
+        assert d <= tol
 
 
 # ---------------------------------------------------------------------------
