@@ -53,8 +53,11 @@ typedef enum {
     STO_PATH_SMALL = 1,     /* one workgroup holds W and the state; all steps in one launch */
     STO_PATH_RESIDENT = 2,  /* W split across the CUs' LDS; all steps in one cooperative launch */
     STO_PATH_STREAM = 3,    /* W streamed from HBM once per RK4 stage, one launch per stage */
-    STO_PATH_MULTI = 4      /* S input streams share W: the coupling of all streams is one FP32
+    STO_PATH_MULTI = 4,     /* S input streams share W: the coupling of all streams is one FP32
                                MFMA matrix product per stage; all steps in one cooperative launch */
+    STO_PATH_BATCH = 5      /* S input streams share W: the same FP32 MFMA product, one launch per
+                               RK4 stage; both couplings, any n (chosen for S > 1 when
+                               STO_PATH_MULTI cannot run the reservoir) */
 } sto_path;
 
 /*
@@ -113,10 +116,11 @@ sto_status reservoir_create(int64_t n, int64_t n_in, const sto_params *prm,
  * (Eq. (coup) applied to every stream).
  *   streams  S >= 1; S == 1 is reservoir_create
  *   m0       host, S*n*3 doubles, [stream][node][xyz]
- * For S > 1 the handle runs STO_PATH_MULTI: prm->dtype must be STO_F32,
- * prm->coupling STO_COUPLE_X and n <= 1024, else STO_E_UNSUPPORTED (also when
- * the S x n tiles cannot all be co-resident).  For such a handle, u and
- * states of the run calls gain a stream axis: u is [sample][stream][n_in]
+ * For S > 1 prm->dtype must be STO_F32 (STO_E_UNSUPPORTED otherwise) and the
+ * handle runs STO_PATH_MULTI when it can (STO_COUPLE_X, n <= 1024, all S x n
+ * tiles co-resident), else STO_PATH_BATCH; prm->path may ask for either
+ * (STO_E_UNSUPPORTED if STO_PATH_MULTI cannot run it).  For such a handle, u
+ * and states of the run calls gain a stream axis: u is [sample][stream][n_in]
  * and states [sample][stream][node][xyz]; get/set_state use [stream][node][xyz].
  */
 sto_status reservoir_create_streams(int64_t n, int64_t n_in, int64_t streams, const sto_params *prm,
@@ -158,18 +162,21 @@ sto_status reservoir_run_device(sto_reservoir *r, const void *u_dev, int64_t ste
  * has no adjoint; the derivatives are those of its integrator.
  *
  * The run is recomputed from m_start over u (the handle's current state is
- * neither used nor changed), and L enters only through its gradient:
- *   m_start_dev      device, n*3 elements of the handle's dtype, AoS: the
+ * neither used nor changed), and L enters only through its gradient.  For a
+ * handle of S input streams (reservoir_create_streams) every per-stream
+ * array below gains the stream axis as in the run calls, and the gradients
+ * of the shared W, w_in and constants sum over the streams.
+ *   m_start_dev      device, S*n*3 elements of the handle's dtype, AoS: the
  *                    state the run starts from
- *   u_dev            device, (steps/substeps)*n_in doubles: the run's inputs
+ *   u_dev            device, (steps/substeps)*S*n_in doubles: the run's inputs
  *   steps            RK4 steps, a non-negative multiple of substeps
- *   grad_states_dev  device, (steps/substeps)*n*3 dtype: dL/d(record s), the
+ *   grad_states_dev  device, (steps/substeps)*S*n*3 dtype: dL/d(record), the
  *                    records being those reservoir_run writes; NULL: zero
- *   grad_final_dev   device, n*3 dtype: dL/d(state after the run); NULL: zero
+ *   grad_final_dev   device, S*n*3 dtype: dL/d(state after the run); NULL: zero
  * Outputs (device, overwritten; each may be NULL to skip it):
  *   grad_W_dev       n*n dtype, row-major, no padding: dL/dW
  *   grad_w_in_dev    n*n_in dtype: dL/dw_in
- *   grad_m0_dev      n*3 dtype, AoS: dL/dm_start
+ *   grad_m0_dev      S*n*3 dtype, AoS: dL/dm_start
  *   grad_scalars_dev 4 doubles: dL/da_cp, dL/da_in, dL/dh_s, dL/dh_appl
  *                    (the dimensionless constants of sto_params)
  *   checkpoint_every RK4 steps per recomputed segment; 0: the library
@@ -179,14 +186,15 @@ sto_status reservoir_run_device(sto_reservoir *r, const void *u_dev, int64_t ste
  *   hip_stream       hipStream_t to enqueue on (NULL: the null stream)
  * The forward is run from m_start and a state checkpoint kept at the start of
  * every segment; each segment is recomputed with its stage trace and
- * reversed.  The call allocates its workspace (about
- * checkpoint_every * (4*(3+2C)+1) * ld elements, C = 1 or 3 coupled
- * components, ld = n rounded up to 64) plus one transpose of W kept by the
- * handle, and returns after the stream has finished.  FP32 handles compute
- * the adjoint in FP32 (the scalar sums in FP64).
- * Errors: STO_E_INVALID (arguments), STO_E_UNSUPPORTED (S > 1 streams),
- * STO_E_NONFINITE (the recomputed state is not finite; the message names
- * the sample), STO_E_NOMEM, STO_E_DEVICE.
+ * reversed.  With one stream each stage is a streamed mat-vec with W or
+ * W^T; with S streams it is one FP32 MFMA product for all streams.  The call
+ * allocates its workspace (about checkpoint_every * (4*(3+2C)+1) * S * ld
+ * elements, C = 1 or 3 coupled components, ld = n rounded up to 64) plus
+ * one transpose of W kept by the handle, and returns after the stream has
+ * finished.  FP32 handles compute the adjoint in FP32 (the scalar sums in
+ * FP64).
+ * Errors: STO_E_INVALID (arguments), STO_E_NONFINITE (the recomputed state
+ * is not finite; the message names the sample), STO_E_NOMEM, STO_E_DEVICE.
  */
 sto_status reservoir_adjoint_device(sto_reservoir *r, const void *m_start_dev, const void *u_dev, int64_t steps,
                                     const void *grad_states_dev, const void *grad_final_dev, void *grad_W_dev,
@@ -195,9 +203,10 @@ sto_status reservoir_adjoint_device(sto_reservoir *r, const void *m_start_dev, c
 
 /*
  * reservoir_adjoint -- reservoir_adjoint_device on host arrays of doubles
- * (m_start n*3, u (steps/substeps)*n_in, grad_states, grad_final, and the
- * outputs grad_W n*n, grad_w_in n*n_in, grad_m0 n*3, grad_scalars 4), on the
- * handle's stream.  Inputs are checked for finiteness (STO_E_NONFINITE).
+ * (m_start S*n*3, u (steps/substeps)*S*n_in, grad_states, grad_final, and
+ * the outputs grad_W n*n, grad_w_in n*n_in, grad_m0 S*n*3, grad_scalars 4),
+ * on the handle's stream.  Inputs are checked for finiteness
+ * (STO_E_NONFINITE).
  */
 sto_status reservoir_adjoint(sto_reservoir *r, const double *m_start, const double *u, int64_t steps,
                              const double *grad_states, const double *grad_final, double *grad_W,

@@ -24,8 +24,9 @@ LIB_PATH = os.path.join(_PKG, "libsto_reservoir.so")
 STO_OK, STO_E_INVALID, STO_E_NOMEM, STO_E_DEVICE, STO_E_NONFINITE, STO_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 STO_F64, STO_F32 = 0, 1
 STO_COUPLE_X, STO_COUPLE_XYZ = 0, 1
-PATH_AUTO, PATH_SMALL, PATH_RESIDENT, PATH_STREAM, PATH_MULTI = 0, 1, 2, 3, 4
-PATH_NAMES = {PATH_SMALL: "small", PATH_RESIDENT: "resident", PATH_STREAM: "stream", PATH_MULTI: "multi"}
+PATH_AUTO, PATH_SMALL, PATH_RESIDENT, PATH_STREAM, PATH_MULTI, PATH_BATCH = 0, 1, 2, 3, 4, 5
+PATH_NAMES = {PATH_SMALL: "small", PATH_RESIDENT: "resident", PATH_STREAM: "stream", PATH_MULTI: "multi",
+              PATH_BATCH: "batch"}
 _STATUS_NAMES = {STO_E_INVALID: "invalid", STO_E_NOMEM: "nomem", STO_E_DEVICE: "device",
                  STO_E_NONFINITE: "nonfinite", STO_E_UNSUPPORTED: "unsupported"}
 
@@ -57,7 +58,7 @@ def make_params(alpha, h_appl, h_k, h_s, lambda_stt, p, a_cp, a_in, dt, substeps
     pr.dtype = {"f64": STO_F64, "f32": STO_F32}[dtype]
     pr.coupling = {"x": STO_COUPLE_X, "xyz": STO_COUPLE_XYZ}[coupling]
     pr.path = {"auto": PATH_AUTO, "small": PATH_SMALL, "resident": PATH_RESIDENT, "stream": PATH_STREAM,
-               "multi": PATH_MULTI}[path]
+               "multi": PATH_MULTI, "batch": PATH_BATCH}[path]
     pr.reserved = 0
     return pr
 
@@ -258,16 +259,26 @@ def _vp(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def reservoir_adjoint(h, n: int, n_in: int, m_start, u, steps: int, grad_states=None, grad_final=None,
-                      checkpoint_every: int = 0) -> dict:
+def reservoir_adjoint(h, n: int, n_in: int, substeps: int, m_start, u, steps: int, grad_states=None,
+                      grad_final=None, checkpoint_every: int = 0) -> dict:
     """Host arrays in and out (float64).  Returns {"W", "w_in", "m0", "a_cp",
     "a_in", "h_s", "h_appl"}: the gradients of the loss whose gradient with
-    respect to the records is grad_states (and to the final state grad_final)."""
-    m_start = _f64(m_start, (n, 3))
-    u = _f64(u).reshape(-1, n_in)
-    gs = _f64(grad_states) if grad_states is not None else None
-    gf = _f64(grad_final, (n, 3)) if grad_final is not None else None
-    out = {"W": np.empty((n, n)), "w_in": np.empty((n, n_in)), "m0": np.empty((n, 3))}
+    respect to the records is grad_states (and to the final state grad_final).
+    For a handle of S > 1 streams, m_start, grad_final and "m0" are
+    (S, n, 3), u is (samples, S, n_in) and grad_states (samples, S, n, 3).
+    Every array is sized from the handle's own S before the call."""
+    streams = reservoir_streams(h)
+    if streams < 1:
+        raise StoError(STO_E_INVALID, "invalid handle")
+    samples = max(0, steps) // substeps
+    m_start = _f64(m_start, (streams * n, 3))
+    u = _f64(u)
+    if u.size < samples * streams * n_in:
+        raise ValueError("u holds fewer than steps/substeps * streams * n_in values")
+    gs = _f64(grad_states, (samples * streams * n, 3)) if grad_states is not None else None
+    gf = _f64(grad_final, (streams * n, 3)) if grad_final is not None else None
+    m0_shape = (n, 3) if streams == 1 else (streams, n, 3)
+    out = {"W": np.empty((n, n)), "w_in": np.empty((n, n_in)), "m0": np.empty(m0_shape)}
     scal = np.empty(4)
     _check(_lib.reservoir_adjoint(h, _dptr(m_start), _dptr(u), steps, _dptr(gs) if gs is not None else None,
                                   _dptr(gf) if gf is not None else None, _dptr(out["W"]), _dptr(out["w_in"]),
@@ -370,9 +381,9 @@ class Reservoir:
 
     def adjoint(self, m_start, u, grad_states=None, grad_final=None, checkpoint_every: int = 0) -> dict:
         """Gradients (host, float64) of the run from m_start over u; see reservoir_adjoint."""
-        u = _f64(u).reshape(-1, self.n_in)
-        return reservoir_adjoint(self.h, self.n, self.n_in, m_start, u, len(u) * self.substeps, grad_states,
-                                 grad_final, checkpoint_every)
+        u = _f64(u).reshape(-1, self.streams * self.n_in)
+        return reservoir_adjoint(self.h, self.n, self.n_in, self.substeps, m_start, u, len(u) * self.substeps,
+                                 grad_states, grad_final, checkpoint_every)
 
     def adjoint_device(self, m_start_dev, u_dev, grad_states_dev=None, grad_final_dev=None, want=("W", "w_in", "m0",
                        "scalars"), checkpoint_every: int = 0, stream=None) -> dict:
@@ -386,10 +397,18 @@ class Reservoir:
         if "w_in" in want:
             out["w_in"] = torch.empty((self.n, self.n_in), dtype=dt, device=dev)
         if "m0" in want:
-            out["m0"] = torch.empty((self.n, 3), dtype=dt, device=dev)
+            out["m0"] = torch.empty(((self.n, 3) if self.streams == 1 else (self.streams, self.n, 3)), dtype=dt,
+                                    device=dev)
         if "scalars" in want:
             out["scalars"] = torch.empty(4, dtype=torch.float64, device=dev)
-        samples = u_dev.numel() // self.n_in
+        samples = u_dev.numel() // (self.n_in * self.streams)
+        # every buffer is checked against the handle's shape before the call
+        per = self.streams * self.n
+        assert u_dev.is_cuda and u_dev.dtype == torch.float64 and u_dev.is_contiguous()
+        assert u_dev.numel() == samples * self.streams * self.n_in
+        for t, count in ((m_start_dev, per * 3), (grad_states_dev, samples * per * 3), (grad_final_dev, per * 3)):
+            if t is not None:
+                assert t.is_cuda and t.dtype == dt and t.is_contiguous() and t.numel() == count
         reservoir_adjoint_device(self.h, m_start_dev, u_dev, samples * self.substeps, grad_states_dev,
                                  grad_final_dev, out.get("W"), out.get("w_in"), out.get("m0"), out.get("scalars"),
                                  checkpoint_every, stream)

@@ -218,11 +218,13 @@ sto_status upload_state(sto_reservoir* r, const double* m_aos) {
     const size_t count = soa.size();
     if (r->dtype == STO_F64) {
         HIP_TRY(hipMemcpy(r->m, soa.data(), count * 8, hipMemcpyHostToDevice), "state upload");
-        if (S == 1) HIP_TRY(hipMemcpy(r->ms[r->cur], soa.data(), count * 8, hipMemcpyHostToDevice), "state upload");
+        if (S == 1 || r->path == STO_PATH_BATCH)
+            HIP_TRY(hipMemcpy(r->ms[r->cur], soa.data(), count * 8, hipMemcpyHostToDevice), "state upload");
     } else {
         std::vector<float> f(soa.begin(), soa.end());
         HIP_TRY(hipMemcpy(r->m, f.data(), count * 4, hipMemcpyHostToDevice), "state upload");
-        if (S == 1) HIP_TRY(hipMemcpy(r->ms[r->cur], f.data(), count * 4, hipMemcpyHostToDevice), "state upload");
+        if (S == 1 || r->path == STO_PATH_BATCH)
+            HIP_TRY(hipMemcpy(r->ms[r->cur], f.data(), count * 4, hipMemcpyHostToDevice), "state upload");
     }
     return STO_OK;
 }
@@ -238,7 +240,7 @@ sto_status validate_params(const sto_params* p) {
     if (p->dtype != STO_F64 && p->dtype != STO_F32) return fail(STO_E_INVALID, "unknown dtype %d", p->dtype);
     if (p->coupling != STO_COUPLE_X && p->coupling != STO_COUPLE_XYZ)
         return fail(STO_E_INVALID, "unknown coupling %d", p->coupling);
-    if (p->path < STO_PATH_AUTO || p->path > STO_PATH_MULTI)
+    if (p->path < STO_PATH_AUTO || p->path > STO_PATH_BATCH)
         return fail(STO_E_INVALID, "unknown path %d", p->path);
     if (p->renormalize != 0 && p->renormalize != 1) return fail(STO_E_INVALID, "renormalize must be 0 or 1");
     if (p->reserved != 0) return fail(STO_E_INVALID, "reserved must be 0");
@@ -263,6 +265,33 @@ hipError_t dispatch(sto_reservoir* r, const double* u_dev, int samples, void* st
         case STO_PATH_RESIDENT: return sto::run_resident<T>(d, k, spec);
         case STO_PATH_MULTI:
             if constexpr (sizeof(T) == 4) return sto::run_multi(d, k, spec, (int)r->streams);
+            return hipErrorInvalidValue;
+        case STO_PATH_BATCH:
+            if constexpr (sizeof(T) == 4) {
+                sto::BatchRun b;
+                b.W = d.W;
+                b.Wt = static_cast<const float*>(r->Wt);
+                b.w_in = d.w_in;
+                b.m = d.m;
+                b.ms[0] = d.ms[0];
+                b.ms[1] = d.ms[1];
+                b.acc = d.acc;
+                b.bad = d.bad;
+                b.u = u_dev;
+                b.states = static_cast<float*>(states_dev);
+                b.k = k;
+                b.n = d.n;
+                b.n_in = d.n_in;
+                b.streams = (int)r->streams;
+                b.substeps = spec.substeps;
+                b.renorm = spec.renorm;
+                b.xyz = spec.xyz;
+                b.samples = samples;
+                b.cur = r->cur;
+                b.ld = d.ld;
+                b.stream = s;
+                return sto::run_batch(b);
+            }
             return hipErrorInvalidValue;
         default: return sto::run_stream<T>(d, k, spec);
     }
@@ -298,6 +327,26 @@ sto_status run_device_impl(sto_reservoir* r, const double* u_dev, int64_t steps,
     return STO_OK;
 }
 
+// The transpose of W (zero padding), made once per handle: the adjoint's
+// reversed stages and the BATCH path read it.
+sto_status ensure_transpose(sto_reservoir* r, hipStream_t stream) {
+    if (r->Wt) return STO_OK;
+    const size_t wb = (size_t)r->n * r->ld * r->elem;
+    HIP_TRY(hipMalloc(&r->Wt, wb), "hipMalloc W^T");
+    HIP_TRY(hipMemsetAsync(r->Wt, 0, wb, stream), "W^T clear");
+    hipError_t e = r->dtype == STO_F64
+                       ? sto::transpose_matrix<double>(static_cast<const double*>(r->W), static_cast<double*>(r->Wt),
+                                                       (int)r->n, r->ld, stream)
+                       : sto::transpose_matrix<float>(static_cast<const float*>(r->W), static_cast<float*>(r->Wt),
+                                                      (int)r->n, r->ld, stream);
+    if (e != hipSuccess) {
+        (void)hipFree(r->Wt);
+        r->Wt = nullptr;
+        return hip_fail(e, "transpose");
+    }
+    return STO_OK;
+}
+
 // Workspace budget of the adjoint's stage trace when the caller lets the
 // library choose the segment length.
 constexpr int64_t kAdjointTraceBudget = int64_t(4) << 30;
@@ -312,6 +361,7 @@ sto_status adjoint_dispatch(sto_reservoir* r, const void* m_start, const double*
     a.w_in = static_cast<const T*>(r->w_in);
     a.n = (int)r->n;
     a.n_in = (int)r->n_in;
+    a.streams = (int)r->streams;
     a.ld = r->ld;
     a.k = make_coef<T>(r->prm);
     a.substeps = r->prm.substeps;
@@ -338,7 +388,6 @@ sto_status adjoint_device_impl(sto_reservoir* r, const void* m_start, const void
                                const void* g_rec, const void* g_fin, void* g_W, void* g_win, void* g_m0,
                                double* g_scal, int64_t checkpoint_every, hipStream_t stream) {
     if (!r) return fail(STO_E_INVALID, "handle is NULL");
-    if (r->streams != 1) return fail(STO_E_UNSUPPORTED, "the adjoint needs a single-stream reservoir");
     if (steps < 0 || steps % r->prm.substeps != 0)
         return fail(STO_E_INVALID, "steps (%lld) must be a non-negative multiple of substeps (%d)",
                     (long long)steps, r->prm.substeps);
@@ -348,23 +397,13 @@ sto_status adjoint_device_impl(sto_reservoir* r, const void* m_start, const void
     if (checkpoint_every < 0) return fail(STO_E_INVALID, "checkpoint_every must be >= 0");
     int64_t seg = checkpoint_every;
     if (seg == 0) {
-        const int64_t per = sto::adjoint_trace_bytes_per_step(r->ld, (int)r->elem, r->prm.coupling == STO_COUPLE_XYZ);
+        const int64_t per = sto::adjoint_trace_bytes_per_step(r->ld, (int)r->elem, r->prm.coupling == STO_COUPLE_XYZ,
+                                                              (int)r->streams);
         seg = std::max<int64_t>(1, std::min<int64_t>(std::max<int64_t>(steps, 1), kAdjointTraceBudget / per));
     }
-    if (!r->Wt) {
-        const size_t wb = (size_t)r->n * r->ld * r->elem;
-        HIP_TRY(hipMalloc(&r->Wt, wb), "hipMalloc W^T");
-        HIP_TRY(hipMemsetAsync(r->Wt, 0, wb, stream), "W^T clear");
-        hipError_t e = r->dtype == STO_F64
-                           ? sto::transpose_matrix<double>(static_cast<const double*>(r->W),
-                                                           static_cast<double*>(r->Wt), (int)r->n, r->ld, stream)
-                           : sto::transpose_matrix<float>(static_cast<const float*>(r->W), static_cast<float*>(r->Wt),
-                                                          (int)r->n, r->ld, stream);
-        if (e != hipSuccess) {
-            (void)hipFree(r->Wt);
-            r->Wt = nullptr;
-            return hip_fail(e, "transpose");
-        }
+    {
+        sto_status ts = ensure_transpose(r, stream);
+        if (ts != STO_OK) return ts;
     }
     const int none = INT_MAX;
     HIP_TRY(hipMemcpyAsync(r->bad, &none, sizeof(int), hipMemcpyHostToDevice, stream), "flag reset");
@@ -584,18 +623,22 @@ sto_status reservoir_create_streams(int64_t n, int64_t n_in, int64_t streams, co
     int path = prm->path;
     int grid = 0;
     const int small_n = sto::small_max_n((int)r->elem, xyz);
-    if (streams > 1 || path == STO_PATH_MULTI) {
+    if (streams > 1 || path == STO_PATH_MULTI || path == STO_PATH_BATCH) {
+        // the persistent multi-stream kernel when it can run the reservoir,
+        // else one launch per stage (both couplings, any n)
+        const bool multi_ok = !xyz && sto::multi_fits((int)n, (int)streams, nullptr, nullptr);
         const char* why = nullptr;
-        if (prm->dtype != STO_F32) why = "the multi-stream path computes in FP32";
-        else if (xyz) why = "the multi-stream path couples m^x only";
-        else if (path != STO_PATH_AUTO && path != STO_PATH_MULTI) why = "streams > 1 runs only the multi-stream path";
-        else if (!sto::multi_fits((int)n, (int)streams, nullptr, nullptr))
-            why = "n x streams does not fit the multi-stream kernel (n <= 1024, all tiles co-resident)";
+        if (prm->dtype != STO_F32) why = "the multi-stream paths compute in FP32";
+        else if (path == STO_PATH_MULTI && xyz) why = "the persistent multi-stream path couples m^x only";
+        else if (path == STO_PATH_MULTI && !multi_ok)
+            why = "n x streams does not fit the persistent multi-stream kernel (n <= 1024, all tiles co-resident)";
+        else if (path != STO_PATH_AUTO && path != STO_PATH_MULTI && path != STO_PATH_BATCH)
+            why = "streams > 1 runs only the multi-stream paths";
         if (why) {
             delete r;
             return fail(STO_E_UNSUPPORTED, "%s", why);
         }
-        path = STO_PATH_MULTI;
+        if (path == STO_PATH_AUTO) path = multi_ok ? STO_PATH_MULTI : STO_PATH_BATCH;
     } else if (path == STO_PATH_AUTO) {
         if (n <= small_n) path = STO_PATH_SMALL;
         else if (sto::resident_fits((int)n, (int)r->elem, xyz, &grid)) path = STO_PATH_RESIDENT;
@@ -624,10 +667,11 @@ sto_status reservoir_create_streams(int64_t n, int64_t n_in, int64_t streams, co
     const size_t vec = (size_t)3 * r->ld * r->elem;
     ALLOC(r->W, (size_t)n * r->ld * r->elem);
     ALLOC(r->w_in, (size_t)n * n_in * r->elem);
+    const size_t svec = path == STO_PATH_BATCH ? vec * streams : vec;   // stage buffers of all streams
     ALLOC(r->m, vec * streams);
-    ALLOC(r->ms[0], vec);
-    ALLOC(r->ms[1], vec);
-    ALLOC(r->acc, vec);
+    ALLOC(r->ms[0], svec);
+    ALLOC(r->ms[1], svec);
+    ALLOC(r->acc, svec);
     if (path == STO_PATH_RESIDENT) {
         ALLOC(r->xchg, 3 * vec);
     } else if (path == STO_PATH_MULTI) {
@@ -645,6 +689,11 @@ sto_status reservoir_create_streams(int64_t n, int64_t n_in, int64_t streams, co
     if (st != STO_OK) return cleanup(st);
     st = upload_state(r, m0);
     if (st != STO_OK) return cleanup(st);
+    if (path == STO_PATH_BATCH) {
+        st = ensure_transpose(r, r->stream);
+        if (st == STO_OK && hipStreamSynchronize(r->stream) != hipSuccess) st = fail(STO_E_DEVICE, "transpose");
+        if (st != STO_OK) return cleanup(st);
+    }
     *out = r;
     return STO_OK;
 }
@@ -718,15 +767,15 @@ sto_status reservoir_adjoint(sto_reservoir* r, const double* m_start, const doub
                              const double* grad_states, const double* grad_final, double* grad_W, double* grad_w_in,
                              double* grad_m0, double* grad_scalars, int64_t checkpoint_every) {
     if (!r) return fail(STO_E_INVALID, "handle is NULL");
-    if (r->streams != 1) return fail(STO_E_UNSUPPORTED, "the adjoint needs a single-stream reservoir");
     if (steps < 0 || steps % r->prm.substeps != 0)
         return fail(STO_E_INVALID, "steps (%lld) must be a non-negative multiple of substeps (%d)",
                     (long long)steps, r->prm.substeps);
     if (!m_start) return fail(STO_E_INVALID, "m_start is NULL");
-    const int64_t samples = steps / r->prm.substeps, n = r->n;
+    const int64_t samples = steps / r->prm.substeps, n = r->n, S = r->streams;
     if (samples > 0 && !u) return fail(STO_E_INVALID, "u is NULL");
-    if (!finite_all(m_start, 3 * n) || (samples > 0 && !finite_all(u, samples * r->n_in)) ||
-        (grad_states && !finite_all(grad_states, samples * n * 3)) || (grad_final && !finite_all(grad_final, 3 * n)))
+    if (!finite_all(m_start, 3 * n * S) || (samples > 0 && !finite_all(u, samples * S * r->n_in)) ||
+        (grad_states && !finite_all(grad_states, samples * S * n * 3)) ||
+        (grad_final && !finite_all(grad_final, 3 * n * S)))
         return fail(STO_E_NONFINITE, "non-finite input");
     void *m_d = nullptr, *gr_d = nullptr, *gf_d = nullptr, *gw_d = nullptr, *gwin_d = nullptr, *gm_d = nullptr;
     double *u_d = nullptr, *gs_d = nullptr;
@@ -735,19 +784,19 @@ sto_status reservoir_adjoint(sto_reservoir* r, const double* m_start, const doub
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
     };
-    sto_status st = to_device(r, m_start, 3 * n, &m_d);
-    if (st == STO_OK) st = to_device(r, grad_states, samples * n * 3, &gr_d);
-    if (st == STO_OK) st = to_device(r, grad_final, 3 * n, &gf_d);
+    sto_status st = to_device(r, m_start, 3 * n * S, &m_d);
+    if (st == STO_OK) st = to_device(r, grad_states, samples * S * n * 3, &gr_d);
+    if (st == STO_OK) st = to_device(r, grad_final, 3 * n * S, &gf_d);
     if (st == STO_OK && samples > 0) {
-        if (hipMalloc(&u_d, (size_t)samples * r->n_in * 8) != hipSuccess ||
-            hipMemcpy(u_d, u, (size_t)samples * r->n_in * 8, hipMemcpyHostToDevice) != hipSuccess)
+        if (hipMalloc(&u_d, (size_t)samples * S * r->n_in * 8) != hipSuccess ||
+            hipMemcpy(u_d, u, (size_t)samples * S * r->n_in * 8, hipMemcpyHostToDevice) != hipSuccess)
             st = fail(STO_E_DEVICE, "u upload");
     }
     if (st == STO_OK && grad_W && hipMalloc(&gw_d, (size_t)n * n * r->elem) != hipSuccess)
         st = fail(STO_E_NOMEM, "hipMalloc dL/dW");
     if (st == STO_OK && grad_w_in && hipMalloc(&gwin_d, (size_t)n * r->n_in * r->elem) != hipSuccess)
         st = fail(STO_E_NOMEM, "hipMalloc dL/dw_in");
-    if (st == STO_OK && grad_m0 && hipMalloc(&gm_d, (size_t)n * 3 * r->elem) != hipSuccess)
+    if (st == STO_OK && grad_m0 && hipMalloc(&gm_d, (size_t)S * n * 3 * r->elem) != hipSuccess)
         st = fail(STO_E_NOMEM, "hipMalloc dL/dm0");
     if (st == STO_OK && grad_scalars && hipMalloc(&gs_d, 4 * sizeof(double)) != hipSuccess)
         st = fail(STO_E_NOMEM, "hipMalloc scalars");
@@ -756,7 +805,7 @@ sto_status reservoir_adjoint(sto_reservoir* r, const double* m_start, const doub
                                  r->stream);
     if (st == STO_OK) st = from_device(r, gw_d, n * n, grad_W);
     if (st == STO_OK) st = from_device(r, gwin_d, n * r->n_in, grad_w_in);
-    if (st == STO_OK) st = from_device(r, gm_d, n * 3, grad_m0);
+    if (st == STO_OK) st = from_device(r, gm_d, S * n * 3, grad_m0);
     if (st == STO_OK && grad_scalars && hipMemcpy(grad_scalars, gs_d, 4 * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
         st = fail(STO_E_DEVICE, "download");
     release();

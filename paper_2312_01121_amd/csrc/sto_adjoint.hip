@@ -38,6 +38,7 @@
 #include <vector>
 
 #include "sto_adjoint.hpp"
+#include "sto_adjoint_dev.hpp"
 
 namespace sto {
 
@@ -50,173 +51,11 @@ template <> struct AVec<double> { using type = dv2; static constexpr int n = 2; 
 template <> struct AVec<float> { using type = fv4; static constexpr int n = 4; };
 
 
-// Device view of the adjoint workspace for one segment.
-template <typename T>
-struct AdjDev {
-    const T* W;
-    const T* Wt;
-    const T* w_in;
-    T* m;            // forward state, SoA 3 x ld
-    T* ms[2];        // forward stage inputs (ping-pong)
-    T* acc;          // forward RK4 accumulator
-    int* bad;
-    T* xt;           // trace: stage inputs [K][4][3][ld]
-    T* wx;           // trace: raw coupling sums (W x) [K][4][C][ld]
-    T* st;           // adjoint of the coupling field per stage [K][4][C][ld]
-    T* pn;           // trace: norm before renormalisation [K][ld]
-    T* abar;         // [3][ld]  a of the step being reversed
-    T* mbar;         // [3][ld]  running dL/dm of the step being reversed
-    T* loc;          // [3][ld]  pointwise part of xbar of the stage being reversed
-    double* gacc;    // [4][ld]  per-node d/da_cp, d/da_in, d/dh_s, d/dh_appl
-    double* gwin;    // [n_in][ld]
-    const T* g_rec;
-    const T* g_fin;
-    const double* u;
-    int n, n_in, substeps, renorm;
-    int64_t ld, steps, j0;   // j0: global index of the segment's first step
-};
-
 // Sum over the 64 lanes of a wave (every lane ends with the total).
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
-}
-
-template <int C>
-__device__ __forceinline__ int64_t slot(int kk, int stage, int64_t ld) {
-    return ((int64_t)kk * 4 + stage) * C * ld;
-}
-
-// Unscaled input sum (w_in u)_row in the arithmetic type.
-template <typename T>
-__device__ __forceinline__ T input_dot(const T* w_in_row, const double* u_s, int n_in) {
-    typename Acc<T>::type a = Acc<T>::zero();
-    for (int j = 0; j < n_in; ++j) Acc<T>::fma(a, w_in_row[j], (T)u_s[j]);
-    return Acc<T>::round(a);
-}
-
-// Pointwise adjoint of the right-hand side of Eq. (gov) at stage input m,
-// coupling field c and input field hin, applied to v.  Returns
-// g = v^T dF/dm with c held fixed, bb = v^T dF/db and hsp = v^T dF/dh_s.
-template <typename T, bool XYZ>
-__device__ __forceinline__ void llg_vjp(const Coef<T>& k, T mx, T my, T mz, T cx, T cy, T cz, T hin, T vx,
-                                        T vy, T vz, T& gx, T& gy, T& gz, T& bbx, T& bby, T& bbz, T& hsp) {
-    const T mp = (mx * k.px + my * k.py) + mz * k.pz;
-    const T den = T(1) + k.lam * mp;
-    const T hs = k.h_s / den;
-    const T qx = k.py * mz - k.pz * my;
-    const T qy = k.pz * mx - k.px * mz;
-    const T qz = k.px * my - k.py * mx;
-    const T hz = k.h_appl + k.h_k * mz;
-    const T bx = (cx + hin) + hs * qx;
-    const T by = XYZ ? cy + hs * qy : hs * qy;
-    const T bz = XYZ ? (hz + cz) + hs * qz : hz + hs * qz;
-    // mb = m x b
-    const T ax = my * bz - mz * by;
-    const T ay = mz * bx - mx * bz;
-    const T az = mx * by - my * bx;
-    // adjoint of mb: -c1 v - c2 (v x m)
-    const T wmx = vy * mz - vz * my;
-    const T wmy = vz * mx - vx * mz;
-    const T wmz = vx * my - vy * mx;
-    const T ex = (-k.c1) * vx - k.c2 * wmx;
-    const T ey = (-k.c1) * vy - k.c2 * wmy;
-    const T ez = (-k.c1) * vz - k.c2 * wmz;
-    // through the m in m x (m x b): -c2 (mb x v); through m in m x b: b x ebar
-    gx = (-k.c2) * (ay * vz - az * vy) + (by * ez - bz * ey);
-    gy = (-k.c2) * (az * vx - ax * vz) + (bz * ex - bx * ez);
-    gz = (-k.c2) * (ax * vy - ay * vx) + (bx * ey - by * ex);
-    // adjoint of b: ebar x m
-    bbx = ey * mz - ez * my;
-    bby = ez * mx - ex * mz;
-    bbz = ex * my - ey * mx;
-    // b through m: h_k m_z, hs (p x m), hs(m . p)
-    gz = gz + k.h_k * bbz;
-    const T rx = bby * k.pz - bbz * k.py;
-    const T ry = bbz * k.px - bbx * k.pz;
-    const T rz = bbx * k.py - bby * k.px;
-    const T hsbar = (bbx * qx + bby * qy) + bbz * qz;
-    const T dh = hsbar * ((-k.lam) * hs / den);
-    gx = gx + hs * rx + dh * k.px;
-    gy = gy + hs * ry + dh * k.py;
-    gz = gz + hs * rz + dh * k.pz;
-    hsp = hsbar / den;
-}
-
-// Pointwise adjoint of stage `stage` of local step kk at node i, applied to
-// v: stores the pointwise part of xbar (loc), the coupling adjoint (st) and
-// adds the parameter partials of the node.
-template <typename T, bool XYZ>
-__device__ __forceinline__ void stage_vjp(const AdjDev<T>& d, const Coef<T>& k, int i, int kk, int stage, T vx,
-                                          T vy, T vz) {
-    constexpr int C = XYZ ? 3 : 1;
-    const int64_t ld = d.ld;
-    const T* x = d.xt + slot<3>(kk, stage, ld);
-    const T* wx = d.wx + slot<C>(kk, stage, ld);
-    const T mx = x[i], my = x[ld + i], mz = x[2 * ld + i];
-    const T wxx = wx[i];
-    const T wxy = XYZ ? wx[ld + i] : T(0);
-    const T wxz = XYZ ? wx[2 * ld + i] : T(0);
-    const int64_t sample = (d.j0 + kk) / d.substeps;
-    const double* u_s = d.u + sample * d.n_in;
-    const T raw = input_dot<T>(d.w_in + (int64_t)i * d.n_in, u_s, d.n_in);
-    const T hin = k.a_in * raw;
-    T gx, gy, gz, bx, by, bz, hsp;
-    llg_vjp<T, XYZ>(k, mx, my, mz, k.a_cp * wxx, k.a_cp * wxy, k.a_cp * wxz, hin, vx, vy, vz, gx, gy, gz, bx, by,
-                    bz, hsp);
-    d.loc[i] = gx;
-    d.loc[ld + i] = gy;
-    d.loc[2 * ld + i] = gz;
-    T* s = d.st + slot<C>(kk, stage, ld);
-    s[i] = bx;
-    if (XYZ) {
-        s[ld + i] = by;
-        s[2 * ld + i] = bz;
-    }
-    double pcp = (double)bx * (double)wxx;
-    if (XYZ) pcp += (double)by * (double)wxy + (double)bz * (double)wxz;
-    d.gacc[i] += pcp;
-    d.gacc[ld + i] += (double)bx * (double)raw;
-    d.gacc[2 * ld + i] += (double)hsp;
-    d.gacc[3 * ld + i] += (double)bz;
-    for (int q = 0; q < d.n_in; ++q) d.gwin[q * ld + i] += (double)k.a_in * (double)bx * u_s[q];
-}
-
-// Start reversing local step kk (global step j = j0 + kk): a = dL/dm_{j+1}
-// (carry plus the loss gradient on m_{j+1}), reversed through the optional
-// projection; then the pointwise adjoint of its last stage.
-//   mhat  the state m_{j+1} (after projection), SoA with pitch ld
-//   pn    the norm of m_{j+1} before projection
-template <typename T, bool XYZ>
-__device__ __forceinline__ void prep_step(const AdjDev<T>& d, const Coef<T>& k, int i, int kk, const T* mhat,
-                                          T pn, T cx, T cy, T cz) {
-    const int64_t ld = d.ld;
-    const int64_t jn = d.j0 + kk + 1;   // index of the state this step produces
-    T a[3] = {cx, cy, cz};
-    if (d.g_rec && jn % d.substeps == 0) {
-        const T* g = d.g_rec + ((jn / d.substeps - 1) * d.n + i) * 3;
-        a[0] += g[0];
-        a[1] += g[1];
-        a[2] += g[2];
-    }
-    if (d.g_fin && jn == d.steps) {
-        a[0] += d.g_fin[3 * (int64_t)i + 0];
-        a[1] += d.g_fin[3 * (int64_t)i + 1];
-        a[2] += d.g_fin[3 * (int64_t)i + 2];
-    }
-    if (d.renorm) {
-        const T ux = mhat[i], uy = mhat[ld + i], uz = mhat[2 * ld + i];
-        const T ao = (a[0] * ux + a[1] * uy) + a[2] * uz;
-        a[0] = (a[0] - ao * ux) / pn;
-        a[1] = (a[1] - ao * uy) / pn;
-        a[2] = (a[2] - ao * uz) / pn;
-    }
-    for (int c = 0; c < 3; ++c) {
-        d.abar[c * ld + i] = a[c];
-        d.mbar[c * ld + i] = a[c];
-    }
-    stage_vjp<T, XYZ>(d, k, i, kk, 3, k.h6 * a[0], k.h6 * a[1], k.h6 * a[2]);
 }
 
 // ---------------------------------------------------------------------------
@@ -229,14 +68,12 @@ __global__ void __launch_bounds__(256) k_fwd_trace(AdjDev<T> d, Coef<T> k, int k
     using AT = typename A::type;
     using V = typename AVec<T>::type;
     constexpr int VN = AVec<T>::n;
-    constexpr int C = XYZ ? 3 : 1;
     const int lane = threadIdx.x & 63;
     const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * R;
     const int n = d.n;
     if (row0 >= n) return;   // wave-uniform
     const int64_t ld = d.ld;
     const T* __restrict__ xin = d.ms[cur];
-    T* __restrict__ xout = d.ms[cur ^ 1];
     const T* wrow[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) wrow[r] = d.W + (int64_t)min(row0 + r, n - 1) * ld;
@@ -284,55 +121,7 @@ __global__ void __launch_bounds__(256) k_fwd_trace(AdjDev<T> d, Coef<T> k, int k
     }
     const int row = row0 + lane;
     if (lane >= R || row >= n) return;
-    const int64_t j = d.j0 + kk;
-    const int sample = (int)(j / d.substeps);
-    const T hin = input_field(k, d.w_in + (int64_t)row * d.n_in, d.u + (int64_t)sample * d.n_in, d.n_in);
-    const T sx = xin[row], sy = xin[ld + row], sz = xin[2 * ld + row];
-    if (trace) {
-        T* x = d.xt + slot<3>(kk, stage, ld);
-        x[row] = sx;
-        x[ld + row] = sy;
-        x[2 * ld + row] = sz;
-        T* w = d.wx + slot<C>(kk, stage, ld);
-        w[row] = dx;
-        if (XYZ) {
-            w[ld + row] = dy;
-            w[2 * ld + row] = dz;
-        }
-    }
-    T fx, fy, fz;
-    llg_rhs<T, XYZ>(k, sx, sy, sz, k.a_cp * dx, XYZ ? k.a_cp * dy : T(0), XYZ ? k.a_cp * dz : T(0), hin, fx, fy,
-                    fz);
-    const T mx = d.m[row], my = d.m[ld + row], mz = d.m[2 * ld + row];
-    T cx = T(0), cy = T(0), cz = T(0);
-    if (stage > 0) {
-        cx = d.acc[row];
-        cy = d.acc[ld + row];
-        cz = d.acc[2 * ld + row];
-    }
-    T nx = rk4_update(k, stage, mx, cx, fx);
-    T ny = rk4_update(k, stage, my, cy, fy);
-    T nz = rk4_update(k, stage, mz, cz, fz);
-    if (stage == 3) {
-        if (d.renorm) {
-            if (trace) {
-                const double ex = nx, ey = ny, ez = nz;
-                d.pn[(int64_t)kk * ld + row] = (T)__builtin_sqrt((ex * ex + ey * ey) + ez * ez);
-            }
-            renormalize(nx, ny, nz);
-        }
-        d.m[row] = nx;
-        d.m[ld + row] = ny;
-        d.m[2 * ld + row] = nz;
-        if (!finite3(nx, ny, nz)) atomicMin(d.bad, sample);
-    } else {
-        d.acc[row] = cx;
-        d.acc[ld + row] = cy;
-        d.acc[2 * ld + row] = cz;
-    }
-    xout[row] = nx;
-    xout[ld + row] = ny;
-    xout[2 * ld + row] = nz;
+    fwd_epilogue<T, XYZ>(d, k, row, 0, kk, stage, cur, trace, dx, dy, dz);
 }
 
 // ---------------------------------------------------------------------------
@@ -351,7 +140,7 @@ __global__ void __launch_bounds__(256) k_adj_stage(AdjDev<T> d, Coef<T> k, int k
     const int n = d.n;
     if (row0 >= n) return;   // wave-uniform
     const int64_t ld = d.ld;
-    const T* __restrict__ s = d.st + slot<C>(kk, stage, ld);
+    const T* __restrict__ s = d.st + adj_slot<C>(kk, stage, 1, ld);
     const T* wrow[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) wrow[r] = d.Wt + (int64_t)min(row0 + r, n - 1) * ld;
@@ -399,31 +188,7 @@ __global__ void __launch_bounds__(256) k_adj_stage(AdjDev<T> d, Coef<T> k, int k
     }
     const int i = row0 + lane;
     if (lane >= R || i >= n) return;
-    T xb[3] = {d.loc[i] + k.a_cp * dx, d.loc[ld + i], d.loc[2 * ld + i]};
-    if (XYZ) {
-        xb[1] = xb[1] + k.a_cp * dy;
-        xb[2] = xb[2] + k.a_cp * dz;
-    }
-    T mb[3];
-    for (int c = 0; c < 3; ++c) {
-        mb[c] = d.mbar[c * ld + i] + xb[c];
-        d.mbar[c * ld + i] = mb[c];
-    }
-    if (stage > 0) {
-        // kbar of stage-1: its weight in m' times a, plus its step into this stage's input
-        const T wgt = (stage - 1 == 0) ? k.h6 : T(2) * k.h6;
-        const T hst = (stage == 3) ? k.h1 : k.h2;
-        const T v0 = wgt * d.abar[i] + hst * xb[0];
-        const T v1 = wgt * d.abar[ld + i] + hst * xb[1];
-        const T v2 = wgt * d.abar[2 * ld + i] + hst * xb[2];
-        stage_vjp<T, XYZ>(d, k, i, kk, stage - 1, v0, v1, v2);
-    } else if (kk > 0) {
-        // step j = j0 + kk is reversed: mbar = dL/dm_j.  Start step j - 1,
-        // whose output m_j is the first stage input of step j.
-        const T* mhat = d.xt + slot<3>(kk, 0, ld);
-        const T pn = d.renorm ? d.pn[(int64_t)(kk - 1) * ld + i] : T(1);
-        prep_step<T, XYZ>(d, k, i, kk - 1, mhat, pn, mb[0], mb[1], mb[2]);
-    }
+    rev_epilogue<T, XYZ>(d, k, i, 0, kk, stage, dx, dy, dz);
 }
 
 // Start reversing the last step (local kk) of a segment: the carry is the
@@ -432,10 +197,12 @@ __global__ void __launch_bounds__(256) k_adj_stage(AdjDev<T> d, Coef<T> k, int k
 template <typename T, bool XYZ>
 __global__ void __launch_bounds__(256) k_adj_prep(AdjDev<T> d, Coef<T> k, int kk) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
     if (i >= d.n) return;
     const int64_t ld = d.ld;
-    const T pn = d.renorm ? d.pn[(int64_t)kk * ld + i] : T(1);
-    prep_step<T, XYZ>(d, k, i, kk, d.m, pn, d.mbar[i], d.mbar[ld + i], d.mbar[2 * ld + i]);
+    const int64_t sb = (int64_t)s * 3 * ld;
+    const T pn = d.renorm ? d.pn[((int64_t)kk * d.S + s) * ld + i] : T(1);
+    prep_step<T, XYZ>(d, k, i, s, kk, d.m + sb, pn, d.mbar[sb + i], d.mbar[sb + ld + i], d.mbar[sb + 2 * ld + i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -589,38 +356,49 @@ __global__ void __launch_bounds__(256) k_transpose(const T* __restrict__ W, T* _
     }
 }
 
-// AoS (n x 3) -> SoA (3 x ld) into m and the current stage input.
+// AoS ([S][n][3]) -> SoA ([S][3][ld]) into m and the current stage input.
 template <typename T>
 __global__ void k_load_state(const T* __restrict__ aos, T* __restrict__ m, T* __restrict__ x, int n, int64_t ld) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
     if (i >= n) return;
     for (int c = 0; c < 3; ++c) {
-        const T v = aos[3 * (int64_t)i + c];
-        m[c * ld + i] = v;
-        x[c * ld + i] = v;
+        const T v = aos[((int64_t)s * n + i) * 3 + c];
+        m[((int64_t)s * 3 + c) * ld + i] = v;
+        x[((int64_t)s * 3 + c) * ld + i] = v;
     }
 }
 
-// Outputs: dL/dm0 (AoS), dL/dw_in (n x n_in) from the accumulators.
+// Outputs: dL/dm0 ([S][n][3]) and dL/dw_in (n x n_in, summed over the
+// streams in order) from the accumulators.
 template <typename T>
 __global__ void k_adj_outputs(const T* __restrict__ mbar, const double* __restrict__ gwin, T* __restrict__ g_m0,
-                              T* __restrict__ g_win, int n, int n_in, int64_t ld) {
+                              T* __restrict__ g_win, int n, int n_in, int S, int64_t ld) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (g_m0)
-        for (int c = 0; c < 3; ++c) g_m0[3 * (int64_t)i + c] = mbar[c * ld + i];
+        for (int s = 0; s < S; ++s)
+            for (int c = 0; c < 3; ++c) g_m0[((int64_t)s * n + i) * 3 + c] = mbar[((int64_t)s * 3 + c) * ld + i];
     if (g_win)
-        for (int q = 0; q < n_in; ++q) g_win[(int64_t)i * n_in + q] = (T)gwin[q * ld + i];
+        for (int q = 0; q < n_in; ++q) {
+            double v = 0.0;
+            for (int s = 0; s < S; ++s) v += gwin[((int64_t)q * S + s) * ld + i];
+            g_win[(int64_t)i * n_in + q] = (T)v;
+        }
 }
 
-// Sum of the per-node scalar partials in a fixed order (one workgroup).
-__global__ void __launch_bounds__(256) k_adj_scalars(const double* __restrict__ gacc, int n, int64_t ld,
+// Sum of the per-node scalar partials ([4][S][ld]) in a fixed order (one workgroup).
+__global__ void __launch_bounds__(256) k_adj_scalars(const double* __restrict__ gacc, int n, int S, int64_t ld,
                                                      double* __restrict__ out) {
     __shared__ double part[256];
+    const int64_t total = (int64_t)S * n;
     for (int q = 0; q < 4; ++q) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < n; i += 256) s += gacc[q * ld + i];
-        part[threadIdx.x] = s;
+        double v = 0.0;
+        for (int64_t e = threadIdx.x; e < total; e += 256) {
+            const int64_t s = e / n, i = e - s * n;
+            v += gacc[((int64_t)q * S + s) * ld + i];
+        }
+        part[threadIdx.x] = v;
         __syncthreads();
         for (int w = 128; w > 0; w >>= 1) {
             if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
@@ -715,11 +493,12 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
     const hipStream_t st = a.stream;
     int rows = 2, unroll = 2;
     adj_shape<T>(&rows, &unroll);
-    const int n = a.n;
-    const int64_t ld = a.ld, S = a.steps;
-    const int64_t K = std::max<int64_t>(1, std::min<int64_t>(a.seg_steps, S));
-    const int64_t nseg = (S + K - 1) / K;
-    const size_t vec = (size_t)3 * ld * sizeof(T);
+    const int n = a.n, NS = a.streams;
+    const int64_t ld = a.ld, NSTEP = a.steps;
+    const int64_t K = std::max<int64_t>(1, std::min<int64_t>(a.seg_steps, NSTEP));
+    const int64_t nseg = (NSTEP + K - 1) / K;
+    const size_t vec = (size_t)3 * ld * NS * sizeof(T);   // one state of all streams
+    const size_t per_stage = (size_t)NS * ld * sizeof(T);  // one component of all streams
     DevAlloc mem;
     AdjDev<T> d{};
     d.W = a.W;
@@ -729,12 +508,14 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
     d.g_rec = a.g_rec;
     d.g_fin = a.g_fin;
     d.u = a.u;
+    d.rec = nullptr;
     d.n = n;
     d.n_in = a.n_in;
     d.substeps = a.substeps;
     d.renorm = a.renorm;
+    d.S = NS;
     d.ld = ld;
-    d.steps = S;
+    d.steps = NSTEP;
     T* cps = nullptr;
     ADJ_TRY(mem.get(&d.m, vec));
     ADJ_TRY(mem.get(&d.ms[0], vec));
@@ -744,54 +525,71 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
     ADJ_TRY(mem.get(&d.mbar, vec));
     ADJ_TRY(mem.get(&d.loc, vec));
     ADJ_TRY(mem.get(&cps, vec * (size_t)nseg));
-    ADJ_TRY(mem.get(&d.xt, (size_t)K * 4 * 3 * ld * sizeof(T)));
-    ADJ_TRY(mem.get(&d.wx, (size_t)K * 4 * C * ld * sizeof(T)));
-    ADJ_TRY(mem.get(&d.st, (size_t)K * 4 * C * ld * sizeof(T)));
-    ADJ_TRY(mem.get(&d.pn, (size_t)K * ld * sizeof(T)));
-    ADJ_TRY(mem.get(&d.gacc, (size_t)4 * ld * sizeof(double)));
-    ADJ_TRY(mem.get(&d.gwin, (size_t)std::max(1, a.n_in) * ld * sizeof(double)));
+    ADJ_TRY(mem.get(&d.xt, (size_t)K * 4 * 3 * per_stage));
+    ADJ_TRY(mem.get(&d.wx, (size_t)K * 4 * C * per_stage));
+    ADJ_TRY(mem.get(&d.st, (size_t)K * 4 * C * per_stage));
+    ADJ_TRY(mem.get(&d.pn, (size_t)K * per_stage));
+    ADJ_TRY(mem.get(&d.gacc, (size_t)4 * NS * ld * sizeof(double)));
+    ADJ_TRY(mem.get(&d.gwin, (size_t)std::max(1, a.n_in) * NS * ld * sizeof(double)));
     // zero everything whose padding is read (stage inputs, coupling adjoints)
     // and every accumulator
     for (T* p : {d.m, d.ms[0], d.ms[1], d.acc, d.abar, d.mbar, d.loc}) ADJ_TRY(hipMemsetAsync(p, 0, vec, st));
-    ADJ_TRY(hipMemsetAsync(d.st, 0, (size_t)K * 4 * C * ld * sizeof(T), st));
-    ADJ_TRY(hipMemsetAsync(d.gacc, 0, (size_t)4 * ld * sizeof(double), st));
-    ADJ_TRY(hipMemsetAsync(d.gwin, 0, (size_t)std::max(1, a.n_in) * ld * sizeof(double), st));
+    ADJ_TRY(hipMemsetAsync(d.st, 0, (size_t)K * 4 * C * per_stage, st));
+    ADJ_TRY(hipMemsetAsync(d.gacc, 0, (size_t)4 * NS * ld * sizeof(double), st));
+    ADJ_TRY(hipMemsetAsync(d.gwin, 0, (size_t)std::max(1, a.n_in) * NS * ld * sizeof(double), st));
 
-    const dim3 pgrid((n + 255) / 256), pblock(256);
+    const dim3 pgrid((n + 255) / 256, NS), pblock(256);
     const Coef<T> k = a.k;
+    // one forward / reversed stage: streamed mat-vecs for one stream, the
+    // FP32 MFMA product of all streams otherwise
+    auto fwd_stage = [&](int kk, int stage, int trace) {
+        if (NS == 1) {
+            launch_fwd<T, XYZ>(rows, unroll, st, d, k, kk, stage, trace);
+        } else if constexpr (sizeof(T) == 4) {
+            launch_batch_fwd(d, k, kk, stage, stage & 1, trace, XYZ, st);
+        }
+    };
+    auto rev_stage = [&](int kk, int stage) {
+        if (NS == 1) {
+            launch_rev<T, XYZ>(rows, unroll, st, d, k, kk, stage);
+        } else if constexpr (sizeof(T) == 4) {
+            launch_batch_rev(d, k, kk, stage, XYZ, st);
+        }
+    };
     // forward over local steps [0, kn) of the segment starting at j0; the
     // state is in m and ms[0] (cur = 0 between steps)
     auto forward = [&](int64_t j0, int64_t kn, int trace) -> hipError_t {
         d.j0 = j0;
         for (int64_t kk = 0; kk < kn; ++kk)
-            for (int stage = 0; stage < 4; ++stage) launch_fwd<T, XYZ>(rows, unroll, st, d, k, (int)kk, stage, trace);
+            for (int stage = 0; stage < 4; ++stage) fwd_stage((int)kk, stage, trace);
         return hipGetLastError();
     };
-    if (S > 0) {
+    if (NSTEP > 0) {
         hipLaunchKernelGGL(k_load_state<T>, pgrid, pblock, 0, st, a.m_start, d.m, d.ms[0], n, ld);
         ADJ_TRY(hipGetLastError());
     }
     // pass 1: checkpoints; the last segment is traced directly
     for (int64_t g = 0; g < nseg; ++g) {
-        const int64_t j0 = g * K, kn = std::min(K, S - j0);
-        ADJ_TRY(hipMemcpyAsync(cps + (size_t)g * 3 * ld, d.m, vec, hipMemcpyDeviceToDevice, st));
+        const int64_t j0 = g * K, kn = std::min(K, NSTEP - j0);
+        ADJ_TRY(hipMemcpyAsync(cps + (size_t)g * 3 * ld * NS, d.m, vec, hipMemcpyDeviceToDevice, st));
         ADJ_TRY(forward(j0, kn, g == nseg - 1));
     }
     int gw_started = 0;
     for (int64_t g = nseg - 1; g >= 0; --g) {
-        const int64_t j0 = g * K, kn = std::min(K, S - j0);
+        const int64_t j0 = g * K, kn = std::min(K, NSTEP - j0);
         if (g < nseg - 1) {
-            ADJ_TRY(hipMemcpyAsync(d.m, cps + (size_t)g * 3 * ld, vec, hipMemcpyDeviceToDevice, st));
+            ADJ_TRY(hipMemcpyAsync(d.m, cps + (size_t)g * 3 * ld * NS, vec, hipMemcpyDeviceToDevice, st));
             ADJ_TRY(hipMemcpyAsync(d.ms[0], d.m, vec, hipMemcpyDeviceToDevice, st));
             ADJ_TRY(forward(j0, kn, 1));
         }
         d.j0 = j0;
         hipLaunchKernelGGL((k_adj_prep<T, XYZ>), pgrid, pblock, 0, st, d, k, (int)(kn - 1));
         for (int64_t kk = kn - 1; kk >= 0; --kk)
-            for (int stage = 3; stage >= 0; --stage) launch_rev<T, XYZ>(rows, unroll, st, d, k, (int)kk, stage);
+            for (int stage = 3; stage >= 0; --stage) rev_stage((int)kk, stage);
         ADJ_TRY(hipGetLastError());
         if (a.g_W) {
-            const int L = (int)(kn * 4 * C);
+            // rows of the panels: (step, stage, stream, component), pitch ld
+            const int L = (int)(kn * 4 * NS * C);
             const int64_t xld = XYZ ? ld : 3 * ld;
             if constexpr (sizeof(T) == 4) {
                 const dim3 ggrid((n + 127) / 128, (n + 127) / 128);
@@ -807,19 +605,21 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
         }
     }
     if (a.g_W && !gw_started) ADJ_TRY(hipMemsetAsync(a.g_W, 0, (size_t)n * n * sizeof(T), st));
-    if (S == 0) {
+    if (NSTEP == 0) {
         // no step: dL/dm0 is the final-state gradient
+        const size_t mb = (size_t)NS * n * 3 * sizeof(T);
         if (a.g_fin && a.g_m0)
-            ADJ_TRY(hipMemcpyAsync(a.g_m0, a.g_fin, (size_t)n * 3 * sizeof(T), hipMemcpyDeviceToDevice, st));
+            ADJ_TRY(hipMemcpyAsync(a.g_m0, a.g_fin, mb, hipMemcpyDeviceToDevice, st));
         else if (a.g_m0)
-            ADJ_TRY(hipMemsetAsync(a.g_m0, 0, (size_t)n * 3 * sizeof(T), st));
+            ADJ_TRY(hipMemsetAsync(a.g_m0, 0, mb, st));
         if (a.g_win) ADJ_TRY(hipMemsetAsync(a.g_win, 0, (size_t)n * a.n_in * sizeof(T), st));
     } else if (a.g_m0 || a.g_win) {
-        hipLaunchKernelGGL(k_adj_outputs<T>, pgrid, pblock, 0, st, d.mbar, d.gwin, a.g_m0, a.g_win, n, a.n_in, ld);
+        hipLaunchKernelGGL(k_adj_outputs<T>, dim3((n + 255) / 256), pblock, 0, st, d.mbar, d.gwin, a.g_m0, a.g_win,
+                           n, a.n_in, NS, ld);
         ADJ_TRY(hipGetLastError());
     }
     if (a.g_scal) {
-        hipLaunchKernelGGL(k_adj_scalars, dim3(1), dim3(256), 0, st, d.gacc, n, ld, a.g_scal);
+        hipLaunchKernelGGL(k_adj_scalars, dim3(1), dim3(256), 0, st, d.gacc, n, NS, ld, a.g_scal);
         ADJ_TRY(hipGetLastError());
     }
     // the workspace is freed on return: wait for the work that uses it
@@ -828,9 +628,9 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
 
 }  // namespace
 
-int64_t adjoint_trace_bytes_per_step(int64_t ld, int elem_bytes, int xyz) {
+int64_t adjoint_trace_bytes_per_step(int64_t ld, int elem_bytes, int xyz, int streams) {
     const int C = xyz ? 3 : 1;
-    return (int64_t)(4 * (3 + 2 * C) + 1) * ld * elem_bytes;
+    return (int64_t)(4 * (3 + 2 * C) + 1) * ld * elem_bytes * streams;
 }
 
 template <typename T>

@@ -13,19 +13,20 @@ struct AdjArgs {
     const T* Wt;         // n x ld, the transpose of W, zero padding
     const T* w_in;       // n x n_in
     int n, n_in;
+    int streams;         // S input streams sharing W (S > 1: FP32 only)
     int64_t ld;
     Coef<T> k;
     int substeps, renorm, xyz;
     // run
-    const double* u;     // device, (steps / substeps) x n_in
+    const double* u;     // device, (steps / substeps) x S x n_in
     int64_t steps;
-    const T* m_start;    // device, n x 3 AoS
-    const T* g_rec;      // device, (steps / substeps) x n x 3 AoS: dL/d(record); or nullptr
-    const T* g_fin;      // device, n x 3 AoS: dL/d(final state); or nullptr
+    const T* m_start;    // device, S x n x 3 AoS
+    const T* g_rec;      // device, (steps / substeps) x S x n x 3 AoS: dL/d(record); or nullptr
+    const T* g_fin;      // device, S x n x 3 AoS: dL/d(final state); or nullptr
     // outputs (device; each may be nullptr)
     T* g_W;              // n x n, row-major, no padding
     T* g_win;            // n x n_in
-    T* g_m0;             // n x 3 AoS
+    T* g_m0;             // S x n x 3 AoS
     double* g_scal;      // 4: a_cp, a_in, h_s, h_appl
     int64_t seg_steps;   // RK4 steps per recomputed segment (>= 1)
     int* bad;            // device flag: first non-finite sample (INT_MAX: none)
@@ -33,7 +34,7 @@ struct AdjArgs {
 };
 
 // Bytes of the per-step stage trace (the workspace per step of a segment).
-int64_t adjoint_trace_bytes_per_step(int64_t ld, int elem_bytes, int xyz);
+int64_t adjoint_trace_bytes_per_step(int64_t ld, int elem_bytes, int xyz, int streams);
 
 template <typename T>
 hipError_t transpose_matrix(const T* W, T* Wt, int n, int64_t ld, hipStream_t st);
@@ -42,6 +43,25 @@ hipError_t transpose_matrix(const T* W, T* Wt, int n, int64_t ld, hipStream_t st
 // by segment.  Allocates and frees its own workspace.
 template <typename T>
 hipError_t adjoint_run(const AdjArgs<T>& a);
+
+// One plain run of the BATCH path (S streams, one launch per RK4 stage,
+// coupling of all streams as one FP32 MFMA product; sto_batch.hip).
+struct BatchRun {
+    const float* W;      // n x ld
+    const float* Wt;     // n x ld, transpose of W
+    const float* w_in;   // n x n_in
+    float* m;            // [S][3][ld]
+    float* ms[2];        // [S][3][ld]; the state is in ms[cur] between steps
+    float* acc;          // [S][3][ld]
+    int* bad;
+    const double* u;     // samples x S x n_in
+    float* states;       // samples x S x n x 3, or nullptr
+    Coef<float> k;
+    int n, n_in, streams, substeps, renorm, xyz, samples, cur;
+    int64_t ld;
+    hipStream_t stream;
+};
+hipError_t run_batch(const BatchRun& b);
 
 // Gradient of the ridge objective at its optimum with respect to the records
 // (readout.hip).  rec_dev: T x n x 3 records (FP32 if rec_f32); w_dev: the

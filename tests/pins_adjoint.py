@@ -3,6 +3,7 @@
 None of these re-types the adjoint.  Each derivative is obtained a second,
 independent way:
 
+* central finite differences (h = 1e-6) of the forward oracle in FP64;
 * complex-step differentiation of the forward oracle: the forward RK4 map
   is evaluated with one input moved by i*h (h = 1e-20), and Im L / h is the
   exact directional derivative up to rounding (no cancellation, unlike
@@ -163,5 +164,27 @@ def pin_ridge_envelope(**_):
         assert abs(mine - cs) <= 1e-9 * max(1.0, abs(cs)), (comps, mine, cs)
 
 
-ADJOINT_PINS = [pin_adjoint_complex_step, pin_adjoint_precession]
+def pin_adjoint_central_fd(vjp=None, reverse=None, **_):
+    """Central finite differences (h = 1e-6) of the forward oracle in FP64
+    agree with the adjoint to 1e-7 relative (truncation ~h^2, rounding
+    ~1e-16/h), for the four scalars and a random direction of W."""
+    w, w_in, m0, u, prm, g_rec, g_fin = adjoint_case("xyz", True)
+    got = adjoint.run_adjoint(w, w_in, m0, u, prm, g_rec, g_fin, dot="blas", vjp=vjp, reverse=reverse)
+
+    def loss(p, ww):
+        rec, fin = sto.run(ww, w_in, m0, u, p, dot="blas")
+        return float(np.sum(rec * g_rec) + np.sum(fin * g_fin))
+
+    h = 1e-6
+    for name in SCALARS:
+        v = getattr(prm, name)
+        fd = (loss(prm.replace(**{name: v + h}), w) - loss(prm.replace(**{name: v - h}), w)) / (2 * h)
+        assert abs(fd - got[name]) <= 1e-7 * max(1.0, abs(fd)), (name, fd, got[name])
+    d_w = np.random.default_rng(9).standard_normal(w.shape)
+    fd = (loss(prm, w + h * d_w) - loss(prm, w - h * d_w)) / (2 * h)
+    mine = float(np.sum(got["W"] * d_w))
+    assert abs(fd - mine) <= 1e-7 * max(1.0, abs(fd)), (fd, mine)
+
+
+ADJOINT_PINS = [pin_adjoint_complex_step, pin_adjoint_precession, pin_adjoint_central_fd]
 ALL = ADJOINT_PINS + [pin_ridge_envelope]

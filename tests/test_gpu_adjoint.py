@@ -166,16 +166,11 @@ def test_adjoint_rejects_and_reports(stx):
     w, w_in, m0, u, prm, g_rec, g_fin = case(8, seed=4)
     with stx.Reservoir(w, w_in, m0, lib_params(prm, "f64")) as r:
         with pytest.raises(stx.StoError) as e:
-            stx.reservoir_adjoint(r.h, 8, 1, m0, u, 7, None, None)      # not a multiple of substeps
+            stx.reservoir_adjoint(r.h, 8, 1, prm.substeps, m0, u, 7, None, None)   # not a multiple of substeps
         assert e.value.status == stx.STO_E_INVALID
         with pytest.raises(stx.StoError) as e:
             r.adjoint(m0, u, checkpoint_every=-1)
         assert e.value.status == stx.STO_E_INVALID
-    streams_prm = lib_params(oracle_params(), "f32")
-    with stx.Reservoir(w, w_in, np.stack([m0, m0]), streams_prm, streams=2) as r2:
-        with pytest.raises(stx.StoError) as e:
-            stx.reservoir_adjoint(r2.h, 8, 1, m0, u, 20, None, None)
-        assert e.value.status == stx.STO_E_UNSUPPORTED
     # a state that becomes non-finite (lambda = -1 and m along p: 1 + lambda m.p = 0)
     prm_bad = oracle_params(substeps=2).replace(lam=-1.0)
     m_p = np.tile(np.array([[1.0, 0.0, 0.0]]), (8, 1))
@@ -232,3 +227,130 @@ def test_autograd_end_to_end(stx):
     got = {"W": W.grad.numpy(), "w_in": WIN.grad.numpy(), "m0": M0.grad.numpy()}
     got.update({k: float(t.grad) for k, t in zip(SCALARS, sc)})
     compare(got, ref, 1e-8, "autograd")
+
+
+# ---------------------------------------------------------------------------
+# S input streams sharing W (the batched FP32 adjoint)
+# ---------------------------------------------------------------------------
+def oracle_streams_adjoint(w, w_in, m0s, u, prm, g_rec, g_fin, dot="blas"):
+    """The oracle's adjoint run once per stream: dL/dW, dL/dw_in and the
+    scalars of the shared reservoir sum over the streams."""
+    tot = {}
+    m0 = []
+    for s in range(m0s.shape[0]):
+        r = adjoint.run_adjoint(w, w_in, m0s[s], u[:, s], prm, g_rec[:, s],
+                                None if g_fin is None else g_fin[s], dot=dot)
+        m0.append(r["m0"])
+        for k in ("W", "w_in") + SCALARS:
+            tot[k] = tot.get(k, 0.0) + (np.asarray(r[k]) if k in ("W", "w_in") else r[k])
+    tot["m0"] = np.stack(m0)
+    return tot
+
+
+def unit_states(rng, streams, n, spread=0.3):
+    v = rng.standard_normal((streams, n, 3)) * spread
+    v[..., 2] += 1.0
+    return v / np.linalg.norm(v, axis=2, keepdims=True)
+
+
+@pytest.mark.parametrize("coupling,seg", [("x", 0), ("xyz", 3)])
+def test_adjoint_streams_matches_oracle(stx, coupling, seg):
+    n, S, samples, sub = 40, 3, 3, 4
+    w, w_in, _, _ = random_case(n, seed=21, samples=1, spread=0.3)
+    rng = np.random.default_rng(22)
+    m0s = unit_states(rng, S, n)
+    u = rng.uniform(-1, 1, (samples, S, 1))
+    prm = oracle_params(a_cp=0.3, a_in=0.7, substeps=sub, coupling=coupling)
+    g_rec = np.float32(rng.standard_normal((samples, S, n, 3))).astype(np.float64)
+    g_fin = np.float32(rng.standard_normal((S, n, 3))).astype(np.float64)
+    w, w_in = (np.float32(a).astype(np.float64) for a in (w, w_in))
+    say(f"adjoint streams S={S} n={n} {coupling} seg={seg}")
+    ref = oracle_streams_adjoint(w, w_in, np.float32(m0s).astype(np.float64), u, prm, g_rec, g_fin)
+    with stx.Reservoir(w, w_in, m0s, lib_params(prm, "f32"), streams=S) as r:
+        got = r.adjoint(m0s, u, g_rec, g_fin, checkpoint_every=seg)
+    compare(got, ref, F32_TOL, f"streams {coupling}")
+
+
+def test_adjoint_streams64_xyz_oracle_and_central_fd(stx):
+    """The differentiation workload's shape: N = 512, 64 input streams sharing
+    W, all three components coupled (the N x 192 product), one input sample
+    of 5 RK4 steps.  The GPU adjoint (FP32) against the oracle's adjoint, and
+    the oracle's adjoint against FP64 central differences (h = 1e-6) of the
+    oracle's forward for the four scalars and a random direction of W."""
+    from workloads import STREAMS, WORKLOADS, make_stream_arrays
+    wl = WORKLOADS["streams64"]
+    S = STREAMS["streams64"]
+    a = make_stream_arrays(wl, S, samples=1)
+    prm = oracle_params(a_cp=wl.a_cp, a_in=wl.a_in, coupling="xyz", substeps=5)
+    rng = np.random.default_rng(64)
+    m0s = unit_states(rng, S, wl.n, spread=0.05)
+    g_rec = np.float32(rng.standard_normal((1, S, wl.n, 3))).astype(np.float64)
+    w, w_in = (np.float32(x).astype(np.float64) for x in (a["W"], a["w_in"]))
+    m0_ref = np.float32(m0s).astype(np.float64)
+    say("adjoint streams64 xyz")
+    ref = oracle_streams_adjoint(w, w_in, m0_ref, a["u"], prm, g_rec, None)
+    with stx.Reservoir(w, w_in, m0s, lib_params(prm, "f32"), streams=S) as r:
+        assert r.path == "batch"
+        got = r.adjoint(m0s, a["u"], g_rec, checkpoint_every=2)
+    compare(got, ref, F32_TOL, "streams64 xyz")
+
+    def loss(p, ww):
+        tot = 0.0
+        for s in range(S):
+            rec, _ = sto.run(ww, w_in, m0_ref[s], a["u"][:, s], p, dot="blas")
+            tot += float(np.sum(rec * g_rec[:, s]))
+        return tot
+
+    h = 1e-6
+    errs = {}
+    for name in SCALARS:
+        v = getattr(prm, name)
+        fd = (loss(prm.replace(**{name: v + h}), w) - loss(prm.replace(**{name: v - h}), w)) / (2 * h)
+        errs[name] = abs(fd - ref[name]) / max(abs(ref[name]), 1e-30)
+    d_w = rng.standard_normal(w.shape)
+    fd = (loss(prm, w + h * d_w) - loss(prm, w - h * d_w)) / (2 * h)
+    mine = float(np.sum(ref["W"] * d_w))
+    errs["W"] = abs(fd - mine) / abs(mine)
+    say("  oracle adjoint vs central differences", {k: f"{v:.1e}" for k, v in errs.items()})
+    assert max(errs.values()) <= 1e-6
+
+
+def test_adjoint_matches_central_fd_f64(stx):
+    """dJ of the ridge objective of a GPU run (FP64, 12 samples x 20 steps)
+    by the adjoint against central differences (h = 1e-6) of GPU runs."""
+    import torch
+    n, samples, washout, lam = 64, 12, 2, 1e-4
+    w, w_in, m0, u = random_case(n, seed=31, samples=samples, spread=0.3)
+    prm = oracle_params(a_cp=0.3, a_in=0.7)
+    y = np.tanh(np.convolve(u[:, 0], np.ones(5))[:samples])
+    u_d = torch.from_numpy(u).cuda()
+    y_d = torch.from_numpy(y).cuda()
+
+    def objective(p, ww, grad=False):
+        with stx.Reservoir(ww, w_in, m0, lib_params(p, "f64")) as r:
+            st = torch.empty((samples, n, 3), dtype=torch.float64, device="cuda")
+            r.run_device(u_d, st)
+            w_d, _ = stx.readout_fit_device(st, y_d, washout, lam)
+            g, j = stx.readout_grad_device(st, y_d, washout, lam, w_d)
+            if not grad:
+                return j
+            out = r.adjoint_device(torch.from_numpy(m0).cuda(), u_d, grad_states_dev=g)
+            torch.cuda.synchronize()
+            return j, out
+
+    say("adjoint vs central differences (GPU, f64)")
+    _, out = objective(prm, w, grad=True)
+    scal = out["scalars"].cpu().numpy()
+    gw = out["W"].cpu().numpy()
+    h = 1e-6
+    errs = {}
+    for q, name in enumerate(SCALARS):
+        v = getattr(prm, name)
+        fd = (objective(prm.replace(**{name: v + h}), w) - objective(prm.replace(**{name: v - h}), w)) / (2 * h)
+        errs[name] = abs(fd - scal[q]) / max(abs(scal[q]), 1e-30)
+    d_w = np.random.default_rng(32).standard_normal(w.shape)
+    fd = (objective(prm, w + h * d_w) - objective(prm, w - h * d_w)) / (2 * h)
+    mine = float(np.sum(gw * d_w))
+    errs["W"] = abs(fd - mine) / abs(mine)
+    say("  ", {k: f"{v:.1e}" for k, v in errs.items()})
+    assert max(errs.values()) <= 1e-6

@@ -106,8 +106,80 @@ def test_multi_continuation_and_state(stx):
 def test_multi_rejects_unsupported(stx):
     w, w_in, m0, _ = random_case(20, seed=5, samples=1)
     m0s = np.broadcast_to(m0, (3, 20, 3)).copy()
-    for kw in (dict(dtype="f64"), dict(dtype="f32", coupling="xyz")):
+    for kw in (dict(dtype="f64"), dict(dtype="f32", coupling="xyz", path="multi")):
         prm = oracle_params(coupling=kw.get("coupling", "x"))
         with pytest.raises(stx.StoError) as ei:
-            stx.Reservoir(w, w_in, m0s, lib_params(prm, dtype=kw["dtype"]), streams=3)
+            stx.Reservoir(w, w_in, m0s, lib_params(prm, dtype=kw["dtype"], path=kw.get("path", "auto")), streams=3)
         assert ei.value.status == stx.STO_E_UNSUPPORTED
+    # isotropic coupling with several streams runs on the per-stage batch path
+    with stx.Reservoir(w, w_in, m0s, lib_params(oracle_params(coupling="xyz"), dtype="f32"), streams=3) as r:
+        assert r.path == "batch"
+
+
+# ---------------------------------------------------------------------------
+# BATCH path: the same product, one launch per RK4 stage, both couplings
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,streams,coupling", [(16, 2, "x"), (100, 5, "xyz"), (257, 17, "x"), (512, 64, "xyz"),
+                                                (1100, 3, "x")])
+def test_batch_one_step_matches_oracle(stx, n, streams, coupling):
+    """One RK4 step per stream from the same FP32-representable state."""
+    w, w_in, m0, u = stream_case(n, streams, seed=n + 1, samples=1)
+    prm = oracle_params(a_cp=0.3, substeps=1, coupling=coupling)
+    say("batch one step", n, streams, coupling)
+    rng = np.random.default_rng(n)
+    m0s = np.empty((streams, n, 3))
+    for s in range(streams):
+        v = rng.standard_normal((n, 3)) * 0.05
+        v[:, 2] += 1.0
+        m0s[s] = v / np.linalg.norm(v, axis=1, keepdims=True)
+    with stx.Reservoir(w, w_in, m0s, lib_params(prm, dtype="f32", path="batch"), streams=streams) as r:
+        assert r.path == "batch"
+        rec = r.run(u)
+    worst = 0.0
+    for s in (range(streams) if streams <= 8 else (0, 1, streams // 2, streams - 1)):
+        rec_o, _ = sto.run(f32(w), f32(w_in), f32(m0s[s]), u[:, s], prm)
+        worst = max(worst, float(np.max(np.abs(rec[:, s] - rec_o))))
+    say("  max diff", worst)
+    assert worst <= F32_TOL
+
+
+def test_batch_streams64_xyz_lyapunov_horizon(stx):
+    """The 64-stream, 512-node workload with all three components coupled
+    (the N x 3S product), over ~one Lyapunov time (8 samples = 160 steps),
+    per stream against the FP64 oracle."""
+    wl = WORKLOADS["streams64"]
+    S = STREAMS["streams64"]
+    a = make_stream_arrays(wl, S, samples=8)
+    prm = oracle_params(a_cp=wl.a_cp, a_in=wl.a_in, coupling="xyz")
+    m0s = np.broadcast_to(a["m0"], (S, wl.n, 3)).copy()
+    say("streams64 xyz horizon")
+    with stx.Reservoir(a["W"], a["w_in"], m0s, lib_params(prm, dtype="f32"), streams=S) as r:
+        assert r.path == "batch"
+        rec = r.run(a["u"])
+    worst = 0.0
+    for s in (0, 7, 31, 63):
+        rec_o, _ = sto.run(a["W"], a["w_in"], a["m0"], a["u"][:, s], prm)
+        worst = max(worst, float(np.max(np.abs(rec[:, s] - rec_o))))
+    say("  max diff", worst)
+    assert worst <= F32_TOL
+
+
+def test_batch_continuation_and_agreement(stx):
+    """Split runs equal the whole run bitwise; the batch and the persistent
+    multi-stream paths agree to FP32 rounding."""
+    n, S = 70, 9
+    w, w_in, m0, u = stream_case(n, S, seed=3, samples=6)
+    prm = oracle_params(a_cp=0.3)
+    m0s = np.broadcast_to(m0, (S, n, 3)).copy()
+    with stx.Reservoir(w, w_in, m0s, lib_params(prm, dtype="f32", path="batch"), streams=S) as r:
+        whole = r.run(u)
+        fin = r.get_state()
+        r.set_state(m0s)
+        a = r.run(u[:2])
+        b = r.run(u[2:])
+        assert np.array_equal(r.get_state(), fin)
+    assert np.array_equal(np.concatenate([a, b]), whole)
+    with stx.Reservoir(w, w_in, m0s, lib_params(prm, dtype="f32", path="multi"), streams=S) as r:
+        multi = r.run(u)
+    say("batch vs multi", float(np.max(np.abs(multi - whole))))
+    assert np.max(np.abs(multi - whole)) <= 1e-5
