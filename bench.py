@@ -216,8 +216,9 @@ def run_adjoint_workload(stx, torch, name: str, dtype: str, samples: int, steps:
     }
 
 
-def run_streams_workload(stx, torch, name: str, steps: int, warmup: int):
-    """S input streams share one reservoir (MULTI path, FP32 MFMA coupling);
+def run_streams_workload(stx, torch, name: str, steps: int, warmup: int, coupling: str = "x"):
+    """S input streams share one reservoir (FP32 MFMA coupling: the MULTI
+    path for x coupling, the per-stage BATCH path for all three components);
     one step is the run of every stream plus one readout per stream.  The
     same work through the plain single-reservoir path is timed on one stream
     and scaled by S."""
@@ -227,7 +228,8 @@ def run_streams_workload(stx, torch, name: str, steps: int, warmup: int):
     wl = WORKLOADS[name]
     S = STREAMS[name]
     a = make_stream_arrays(wl, S)
-    prm = stx.make_params(**params.table1(a_cp=wl.a_cp, a_in=wl.a_in, dt=wl.dt, substeps=wl.substeps), dtype="f32")
+    prm = stx.make_params(**params.table1(a_cp=wl.a_cp, a_in=wl.a_in, dt=wl.dt, substeps=wl.substeps), dtype="f32",
+                          coupling=coupling)
     import numpy as np
     m0s = np.ascontiguousarray(np.broadcast_to(a["m0"], (S, wl.n, 3)))
     r = stx.Reservoir(a["W"], a["w_in"], m0s, prm, streams=S)
@@ -276,16 +278,101 @@ def run_streams_workload(stx, torch, name: str, steps: int, warmup: int):
     plain_ms = e0.elapsed_time(e1) * S
     r1.close()
     wall_s = (t1 - t0) / steps
-    flops = 2.0 * wl.n * wl.n * S * 4 * wl.steps
+    C = 3 if coupling == "xyz" else 1
+    flops = 2.0 * wl.n * wl.n * S * C * 4 * wl.steps
     return {
-        "workload": name, "n": wl.n, "streams": S, "dtype": "f32", "path": path, "samples": wl.samples,
+        "workload": name, "n": wl.n, "streams": S, "coupling": coupling, "dtype": "f32", "path": path,
+        "samples": wl.samples,
         "substeps": wl.substeps, "rk4_steps": wl.steps,
         "value": S * wl.n * wl.steps / wall_s, "ms_per_step": wall_s * 1e3, "run_ms": run_ms,
         "us_per_rk4_step": run_ms * 1e3 / wl.steps, "readout_nmse_mean": float(np.mean(nmse)),
-        "kernel": "k_multi", "mfma_tflops": flops / (run_ms * 1e-3) / 1e12,
+        "kernel": "k_multi" if path == "multi" else "k_bfwd", "mfma_tflops": flops / (run_ms * 1e-3) / 1e12,
         "mfma_frac": flops / (run_ms * 1e-3) / 157.3e12,
         "plain_path": plain_path, "plain_run_ms_for_all_streams": plain_ms,
         "speedup_vs_plain": plain_ms / run_ms,
+    }
+
+
+def run_streams_adjoint_workload(stx, torch, name: str, coupling: str, steps: int, warmup: int,
+                                 checkpoint_every: int = 100):
+    """The differentiation workload: S input streams share one reservoir;
+    one step is the forward run of every stream, one ridge readout and its
+    objective's gradient per stream, and the adjoint of all streams
+    (gradients of the summed objective with respect to W, w_in, every
+    stream's m0 and the four scalars), with a state checkpoint every
+    `checkpoint_every` RK4 steps.  The coupling is all three components (an
+    N x N by N x 3S product per stage) or x only.  The coupling and input
+    amplitudes are the paper's (A_cp = A_in = 1 Oe): at the workload's
+    a_cp = 0.1, a_in = 1 the trajectory is chaotic (largest Lyapunov exponent
+    about 0.5 per ns), and the adjoint of a 200 ns horizon grows by ~e^100,
+    beyond the FP32 range."""
+    import numpy as np
+    from workloads import STREAMS, WORKLOADS, make_stream_arrays
+    from paper_2312_01121_amd import params
+
+    wl = WORKLOADS[name]
+    S = STREAMS[name]
+    a = make_stream_arrays(wl, S)
+    amp = params.field_unit()          # 1 Oe in the dimensionless unit
+    prm = stx.make_params(**params.table1(a_cp=amp, a_in=amp, dt=wl.dt, substeps=wl.substeps),
+                          dtype="f32", coupling=coupling)
+    m0s = np.ascontiguousarray(np.broadcast_to(a["m0"], (S, wl.n, 3)))
+    r = stx.Reservoir(a["W"], a["w_in"], m0s, prm, streams=S)
+    path = r.path
+    u_d = torch.from_numpy(a["u"]).cuda()
+    y = np.nan_to_num(a["y"], nan=0.0)
+    y_d = [torch.from_numpy(np.ascontiguousarray(y[:, st])).cuda() for st in range(S)]
+    m0_d = torch.from_numpy(m0s).to("cuda", torch.float32).contiguous()
+    states = torch.empty((wl.samples, S, wl.n, 3), dtype=torch.float32, device="cuda")
+    g_rec = torch.empty_like(states)
+    wash = washout_of(wl.samples)
+    stream = torch.cuda.current_stream()
+
+    def one_step():
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        r.set_state(m0s)
+        ev[0].record(stream)
+        r.run_device(u_d, states, stream)
+        ev[1].record(stream)
+        loss = 0.0
+        for st in range(S):
+            rec = states[:, st].contiguous()
+            w_d, _ = stx.readout_fit_device(rec, y_d[st], wash, wl.ridge, 0, None, stream)
+            g, j = stx.readout_grad_device(rec, y_d[st], wash, wl.ridge, w_d, 0, None, stream)
+            g_rec[:, st] = g
+            loss += j
+        ev[2].record(stream)
+        out = r.adjoint_device(m0_d, u_d, grad_states_dev=g_rec, checkpoint_every=checkpoint_every, stream=stream)
+        ev[3].record(stream)
+        return ev, loss, out
+
+    for _ in range(warmup):
+        one_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [one_step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    wall_s = (time.perf_counter() - t0) / steps
+    fwd_ms = sum(ev[0].elapsed_time(ev[1]) for ev, _, _ in runs) / steps
+    loss_ms = sum(ev[1].elapsed_time(ev[2]) for ev, _, _ in runs) / steps
+    adj_ms = sum(ev[2].elapsed_time(ev[3]) for ev, _, _ in runs) / steps
+    out = runs[-1][2]
+    finite = all(bool(torch.isfinite(t).all()) for t in out.values())
+    r.close()
+    C = 3 if coupling == "xyz" else 1
+    segs = (wl.steps + checkpoint_every - 1) // checkpoint_every
+    last = wl.steps - (segs - 1) * checkpoint_every
+    products = 4 * (wl.steps + (wl.steps - last) + wl.steps)     # stage products of the adjoint
+    flops = products * 2.0 * wl.n * wl.n * S * C + 2.0 * wl.n * wl.n * 4 * wl.steps * S * C   # + dL/dW
+    return {
+        "workload": f"adjoint/{name}", "n": wl.n, "streams": S, "coupling": coupling, "dtype": "f32",
+        "a_cp": amp, "a_in": amp,
+        "forward_path": path, "samples": wl.samples, "rk4_steps": wl.steps, "checkpoint_every": checkpoint_every,
+        "value": S * wl.n * wl.steps / (adj_ms * 1e-3), "unit": "node-steps/s (gradient)",
+        "ms_per_step": wall_s * 1e3, "forward_ms": fwd_ms, "loss_ms": loss_ms, "adjoint_ms": adj_ms,
+        "adjoint_over_forward": adj_ms / fwd_ms, "us_per_rk4_step": adj_ms * 1e3 / wl.steps,
+        "mfma_tflops": flops / (adj_ms * 1e-3) / 1e12, "mfma_frac": flops / (adj_ms * 1e-3) / 157.3e12,
+        "ridge_objective_sum": runs[-1][1], "gradients_finite": finite,
     }
 
 
@@ -458,7 +545,8 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=("f32", "f64"))
     ap.add_argument("--no-also", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--adjoint", default=None, metavar="WORKLOAD:DTYPE:SAMPLES",
-                    help="time only the adjoint line for this workload (e.g. sto10k:f32:50)")
+                    help="time only the adjoint line for this workload (e.g. sto10k:f32:50; for the "
+                         "multi-stream workload the second field is the coupling: streams64:xyz:0)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--samples", type=int, default=None,
                     help="run only the first SAMPLES input samples of the main workload (short profiled runs)")
@@ -498,7 +586,10 @@ def main():
     from workloads import STREAMS, SWEEPS
     if args.adjoint:
         name, dt, samples = args.adjoint.split(":")
-        res = run_adjoint_workload(stx, torch, name, dt, int(samples), args.steps, args.warmup)
+        if name in STREAMS:
+            res = run_streams_adjoint_workload(stx, torch, name, dt, args.steps, args.warmup)
+        else:
+            res = run_adjoint_workload(stx, torch, name, dt, int(samples), args.steps, args.warmup)
         print(json.dumps({"adjoint": res}), flush=True)
         return
     if args.workload in SWEEPS or args.workload in STREAMS:
@@ -549,6 +640,14 @@ def main():
             res = run_adjoint_workload(stx, torch, name, dt, samples, 1, 1)
             log(json.dumps(res))
             also.append(res)
+        log("also streams64 xyz")
+        res = run_streams_workload(stx, torch, "streams64", 1, 1, coupling="xyz")
+        log(json.dumps(res))
+        also.append(res)
+        log("also adjoint streams64 xyz")
+        res = run_streams_adjoint_workload(stx, torch, "streams64", "xyz", 1, 1)
+        log(json.dumps(res))
+        also.append(res)
     cpu = None
     if not args.no_cpu:
         log("cpu baseline")

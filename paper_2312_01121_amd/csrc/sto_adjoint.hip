@@ -273,8 +273,12 @@ typedef float mf4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256) k_gw_mfma(const float* __restrict__ S, int64_t sld, const float* __restrict__ X,
                                                  int64_t xld, int L, int n, int64_t ld, float alpha,
-                                                 float* __restrict__ G, int accumulate) {
+                                                 float* __restrict__ G, int accumulate, int lchunk,
+                                                 float* __restrict__ part) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // slice z of the contraction (rows [lb, le)); with part, its partial
+    // tile goes to part[z] and k_gw_reduce sums the slices
+    const int lb = blockIdx.z * lchunk, le = min(L, lb + lchunk);
     const int i0 = blockIdx.y * 128 + (wave >> 1) * 64;
     const int j0 = blockIdx.x * 128 + (wave & 1) * 64;
     if (i0 >= n || j0 >= n) return;   // wave-uniform
@@ -298,8 +302,8 @@ __global__ void __launch_bounds__(256) k_gw_mfma(const float* __restrict__ S, in
     // offset 0: i0 + c16 < n <= ld), out-of-range operands are zeroed after.
     auto load = [&](int l0, float* ra, float* rb) {
         const int l = l0 + kr;
-        const bool vl = l < L;
-        const int64_t lc = vl ? l : L - 1;
+        const bool vl = l < le;
+        const int64_t lc = vl ? l : le - 1;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const float x = sp[lc * sld + (va[q] ? 16 * q : 0)];
@@ -309,8 +313,8 @@ __global__ void __launch_bounds__(256) k_gw_mfma(const float* __restrict__ S, in
             rb[q] = __uint_as_float(__float_as_uint(y) & mb);
         }
     };
-    load(0, a, b);
-    for (int l0 = 0; l0 < L; l0 += 4) {
+    load(lb, a, b);
+    for (int l0 = lb; l0 < le; l0 += 4) {
         float an[4], bn[4];
         load(l0 + 4, an, bn);
 #pragma unroll
@@ -334,10 +338,24 @@ __global__ void __launch_bounds__(256) k_gw_mfma(const float* __restrict__ S, in
             for (int bj = 0; bj < 4; ++bj) {
                 const int j = j0 + 16 * bj + c16;
                 if (j >= n) continue;
-                float* g = G + (int64_t)i * n + j;
-                *g = accumulate ? *g + alpha * acc[bi][bj][r] : alpha * acc[bi][bj][r];
+                if (part) {
+                    part[((int64_t)blockIdx.z * n + i) * n + j] = acc[bi][bj][r];
+                } else {
+                    float* g = G + (int64_t)i * n + j;
+                    *g = accumulate ? *g + alpha * acc[bi][bj][r] : alpha * acc[bi][bj][r];
+                }
             }
         }
+}
+
+// Sum of the contraction slices of k_gw_mfma in a fixed order.
+__global__ void __launch_bounds__(256) k_gw_reduce(const float* __restrict__ part, int splits, int64_t nn, float alpha,
+                                                   float* __restrict__ G, int accumulate) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nn; e += (int64_t)gridDim.x * blockDim.x) {
+        float v = part[e];
+        for (int z = 1; z < splits; ++z) v += part[z * nn + e];
+        G[e] = accumulate ? G[e] + alpha * v : alpha * v;
+    }
 }
 
 template <typename T>
@@ -538,6 +556,15 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
     ADJ_TRY(hipMemsetAsync(d.gacc, 0, (size_t)4 * NS * ld * sizeof(double), st));
     ADJ_TRY(hipMemsetAsync(d.gwin, 0, (size_t)std::max(1, a.n_in) * NS * ld * sizeof(double), st));
 
+    // FP32 dL/dW: the contraction is split into slices when the output has
+    // too few 128 x 128 tiles to fill the GPU (small n, long segments)
+    const int gw_tiles = ((n + 127) / 128) * ((n + 127) / 128);
+    auto gw_splits = [&](int L) { return std::max(1, std::min({64, 2048 / gw_tiles, L / 256})); };
+    float* gw_part = nullptr;
+    if (sizeof(T) == 4 && a.g_W) {
+        const int smax = gw_splits((int)(K * 4 * NS * C));
+        if (smax > 1) ADJ_TRY(mem.get(&gw_part, (size_t)smax * n * n * sizeof(float)));
+    }
     const dim3 pgrid((n + 255) / 256, NS), pblock(256);
     const Coef<T> k = a.k;
     // one forward / reversed stage: streamed mat-vecs for one stream, the
@@ -592,9 +619,17 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
             const int L = (int)(kn * 4 * NS * C);
             const int64_t xld = XYZ ? ld : 3 * ld;
             if constexpr (sizeof(T) == 4) {
-                const dim3 ggrid((n + 127) / 128, (n + 127) / 128);
+                const int splits = gw_part ? gw_splits(L) : 1;
+                const int lchunk = ((L + splits - 1) / splits + 3) / 4 * 4;
+                const int z = (L + lchunk - 1) / lchunk;
+                const dim3 ggrid((n + 127) / 128, (n + 127) / 128, z);
                 hipLaunchKernelGGL(k_gw_mfma, ggrid, dim3(256), 0, st, d.st, ld, d.xt, xld, L, n, ld, k.a_cp, a.g_W,
-                                   gw_started);
+                                   gw_started, lchunk, z > 1 ? gw_part : nullptr);
+                if (z > 1) {
+                    const int64_t nn = (int64_t)n * n;
+                    hipLaunchKernelGGL(k_gw_reduce, dim3((unsigned)std::min<int64_t>((nn + 255) / 256, 4096)),
+                                       dim3(256), 0, st, gw_part, z, nn, k.a_cp, a.g_W, gw_started);
+                }
             } else {
                 const dim3 ggrid((n + 63) / 64, (n + 63) / 64);
                 hipLaunchKernelGGL(k_gw<T>, ggrid, dim3(256), 0, st, d.st, ld, d.xt, xld, L, n, k.a_cp, a.g_W,

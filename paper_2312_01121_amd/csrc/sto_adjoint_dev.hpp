@@ -100,28 +100,47 @@ __device__ __forceinline__ void llg_vjp(const Coef<T>& k, T mx, T my, T mz, T cx
     hsp = hsbar / den;
 }
 
-// Pointwise adjoint of stage `stage` of local step kk at node i of stream s,
-// applied to v: stores the pointwise part of xbar (loc), the coupling
-// adjoint (st) and adds the node's parameter partials.
+// Inputs of the pointwise adjoint of one stage at node i of stream s: the
+// traced stage input, raw coupling sums and unscaled input sum.
+template <typename T>
+struct VjpIn {
+    T mx, my, mz, wxx, wxy, wxz, raw;
+    const double* u_s;
+};
+
 template <typename T, bool XYZ>
-__device__ __forceinline__ void stage_vjp(const AdjDev<T>& d, const Coef<T>& k, int i, int s, int kk, int stage,
-                                          T vx, T vy, T vz) {
+__device__ __forceinline__ VjpIn<T> vjp_load(const AdjDev<T>& d, int i, int s, int kk, int stage) {
     constexpr int C = XYZ ? 3 : 1;
     const int64_t ld = d.ld;
     const int S = d.S;
     const T* x = d.xt + adj_slot<3>(kk, stage, S, ld) + (int64_t)s * 3 * ld;
     const T* wx = d.wx + adj_slot<C>(kk, stage, S, ld) + (int64_t)s * C * ld;
-    const T mx = x[i], my = x[ld + i], mz = x[2 * ld + i];
-    const T wxx = wx[i];
-    const T wxy = XYZ ? wx[ld + i] : T(0);
-    const T wxz = XYZ ? wx[2 * ld + i] : T(0);
+    VjpIn<T> in;
+    in.mx = x[i];
+    in.my = x[ld + i];
+    in.mz = x[2 * ld + i];
+    in.wxx = wx[i];
+    in.wxy = XYZ ? wx[ld + i] : T(0);
+    in.wxz = XYZ ? wx[2 * ld + i] : T(0);
     const int64_t sample = (d.j0 + kk) / d.substeps;
-    const double* u_s = d.u + (sample * S + s) * d.n_in;
-    const T raw = input_dot<T>(d.w_in + (int64_t)i * d.n_in, u_s, d.n_in);
-    const T hin = k.a_in * raw;
+    in.u_s = d.u + (sample * S + s) * d.n_in;
+    in.raw = input_dot<T>(d.w_in + (int64_t)i * d.n_in, in.u_s, d.n_in);
+    return in;
+}
+
+// Pointwise adjoint of stage `stage` of local step kk at node i of stream s,
+// applied to v: stores the pointwise part of xbar (loc), the coupling
+// adjoint (st) and adds the node's parameter partials.
+template <typename T, bool XYZ>
+__device__ __forceinline__ void vjp_apply(const AdjDev<T>& d, const Coef<T>& k, int i, int s, int kk, int stage,
+                                          const VjpIn<T>& in, T vx, T vy, T vz) {
+    constexpr int C = XYZ ? 3 : 1;
+    const int64_t ld = d.ld;
+    const int S = d.S;
+    const T hin = k.a_in * in.raw;
     T gx, gy, gz, bx, by, bz, hsp;
-    llg_vjp<T, XYZ>(k, mx, my, mz, k.a_cp * wxx, k.a_cp * wxy, k.a_cp * wxz, hin, vx, vy, vz, gx, gy, gz, bx, by,
-                    bz, hsp);
+    llg_vjp<T, XYZ>(k, in.mx, in.my, in.mz, k.a_cp * in.wxx, k.a_cp * in.wxy, k.a_cp * in.wxz, hin, vx, vy, vz, gx,
+                    gy, gz, bx, by, bz, hsp);
     T* lc = d.loc + (int64_t)s * 3 * ld;
     lc[i] = gx;
     lc[ld + i] = gy;
@@ -132,14 +151,20 @@ __device__ __forceinline__ void stage_vjp(const AdjDev<T>& d, const Coef<T>& k, 
         sp[ld + i] = by;
         sp[2 * ld + i] = bz;
     }
-    double pcp = (double)bx * (double)wxx;
-    if (XYZ) pcp += (double)by * (double)wxy + (double)bz * (double)wxz;
+    double pcp = (double)bx * (double)in.wxx;
+    if (XYZ) pcp += (double)by * (double)in.wxy + (double)bz * (double)in.wxz;
     const int64_t gs = (int64_t)S * ld, gi = (int64_t)s * ld + i;
     d.gacc[gi] += pcp;
-    d.gacc[gs + gi] += (double)bx * (double)raw;
+    d.gacc[gs + gi] += (double)bx * (double)in.raw;
     d.gacc[2 * gs + gi] += (double)hsp;
     d.gacc[3 * gs + gi] += (double)bz;
-    for (int q = 0; q < d.n_in; ++q) d.gwin[q * gs + gi] += (double)k.a_in * (double)bx * u_s[q];
+    for (int q = 0; q < d.n_in; ++q) d.gwin[q * gs + gi] += (double)k.a_in * (double)bx * in.u_s[q];
+}
+
+template <typename T, bool XYZ>
+__device__ __forceinline__ void stage_vjp(const AdjDev<T>& d, const Coef<T>& k, int i, int s, int kk, int stage,
+                                          T vx, T vy, T vz) {
+    vjp_apply<T, XYZ>(d, k, i, s, kk, stage, vjp_load<T, XYZ>(d, i, s, kk, stage), vx, vy, vz);
 }
 
 // Start reversing local step kk (global step j = j0 + kk) of stream s:
@@ -180,27 +205,58 @@ __device__ __forceinline__ void prep_step(const AdjDev<T>& d, const Coef<T>& k, 
     stage_vjp<T, XYZ>(d, k, i, s, kk, 3, k.h6 * a[0], k.h6 * a[1], k.h6 * a[2]);
 }
 
-// Epilogue of a forward stage for node i of stream s, given the raw
-// coupling sums (dx, dy, dz): the right-hand side of Eq. (gov), the RK4
-// stage update (the arithmetic of the plain stage kernels), the stage trace
-// and, for plain runs, the record after the last step of a sample.
-template <typename T, bool XYZ>
-__device__ __forceinline__ void fwd_epilogue(const AdjDev<T>& d, const Coef<T>& k, int i, int s, int kk, int stage,
-                                             int cur, int trace, T dx, T dy, T dz) {
-    constexpr int C = XYZ ? 3 : 1;
+// Inputs of a forward stage's epilogue at node i of stream s (stage input,
+// state, RK4 accumulator, input field); none depends on the coupling sums,
+// so the multi-stream kernels load them before the product.
+template <typename T>
+struct FwdIn {
+    T sx, sy, sz, mx, my, mz, cx, cy, cz, hin;
+};
+
+template <typename T>
+__device__ __forceinline__ FwdIn<T> fwd_load(const AdjDev<T>& d, const Coef<T>& k, int i, int s, int kk, int stage,
+                                             int cur) {
     const int64_t ld = d.ld;
     const int64_t sb = (int64_t)s * 3 * ld;
     const T* xin = d.ms[cur] + sb;
+    const T* m = d.m + sb;
+    const T* acc = d.acc + sb;
+    const int sample = (int)((d.j0 + kk) / d.substeps);
+    FwdIn<T> in;
+    in.hin = input_field(k, d.w_in + (int64_t)i * d.n_in, d.u + ((int64_t)sample * d.S + s) * d.n_in, d.n_in);
+    in.sx = xin[i];
+    in.sy = xin[ld + i];
+    in.sz = xin[2 * ld + i];
+    in.mx = m[i];
+    in.my = m[ld + i];
+    in.mz = m[2 * ld + i];
+    in.cx = in.cy = in.cz = T(0);
+    if (stage > 0) {
+        in.cx = acc[i];
+        in.cy = acc[ld + i];
+        in.cz = acc[2 * ld + i];
+    }
+    return in;
+}
+
+// Epilogue of a forward stage for node i of stream s, given its inputs and
+// the raw coupling sums (dx, dy, dz): the right-hand side of Eq. (gov), the
+// RK4 stage update (the arithmetic of the plain stage kernels), the stage
+// trace and, for plain runs, the record after the last step of a sample.
+template <typename T, bool XYZ>
+__device__ __forceinline__ void fwd_finish(const AdjDev<T>& d, const Coef<T>& k, int i, int s, int kk, int stage,
+                                           int cur, int trace, const FwdIn<T>& in, T dx, T dy, T dz) {
+    constexpr int C = XYZ ? 3 : 1;
+    const int64_t ld = d.ld;
+    const int64_t sb = (int64_t)s * 3 * ld;
     T* xout = d.ms[cur ^ 1] + sb;
     const int64_t j = d.j0 + kk;
     const int sample = (int)(j / d.substeps);
-    const T hin = input_field(k, d.w_in + (int64_t)i * d.n_in, d.u + ((int64_t)sample * d.S + s) * d.n_in, d.n_in);
-    const T sx = xin[i], sy = xin[ld + i], sz = xin[2 * ld + i];
     if (trace) {
         T* x = d.xt + adj_slot<3>(kk, stage, d.S, ld) + sb;
-        x[i] = sx;
-        x[ld + i] = sy;
-        x[2 * ld + i] = sz;
+        x[i] = in.sx;
+        x[ld + i] = in.sy;
+        x[2 * ld + i] = in.sz;
         T* w = d.wx + adj_slot<C>(kk, stage, d.S, ld) + (int64_t)s * C * ld;
         w[i] = dx;
         if (XYZ) {
@@ -209,20 +265,14 @@ __device__ __forceinline__ void fwd_epilogue(const AdjDev<T>& d, const Coef<T>& 
         }
     }
     T fx, fy, fz;
-    llg_rhs<T, XYZ>(k, sx, sy, sz, k.a_cp * dx, XYZ ? k.a_cp * dy : T(0), XYZ ? k.a_cp * dz : T(0), hin, fx, fy,
-                    fz);
+    llg_rhs<T, XYZ>(k, in.sx, in.sy, in.sz, k.a_cp * dx, XYZ ? k.a_cp * dy : T(0), XYZ ? k.a_cp * dz : T(0), in.hin,
+                    fx, fy, fz);
     T* m = d.m + sb;
     T* acc = d.acc + sb;
-    const T mx = m[i], my = m[ld + i], mz = m[2 * ld + i];
-    T cx = T(0), cy = T(0), cz = T(0);
-    if (stage > 0) {
-        cx = acc[i];
-        cy = acc[ld + i];
-        cz = acc[2 * ld + i];
-    }
-    T nx = rk4_update(k, stage, mx, cx, fx);
-    T ny = rk4_update(k, stage, my, cy, fy);
-    T nz = rk4_update(k, stage, mz, cz, fz);
+    T cx = in.cx, cy = in.cy, cz = in.cz;
+    T nx = rk4_update(k, stage, in.mx, cx, fx);
+    T ny = rk4_update(k, stage, in.my, cy, fy);
+    T nz = rk4_update(k, stage, in.mz, cz, fz);
     if (stage == 3) {
         if (d.renorm) {
             if (trace) {
@@ -251,35 +301,62 @@ __device__ __forceinline__ void fwd_epilogue(const AdjDev<T>& d, const Coef<T>& 
     xout[2 * ld + i] = nz;
 }
 
-// Epilogue of a reversed stage for node i of stream s, given
+template <typename T, bool XYZ>
+__device__ __forceinline__ void fwd_epilogue(const AdjDev<T>& d, const Coef<T>& k, int i, int s, int kk, int stage,
+                                             int cur, int trace, T dx, T dy, T dz) {
+    fwd_finish<T, XYZ>(d, k, i, s, kk, stage, cur, trace, fwd_load<T>(d, k, i, s, kk, stage, cur), dx, dy, dz);
+}
+
+// Inputs of a reversed stage's epilogue at node i of stream s: the
+// pointwise part of xbar, dL/dm so far, a, and (below the last stage) the
+// inputs of the next stage's pointwise adjoint; none depends on the product.
+template <typename T>
+struct RevIn {
+    T lc[3], mb[3], ab[3];
+    VjpIn<T> v;
+};
+
+template <typename T, bool XYZ>
+__device__ __forceinline__ RevIn<T> rev_load(const AdjDev<T>& d, int i, int s, int kk, int stage) {
+    const int64_t ld = d.ld;
+    const int64_t sb = (int64_t)s * 3 * ld;
+    RevIn<T> in;
+    for (int c = 0; c < 3; ++c) {
+        in.lc[c] = d.loc[sb + c * ld + i];
+        in.mb[c] = d.mbar[sb + c * ld + i];
+        in.ab[c] = d.abar[sb + c * ld + i];
+    }
+    if (stage > 0) in.v = vjp_load<T, XYZ>(d, i, s, kk, stage - 1);
+    return in;
+}
+
+// Epilogue of a reversed stage for node i of stream s, given its inputs and
 // t = (W^T bbar) of the stage: xbar = loc + a_cp t along the coupled
 // components, dL/dm += xbar, then the pointwise adjoint of the next stage to
 // reverse (or, after the first stage, the start of the previous step).
 template <typename T, bool XYZ>
-__device__ __forceinline__ void rev_epilogue(const AdjDev<T>& d, const Coef<T>& k, int i, int s, int kk, int stage,
-                                             T tx, T ty, T tz) {
+__device__ __forceinline__ void rev_finish(const AdjDev<T>& d, const Coef<T>& k, int i, int s, int kk, int stage,
+                                           const RevIn<T>& in, T tx, T ty, T tz) {
     const int64_t ld = d.ld;
     const int64_t sb = (int64_t)s * 3 * ld;
-    const T* lc = d.loc + sb;
-    T xb[3] = {lc[i] + k.a_cp * tx, lc[ld + i], lc[2 * ld + i]};
+    T xb[3] = {in.lc[0] + k.a_cp * tx, in.lc[1], in.lc[2]};
     if (XYZ) {
         xb[1] = xb[1] + k.a_cp * ty;
         xb[2] = xb[2] + k.a_cp * tz;
     }
     T mb[3];
     for (int c = 0; c < 3; ++c) {
-        mb[c] = d.mbar[sb + c * ld + i] + xb[c];
+        mb[c] = in.mb[c] + xb[c];
         d.mbar[sb + c * ld + i] = mb[c];
     }
     if (stage > 0) {
         // kbar of stage-1: its weight in m' times a, plus its step into this stage's input
         const T wgt = (stage - 1 == 0) ? k.h6 : T(2) * k.h6;
         const T hst = (stage == 3) ? k.h1 : k.h2;
-        const T* ab = d.abar + sb;
-        const T v0 = wgt * ab[i] + hst * xb[0];
-        const T v1 = wgt * ab[ld + i] + hst * xb[1];
-        const T v2 = wgt * ab[2 * ld + i] + hst * xb[2];
-        stage_vjp<T, XYZ>(d, k, i, s, kk, stage - 1, v0, v1, v2);
+        const T v0 = wgt * in.ab[0] + hst * xb[0];
+        const T v1 = wgt * in.ab[1] + hst * xb[1];
+        const T v2 = wgt * in.ab[2] + hst * xb[2];
+        vjp_apply<T, XYZ>(d, k, i, s, kk, stage - 1, in.v, v0, v1, v2);
     } else if (kk > 0) {
         // step j = j0 + kk is reversed: mbar = dL/dm_j.  Start step j - 1,
         // whose output m_j is the first stage input of step j.
@@ -287,6 +364,12 @@ __device__ __forceinline__ void rev_epilogue(const AdjDev<T>& d, const Coef<T>& 
         const T pn = d.renorm ? d.pn[((int64_t)(kk - 1) * d.S + s) * ld + i] : T(1);
         prep_step<T, XYZ>(d, k, i, s, kk - 1, mhat, pn, mb[0], mb[1], mb[2]);
     }
+}
+
+template <typename T, bool XYZ>
+__device__ __forceinline__ void rev_epilogue(const AdjDev<T>& d, const Coef<T>& k, int i, int s, int kk, int stage,
+                                             T tx, T ty, T tz) {
+    rev_finish<T, XYZ>(d, k, i, s, kk, stage, rev_load<T, XYZ>(d, i, s, kk, stage), tx, ty, tz);
 }
 
 // Launchers of the multi-stream (S > 1) stage kernels, FP32 (sto_batch.hip).

@@ -10,13 +10,14 @@
 // or their adjoint.
 //
 // Tiling.  Workgroup (bi, bj) owns nodes 16 bi .. 16 bi + 15 and streams
-// 16 bj .. 16 bj + 15.  Its four waves split the contraction over the nodes
-// j into quarters; per MFMA step lane l supplies A[l%16][l/16] = M[j][i]
-// (M = W^T for W X, M = W for W^T Bbar; rows of M are contiguous in i, so 16
-// lanes read 64 consecutive bytes) and B[l/16][l%16] = X[s][c][j].  The four
-// partial tiles meet in LDS and are summed in a fixed order; thread t then
-// owns the pair (node 16 bi + t/16, stream 16 bj + t%16).  W (1 MB at
-// N = 512) stays in the L2 and MALL between launches.
+// 16 bj .. 16 bj + 15.  The contraction over the nodes j runs in blocks of
+// 256 staged through LDS with coalesced loads (M = W^T for W X, M = W for
+// W^T Bbar: rows of M are contiguous in i; X's rows are contiguous in j);
+// per MFMA step lane l supplies A[l%16][l/16] = M[j][i] and
+// B[l/16][l%16] = X[s][c][j] from LDS, and the eight waves take alternate
+// steps.  Their partial tiles meet in LDS and are summed in a fixed order;
+// thread t < 256 then owns the pair (node 16 bi + t/16, stream 16 bj + t%16).
+// W (1 MB at N = 512) stays in the L2 and MALL between launches.
 //
 // Unlike the persistent multi-stream kernel (k_multi, x coupling only), this
 // path handles both couplings and any N, at one launch per stage.
@@ -34,81 +35,121 @@ typedef float bf4 __attribute__((ext_vector_type(4)));
 
 constexpr int kT = 16;   // tile edge (nodes and streams)
 
-// Partial products of the tile over one quarter of the contraction, summed
-// across the four waves in LDS.  M: n x ld (rows j, contiguous in i); X:
-// stream s, component c at X + s * xs + c * xc (contiguous in j).  On return
-// out[c] holds the (node i0 + t/16, stream s0 + t%16) element for thread t.
+// Partial products of the tile, the contraction over the nodes j taken in
+// blocks of kJB staged through LDS, and summed across the waves.  M: n x ld
+// (rows j, contiguous in i); X: stream s, component c at X + s * xs + c * xc
+// (contiguous in j).  Per block the workgroup loads the M rows of its 16
+// nodes and the X rows of its 16 streams with coalesced 16-byte loads (X's
+// rows are padded by 4 floats so that the 16 stream lanes of an MFMA operand
+// read fall in distinct banks); each wave then runs one eighth of the
+// block's MFMA steps.  On return out[c] holds the (node i0 + t/16, stream
+// s0 + t%16) element for threads t < 256.
+constexpr int kWaves = 8;
+constexpr int kJB = 256;          // contraction rows per LDS block
+constexpr int kXP = kJB + 4;      // padded row of the X block
+
+template <int C>
+struct TileLds {
+    float a[kJB][kT];             // M[j][i0 .. i0 + 15]
+    float x[kT * C][kXP];         // X[s0 + s][c][j]
+    float cs[kWaves * C * kT * kT];
+};
+
 template <int C>
 __device__ __forceinline__ void tile_product(const float* __restrict__ M, int64_t ld, int n, int i0,
                                              const float* __restrict__ X, int64_t xs, int64_t xc, int S, int s0,
-                                             float* cs, float* out) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+                                             TileLds<C>& sh, float* out) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int kr = lane >> 4, c16 = lane & 15;
-    const int steps = (n + 3) / 4;             // MFMA steps of 4 nodes over the contraction
-    const int per = (steps + 3) / 4;           // steps of one wave
-    const int t0 = wave * per, t1 = min(steps, t0 + per);
-    const int i = i0 + c16;                    // i < ld: i0 + 15 < n rounded up to 16 <= ld
-    const int s = min(s0 + c16, S - 1);        // clamped; masked below
-    const bool vs = s0 + c16 < S;
     bf4 acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = bf4{0.f, 0.f, 0.f, 0.f};
-    for (int t = t0; t < t1; ++t) {
-        const int j = 4 * t + kr;
-        const bool vj = j < n;
-        const int jc = vj ? j : n - 1;
-        const unsigned ma = vj ? 0xffffffffu : 0u, mb = (vj && vs) ? 0xffffffffu : 0u;
-        const float a = __uint_as_float(__float_as_uint(M[(int64_t)jc * ld + i]) & ma);
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const float b = __uint_as_float(__float_as_uint(X[(int64_t)s * xs + c * xc + jc]) & mb);
-            acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[c], 0, 0, 0);
+    for (int jb = 0; jb < n; jb += kJB) {
+        // A block: kJB rows x 16 floats, one float4 per thread and pass
+        for (int e = tid; e < kJB * kT / 4; e += 64 * kWaves) {
+            const int r = e >> 2, q = e & 3;
+            const int j = jb + r;
+            bf4 v = bf4{0.f, 0.f, 0.f, 0.f};
+            if (j < n) v = *reinterpret_cast<const bf4*>(M + (int64_t)j * ld + i0 + 4 * q);
+            *reinterpret_cast<bf4*>(&sh.a[r][4 * q]) = v;
         }
+        // X block: 16 C rows of kJB floats; rows beyond S and columns beyond
+        // n read as zero (X's rows are ld >= n long and 16-byte aligned)
+        for (int e = tid; e < kT * C * kJB / 4; e += 64 * kWaves) {
+            const int row = e / (kJB / 4), q = e - row * (kJB / 4);
+            const int sl = row / C, c = row - sl * C;
+            const int j = jb + 4 * q;
+            bf4 v = bf4{0.f, 0.f, 0.f, 0.f};
+            if (s0 + sl < S && j < n) v = *reinterpret_cast<const bf4*>(X + (int64_t)(s0 + sl) * xs + c * xc + j);
+            *reinterpret_cast<bf4*>(&sh.x[row][4 * q]) = v;
+        }
+        __syncthreads();
+        // MFMA steps of 4 rows: wave w takes steps w, w + 8, ...
+        for (int t = wave; t < kJB / 4; t += kWaves) {
+            const int jl = 4 * t + kr;
+            const float av = sh.a[jl][c16];
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sh.x[c16 * C + c][jl], acc[c], 0, 0, 0);
+        }
+        __syncthreads();
     }
     // D of lane l: rows (nodes) 4 (l/16) + r, column (stream) l%16
 #pragma unroll
     for (int c = 0; c < C; ++c)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) cs[((wave * C + c) * kT + 4 * kr + r) * kT + c16] = acc[c][r];
+        for (int r = 0; r < 4; ++r) sh.cs[((wave * C + c) * kT + 4 * kr + r) * kT + c16] = acc[c][r];
     __syncthreads();
-    const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
+    if (tid < kT * kT) {
+        const int ti = tid >> 4, tj = tid & 15;
 #pragma unroll
-    for (int c = 0; c < C; ++c)
-        out[c] = ((cs[((0 * C + c) * kT + ti) * kT + tj] + cs[((1 * C + c) * kT + ti) * kT + tj]) +
-                  cs[((2 * C + c) * kT + ti) * kT + tj]) +
-                 cs[((3 * C + c) * kT + ti) * kT + tj];
+        for (int c = 0; c < C; ++c) {
+            float v = sh.cs[((0 * C + c) * kT + ti) * kT + tj];
+#pragma unroll
+            for (int w = 1; w < kWaves; ++w) v += sh.cs[((w * C + c) * kT + ti) * kT + tj];
+            out[c] = v;
+        }
+    }
 }
 
 // Forward stage of all streams (records for plain runs, trace for the adjoint).
 template <bool XYZ>
-__global__ void __launch_bounds__(256) k_bfwd(AdjDev<float> d, Coef<float> k, int kk, int stage, int cur, int trace) {
+__global__ void __launch_bounds__(512) k_bfwd(AdjDev<float> d, Coef<float> k, int kk, int stage, int cur, int trace) {
     constexpr int C = XYZ ? 3 : 1;
-    __shared__ float cs[4 * C * kT * kT];
+    __shared__ TileLds<C> sh;
     const int i0 = blockIdx.x * kT, s0 = blockIdx.y * kT;
-    float out[3] = {0.f, 0.f, 0.f};
-    tile_product<C>(d.Wt, d.ld, d.n, i0, d.ms[cur], 3 * d.ld, d.ld, d.S, s0, cs, out);
     const int i = i0 + (threadIdx.x >> 4), s = s0 + (threadIdx.x & 15);
-    if (i < d.n && s < d.S) fwd_epilogue<float, XYZ>(d, k, i, s, kk, stage, cur, trace, out[0], out[1], out[2]);
+    const bool own = threadIdx.x < kT * kT && i < d.n && s < d.S;
+    // the epilogue's inputs do not depend on the product: load them first
+    FwdIn<float> in{};
+    if (own) in = fwd_load<float>(d, k, i, s, kk, stage, cur);
+    float out[3] = {0.f, 0.f, 0.f};
+    tile_product<C>(d.Wt, d.ld, d.n, i0, d.ms[cur], 3 * d.ld, d.ld, d.S, s0, sh, out);
+    if (own) fwd_finish<float, XYZ>(d, k, i, s, kk, stage, cur, trace, in, out[0], out[1], out[2]);
 }
 
 // Reversed stage of all streams: W^T Bbar, then the adjoint epilogue.
 template <bool XYZ>
-__global__ void __launch_bounds__(256) k_brev(AdjDev<float> d, Coef<float> k, int kk, int stage) {
+__global__ void __launch_bounds__(512) k_brev(AdjDev<float> d, Coef<float> k, int kk, int stage) {
     constexpr int C = XYZ ? 3 : 1;
-    __shared__ float cs[4 * C * kT * kT];
+    __shared__ TileLds<C> sh;
     const int i0 = blockIdx.x * kT, s0 = blockIdx.y * kT;
+    const int i = i0 + (threadIdx.x >> 4), s = s0 + (threadIdx.x & 15);
+    const bool own = threadIdx.x < kT * kT && i < d.n && s < d.S;
+    // the epilogue's inputs do not depend on the product: load them first
+    RevIn<float> in{};
+    if (own) in = rev_load<float, XYZ>(d, i, s, kk, stage);
     const float* bbar = d.st + adj_slot<C>(kk, stage, d.S, d.ld);
     float out[3] = {0.f, 0.f, 0.f};
-    tile_product<C>(d.W, d.ld, d.n, i0, bbar, C * d.ld, d.ld, d.S, s0, cs, out);
-    const int i = i0 + (threadIdx.x >> 4), s = s0 + (threadIdx.x & 15);
-    if (i < d.n && s < d.S) rev_epilogue<float, XYZ>(d, k, i, s, kk, stage, out[0], out[1], out[2]);
+    tile_product<C>(d.W, d.ld, d.n, i0, bbar, C * d.ld, d.ld, d.S, s0, sh, out);
+    if (own) rev_finish<float, XYZ>(d, k, i, s, kk, stage, in, out[0], out[1], out[2]);
 }
 
 }  // namespace
 
 void launch_batch_fwd(const AdjDev<float>& d, const Coef<float>& k, int kk, int stage, int cur, int trace, int xyz,
                       hipStream_t st) {
-    const dim3 grid((d.n + kT - 1) / kT, (d.S + kT - 1) / kT), block(256);
+    const dim3 grid((d.n + kT - 1) / kT, (d.S + kT - 1) / kT), block(64 * kWaves);
     if (xyz)
         hipLaunchKernelGGL(k_bfwd<true>, grid, block, 0, st, d, k, kk, stage, cur, trace);
     else
@@ -116,7 +157,7 @@ void launch_batch_fwd(const AdjDev<float>& d, const Coef<float>& k, int kk, int 
 }
 
 void launch_batch_rev(const AdjDev<float>& d, const Coef<float>& k, int kk, int stage, int xyz, hipStream_t st) {
-    const dim3 grid((d.n + kT - 1) / kT, (d.S + kT - 1) / kT), block(256);
+    const dim3 grid((d.n + kT - 1) / kT, (d.S + kT - 1) / kT), block(64 * kWaves);
     if (xyz)
         hipLaunchKernelGGL(k_brev<true>, grid, block, 0, st, d, k, kk, stage);
     else
