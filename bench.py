@@ -121,7 +121,8 @@ def run_workload(stx, torch, name: str, dtype: str, steps: int, warmup: int, arr
     evs = [one_step() for _ in range(steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    run_ms = sum(e0.elapsed_time(e1) for e0, e1, _, _ in evs) / steps
+    run_each = sorted(e0.elapsed_time(e1) for e0, e1, _, _ in evs)
+    run_ms = sum(run_each) / steps
     fit_ms = sum(e1.elapsed_time(e2) for _, e1, e2, _ in evs) / steps
     nmse = evs[-1][3]
     r.close()
@@ -136,7 +137,8 @@ def run_workload(stx, torch, name: str, dtype: str, steps: int, warmup: int, arr
         "workload": name, "n": wl.n, "dtype": dtype, "path": path, "samples": wl.samples,
         "substeps": wl.substeps, "rk4_steps": wl.steps, "dt": wl.dt,
         "value": node_steps / wall_s, "ms_per_step": wall_s * 1e3,
-        "run_ms": run_ms, "readout_ms": fit_ms, "us_per_rk4_step": run_ms * 1e3 / wl.steps,
+        "run_ms": run_ms, "run_ms_median": run_each[len(run_each) // 2], "run_ms_min": run_each[0],
+        "run_ms_max": run_each[-1], "readout_ms": fit_ms, "us_per_rk4_step": run_ms * 1e3 / wl.steps,
         "readout_nmse": nmse,
         "kernel": kernel, "launches_per_run": launches, "avg_launch_us": launch_s * 1e6,
         "algo_bytes_per_launch": algo_bytes, "achieved_gbs": achieved,
