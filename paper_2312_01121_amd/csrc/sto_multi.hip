@@ -17,8 +17,8 @@
 //
 // Stage inputs are exchanged through three rotating global buffers, laid out
 // [stream][node], whose unpublished entries hold a sentinel bit pattern; the
-// protocol (poll, compute, re-arm two stages ahead, wait for the stores,
-// publish) is the one of the resident kernel.  Every wait is bounded and
+// protocol (poll, re-arm two stages ahead, compute while those stores
+// complete, wait for them, publish) is the one of the resident kernel.  Every wait is bounded and
 // raises a sticky abort flag when it expires.
 
 #include <climits>
@@ -144,6 +144,14 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
                 if (!gather_multi(xin, ld, n, s0, ns, xs, abort_flag)) ok_lds = 0;
                 __syncthreads();
                 if (ok_lds == 0) return;
+                // re-arm this pair's entry of the buffer two stages ahead now:
+                // every workgroup finished reading it (the gather just saw all
+                // outputs of the previous stage, each published after its
+                // workgroup's own gather), and its store then completes while
+                // the stage is computed
+                if (mine)
+                    __hip_atomic_store(reinterpret_cast<unsigned*>(xold + (int64_t)strm * ld + node), ~0u,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 // partial tile of this wave: D[i][j] = sum over its nodes of W[row0+i][k] X[k][s0+j]
                 f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -177,8 +185,6 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
                 sz = nz;
                 if (mine) {
                     const int64_t o = (int64_t)strm * ld + node;
-                    __hip_atomic_store(reinterpret_cast<unsigned*>(xold + o), ~0u, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
                     // the re-arm store must complete before the publish
                     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
                     __hip_atomic_store(xout + o, nx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -15,14 +15,15 @@
 //   1. polls every entry of buffer s % 3 until none is the sentinel, copying
 //      the values into LDS (this is the only wait: data and synchronisation
 //      arrive in the same load);
-//   2. computes its rows of stage s;
-//   3. re-arms its rows of buffer (s + 2) % 3 with the sentinel (every
+//   2. re-arms its rows of buffer (s + 2) % 3 with the sentinel (every
 //      workgroup finished reading that buffer, the input of stage s - 1,
 //      before it published its stage s - 1 output, all of which step 1 has
-//      seen), waits for those stores to complete, and only then
-//   4. publishes its rows of buffer (s + 1) % 3.
+//      seen);
+//   3. computes its rows of stage s while those stores complete;
+//   4. waits for the re-arm stores to complete, and only then publishes its
+//      rows of buffer (s + 1) % 3.
 // All exchange loads and stores are agent-scope atomics, which on gfx950 are
-// coherent across the XCDs without an L2 writeback: the ordering of step 3
+// coherent across the XCDs without an L2 writeback: the ordering of step 2
 // before step 4 is the store-completion wait of the publishing wave, and a
 // reader that sees a published value issues its later loads after it.
 // Agent-scope release fences per workgroup (L2 writebacks) cost ~70 ns each
@@ -175,6 +176,23 @@ __global__ void __launch_bounds__(kBlock) k_resident(DevState<T> d, Coef<T> k, c
                 if (!ok) ok_lds = 0;
                 __syncthreads();
                 if (ok_lds == 0) return;
+                // step 3 early: re-arm this wave's rows of the buffer two
+                // stages ahead as soon as the gather is done (every workgroup
+                // finished reading it: the gather saw all outputs of the
+                // previous stage), so the stores complete during the compute
+                if (lane == 0) {
+#pragma unroll
+                    for (int q = 0; q < kMaxRowsPerWave; ++q) {
+                        const int r = wave + q * kWaves;
+                        if (r >= nrows) break;
+                        const int row = row_begin + r;
+                        rearm(xold + row);
+                        if (XYZ) {
+                            rearm(xold + ld + row);
+                            rearm(xold + 2 * ld + row);
+                        }
+                    }
+                }
 #pragma unroll
                 for (int q = 0; q < kMaxRowsPerWave; ++q) {
                     const int r = wave + q * kWaves;
@@ -211,20 +229,21 @@ __global__ void __launch_bounds__(kBlock) k_resident(DevState<T> d, Coef<T> k, c
                     sx[q] = nx;
                     sy[q] = ny;
                     sz[q] = nz;
-                    if (lane == 0) {
+                }
+                // step 4: publish this wave's rows once the re-arm stores have
+                // completed (one wait for all rows; the clobber keeps the
+                // compiler from moving the stores across it)
+                if (lane == 0) {
+                    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+#pragma unroll
+                    for (int q = 0; q < kMaxRowsPerWave; ++q) {
+                        const int r = wave + q * kWaves;
+                        if (r >= nrows) break;
                         const int row = row_begin + r;
-                        rearm(xold + row);
+                        publish(xout + row, sx[q]);
                         if (XYZ) {
-                            rearm(xold + ld + row);
-                            rearm(xold + 2 * ld + row);
-                        }
-                        // the re-arm stores must complete before the publish;
-                        // the clobber keeps the compiler from moving either
-                        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-                        publish(xout + row, nx);
-                        if (XYZ) {
-                            publish(xout + ld + row, ny);
-                            publish(xout + 2 * ld + row, nz);
+                            publish(xout + ld + row, sy[q]);
+                            publish(xout + 2 * ld + row, sz[q]);
                         }
                     }
                 }
