@@ -198,14 +198,35 @@ __global__ void __launch_bounds__(kBlock) k_resident(DevState<T> d, Coef<T> k, c
                     const int r = wave + q * kWaves;
                     if (r >= nrows) break;   // wave-uniform
                     const T* wr = wsh + (int64_t)r * wld;
+                    // two independent accumulation chains per lane (columns
+                    // j and j + 64 of each 128), joined before the butterfly
+                    // (measured: four chains are slower)
                     AT vx = A::zero(), vy = A::zero(), vz = A::zero();
-                    for (int j = lane; j < n; j += 64) {
-                        const T w = wr[j];
-                        A::fma(vx, w, xs[j]);
+                    AT ux = A::zero(), uy = A::zero(), uz = A::zero();
+                    int j = lane;
+                    for (; j + 64 < n; j += 128) {
+                        const T w0 = wr[j], w1 = wr[j + 64];
+                        A::fma(vx, w0, xs[j]);
+                        A::fma(ux, w1, xs[j + 64]);
                         if (XYZ) {
-                            A::fma(vy, w, xs[n + j]);
-                            A::fma(vz, w, xs[2 * n + j]);
+                            A::fma(vy, w0, xs[n + j]);
+                            A::fma(uy, w1, xs[n + j + 64]);
+                            A::fma(vz, w0, xs[2 * n + j]);
+                            A::fma(uz, w1, xs[2 * n + j + 64]);
                         }
+                    }
+                    if (j < n) {
+                        const T w0 = wr[j];
+                        A::fma(vx, w0, xs[j]);
+                        if (XYZ) {
+                            A::fma(vy, w0, xs[n + j]);
+                            A::fma(vz, w0, xs[2 * n + j]);
+                        }
+                    }
+                    vx = A::add(vx, ux);
+                    if (XYZ) {
+                        vy = A::add(vy, uy);
+                        vz = A::add(vz, uz);
                     }
                     vx = group_reduce<T>(vx, 64);
                     T cx = k.a_cp * A::round(vx), cy = T(0), cz = T(0);
