@@ -510,7 +510,7 @@ sto::SweepDev<T> sweep_dev(const sto_sweep* s, void* states, int64_t samples) {
     d.bad = s->bad;
     d.res = static_cast<const sto::SweepRes*>(s->res_dev);
     d.coef = static_cast<const sto::Coef<T>*>(s->coef_dev);
-    d.task = static_cast<const int2*>(s->task_dev);
+    d.task = static_cast<const sto::SweepTask*>(s->task_dev);
     d.tasks = s->tasks;
     d.n_in = (int)s->n_in;
     d.rec_samples = samples;
@@ -939,7 +939,7 @@ sto_status sweep_create(int32_t count, const int64_t* n, int64_t n_in, const sto
     s->substeps = prm[0].substeps;
     s->renorm = prm[0].renormalize;
     int64_t woff = 0, soff = 0, winoff = 0, noff = 0;
-    std::vector<int2> tasks;
+    std::vector<sto::SweepTask> tasks;
     for (int r = 0; r < count; ++r) {
         sto::SweepRes x;
         x.n = (int)n[r];
@@ -957,7 +957,7 @@ sto_status sweep_create(int32_t count, const int64_t* n, int64_t n_in, const sto
         // wave tasks in reservoir order (a largest-first order was measured
         // slower: the small tasks then form the tail)
         const int rows = sto::sweep_task_rows(x.ld, (int)s->elem);
-        for (int row = 0; row < n[r]; row += rows) tasks.push_back(make_int2(r, row));
+        for (int row = 0; row < n[r]; row += rows) tasks.push_back({x.woff, x.soff, (int)x.ld, x.n, r, row});
     }
     s->nodes = noff;
     s->tasks = (int)tasks.size();
@@ -980,7 +980,7 @@ sto_status sweep_create(int32_t count, const int64_t* n, int64_t n_in, const sto
     SALLOC(s->acc, (size_t)soff * s->elem);
     SALLOC(s->res_dev, sizeof(sto::SweepRes) * count);
     SALLOC(s->coef_dev, (s->dtype == STO_F64 ? sizeof(sto::Coef<double>) : sizeof(sto::Coef<float>)) * count);
-    SALLOC(s->task_dev, sizeof(int2) * tasks.size());
+    SALLOC(s->task_dev, sizeof(sto::SweepTask) * tasks.size());
     SALLOC(s->bad, sizeof(int));
 #undef SALLOC
     e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
@@ -1012,7 +1012,7 @@ sto_status sweep_create(int32_t count, const int64_t* n, int64_t n_in, const sto
         e = hipMemcpy(s->coef_dev, c.data(), sizeof(c[0]) * count, hipMemcpyHostToDevice);
     }
     if (e == hipSuccess) e = hipMemcpy(s->res_dev, s->res.data(), sizeof(sto::SweepRes) * count, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(s->task_dev, tasks.data(), sizeof(int2) * tasks.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->task_dev, tasks.data(), sizeof(sto::SweepTask) * tasks.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return cleanup(hip_fail(e, "sweep upload"));
     *out = s;
     return STO_OK;

@@ -41,6 +41,18 @@ struct SweepRes {
     int64_t noff;      // nodes of the reservoirs before this one
 };
 
+// One wave task of the sweep: consecutive rows of one reservoir.  It
+// carries the offsets its coupling pass needs, so the loads of W can start
+// after this one table read.
+struct SweepTask {
+    int64_t woff;      // element offset of the reservoir's W
+    int64_t soff;      // element offset of its m, ms[], acc
+    int ld;            // row pitch
+    int n;             // nodes of the reservoir
+    int res;           // reservoir index (constants, w_in, records)
+    int row;           // first row of the task
+};
+
 template <typename T>
 struct SweepDev {
     const T* W;
@@ -52,7 +64,7 @@ struct SweepDev {
     int* bad;
     const SweepRes* res;
     const Coef<T>* coef;
-    const int2* task;  // (reservoir, first row) of every wave task
+    const SweepTask* task;   // every wave task
     int tasks;
     int n_in;
     int64_t rec_samples;   // samples of the current run (record layout)

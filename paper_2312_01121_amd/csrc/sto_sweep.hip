@@ -50,19 +50,38 @@ __global__ void __launch_bounds__(256) k_sweep_stage(SweepDev<T> d, const double
     const int lane = threadIdx.x & 63;
     const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (task >= d.tasks) return;   // wave-uniform
-    const int2 tk = d.task[task];  // (reservoir, first row)
-    const SweepRes res = d.res[tk.x];
-    const Coef<T> k = d.coef[tk.x];
-    const int n = res.n;
-    const int64_t ld = res.ld;
+    const SweepTask tk = d.task[task];
+    const int n = tk.n;
+    const int64_t ld = tk.ld;
     const int G = group_lanes(ld, VN);   // wave-uniform
     const int gl = lane & (G - 1);
-    const int rowg = tk.y + (lane / G) * R;   // first row of this lane's group
-    const T* W = d.W + res.woff;
-    T* m = d.m + res.soff;
-    T* acc = d.acc + res.soff;
-    const T* xin = d.ms[cur] + res.soff;
-    T* xout = d.ms[cur ^ 1] + res.soff;
+    const int rowg = tk.row + (lane / G) * R;   // first row of this lane's group
+    const T* W = d.W + tk.woff;
+    T* m = d.m + tk.soff;
+    T* acc = d.acc + tk.soff;
+    const T* xin = d.ms[cur] + tk.soff;
+    T* xout = d.ms[cur ^ 1] + tk.soff;
+    const int row = rowg + gl;
+    const bool own = gl < R && row < n;
+    const SweepRes res = d.res[tk.res];
+    const Coef<T> k = d.coef[tk.res];
+
+    // the epilogue's state inputs do not depend on the row sums: load them
+    // before the coupling pass so that their latency overlaps it
+    T sx = T(0), sy = T(0), sz = T(0), mx = T(0), my = T(0), mz = T(0), ax = T(0), ay = T(0), az = T(0);
+    if (own) {
+        sx = xin[row];
+        sy = xin[ld + row];
+        sz = xin[2 * ld + row];
+        mx = m[row];
+        my = m[ld + row];
+        mz = m[2 * ld + row];
+        if (stage > 0) {
+            ax = acc[row];
+            ay = acc[ld + row];
+            az = acc[2 * ld + row];
+        }
+    }
 
     const T* wrow[R];
 #pragma unroll
@@ -87,19 +106,10 @@ __global__ void __launch_bounds__(256) k_sweep_stage(SweepDev<T> d, const double
         const AT s = group_reduce<T>(av[r], G);
         if (gl == r) dot = A::round(s);
     }
-    const int row = rowg + gl;
-    if (gl >= R || row >= n) return;
+    if (!own) return;
     const T hin = input_field(k, d.w_in + res.winoff + (int64_t)row * d.n_in, u_s, d.n_in);
-    const T sx = xin[row], sy = xin[ld + row], sz = xin[2 * ld + row];
     T fx, fy, fz;
     llg_rhs<T, false>(k, sx, sy, sz, k.a_cp * dot, T(0), T(0), hin, fx, fy, fz);
-    T mx = m[row], my = m[ld + row], mz = m[2 * ld + row];
-    T ax = T(0), ay = T(0), az = T(0);
-    if (stage > 0) {
-        ax = acc[row];
-        ay = acc[ld + row];
-        az = acc[2 * ld + row];
-    }
     T nx = rk4_update(k, stage, mx, ax, fx);
     T ny = rk4_update(k, stage, my, ay, fy);
     T nz = rk4_update(k, stage, mz, az, fz);
@@ -127,16 +137,17 @@ __global__ void __launch_bounds__(256) k_sweep_stage(SweepDev<T> d, const double
 
 }  // namespace
 
-// Rows per lane group (R): 4, measured fastest on a 256-reservoir sweep
-// (372.6 us per RK4 step against 415.3 with 2).  STO_SWEEP_ROWS (2, 4 or 8)
-// overrides it for measurements; it is read once per process, so the task
-// table and the kernel always agree.
+// Rows per lane group (R): 8, measured fastest on a 256-reservoir sweep
+// (361.9 us per RK4 step against 368.6 with 4 and 415 with 2; visiting the
+// tasks last-to-first on alternate stages measured slower, 369.2).
+// STO_SWEEP_ROWS (2, 4 or 8) overrides it for measurements; it is read once
+// per process, so the task table and the kernel always agree.
 int sweep_rows_per_task(int elem_bytes) {
     (void)elem_bytes;
     static const int rows = [] {
         const char* v = getenv("STO_SWEEP_ROWS");
-        const int r = v ? atoi(v) : 4;
-        return (r == 2 || r == 8) ? r : 4;
+        const int r = v ? atoi(v) : 8;
+        return (r == 2 || r == 4) ? r : 8;
     }();
     return rows;
 }
