@@ -535,6 +535,48 @@ def cpu_baseline(name: str, arrays, budget_s: float = 25.0):
         "kind": "oracle",
         "sample": f"first {samples} input sample(s) = {samples * wl.substeps} RK4 steps of the {name} "
                   f"workload (N={wl.n}), FP64 oracle with correctly rounded coupling sums, {el:.1f} s",
+        "blas_form": cpu_blas_form(name, arrays, prm),
+    }
+
+
+def cpu_blas_form(name: str, arrays, prm, budget_s: float = 4.0):
+    """The oracle with its coupling as NumPy's matrix product (the analogue of
+    the paper's NumPy baseline), timed on one input sample with BLAS pinned to
+    one thread and then on all host cores; names the CPU and the BLAS."""
+    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
+    from oracle import sto
+    from workloads import WORKLOADS
+
+    wl = WORKLOADS[name]
+
+    def rate():
+        t0 = time.perf_counter()
+        samples = 0
+        while True:
+            sto.run(arrays["W"], arrays["w_in"], arrays["m0"], arrays["u"][samples:samples + 1], prm, dot="blas")
+            samples += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s or samples >= wl.samples:
+                return wl.n * samples * wl.substeps / el, samples
+
+    np.dot(np.ones(4), np.ones(4))   # load the BLAS before asking for its thread pool
+    pools = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+    with threadpool_limits(limits=1, user_api="blas"):
+        one, s1 = rate()
+    allc, s2 = rate()
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next(line.split(":", 1)[1].strip() for line in fh if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    return {
+        "node_steps_per_s_1_thread": one, "node_steps_per_s_all_cores": allc,
+        "threads_all_cores": pools[0]["num_threads"] if pools else None,
+        "blas": f"{pools[0]['internal_api']} {pools[0]['version']}" if pools else "unknown",
+        "cpu_model": cpu, "host_cpus": os.cpu_count(),
+        "samples": [s1, s2],
     }
 
 
