@@ -598,6 +598,8 @@ def main():
                     help="only run the paper's benchmark (u = 0, FP64, N = 1..1e4) for STEPS RK4 steps each")
     ap.add_argument("--no-plain", action="store_true",
                     help="sweep workload: skip timing the plain single-reservoir path")
+    ap.add_argument("--coupling", default="x", choices=("x", "xyz"),
+                    help="multi-stream workload: the paper's m^x coupling or all three components")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device with a plain copy kernel (scales HBM counters)")
     args = ap.parse_args()
@@ -644,7 +646,7 @@ def main():
                     "unit": "GB/s", "frac": res["hbm_frac"], "traffic": stored_traffic("k_sweep_stage", args.workload, "f32")}
             unit_nodes = res["nodes"]
         else:
-            res = run_streams_workload(stx, torch, args.workload, args.steps, args.warmup)
+            res = run_streams_workload(stx, torch, args.workload, args.steps, args.warmup, coupling=args.coupling)
             roof = {"bound": "mfma", "kernel": res["kernel"], "achieved": res["mfma_tflops"], "peak": 157.3,
                     "unit": "TFLOP/s", "frac": res["mfma_frac"], "traffic": None}
             unit_nodes = res["n"] * res["streams"]
@@ -653,7 +655,7 @@ def main():
             "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": args.workload, "nodes": unit_nodes, "rk4_steps": res["rk4_steps"],
-                       "path": res["path"], "parallelism": "single GPU"},
+                       "path": res["path"], "coupling": res.get("coupling", "x"), "parallelism": "single GPU"},
             "roofline": roof, "cpu_baseline": None, "detail": res, "also": []}), flush=True)
         return
     attainable = stx.sto_read_bandwidth(2 << 30, 5)

@@ -54,7 +54,8 @@ typedef enum {
     STO_PATH_RESIDENT = 2,  /* W split across the CUs' LDS; all steps in one cooperative launch */
     STO_PATH_STREAM = 3,    /* W streamed from HBM once per RK4 stage, one launch per stage */
     STO_PATH_MULTI = 4,     /* S input streams share W: the coupling of all streams is one FP32
-                               MFMA matrix product per stage; all steps in one cooperative launch */
+                               MFMA matrix product per stage; all steps in one cooperative launch;
+                               both couplings, n <= 1024 */
     STO_PATH_BATCH = 5      /* S input streams share W: the same FP32 MFMA product, one launch per
                                RK4 stage; both couplings, any n (chosen for S > 1 when
                                STO_PATH_MULTI cannot run the reservoir) */
@@ -117,7 +118,7 @@ sto_status reservoir_create(int64_t n, int64_t n_in, const sto_params *prm,
  *   streams  S >= 1; S == 1 is reservoir_create
  *   m0       host, S*n*3 doubles, [stream][node][xyz]
  * For S > 1 prm->dtype must be STO_F32 (STO_E_UNSUPPORTED otherwise) and the
- * handle runs STO_PATH_MULTI when it can (STO_COUPLE_X, n <= 1024, all S x n
+ * handle runs STO_PATH_MULTI when it can (either coupling, n <= 1024, all
  * tiles co-resident), else STO_PATH_BATCH; prm->path may ask for either
  * (STO_E_UNSUPPORTED if STO_PATH_MULTI cannot run it).  For such a handle, u
  * and states of the run calls gain a stream axis: u is [sample][stream][n_in]

@@ -626,10 +626,9 @@ sto_status reservoir_create_streams(int64_t n, int64_t n_in, int64_t streams, co
     if (streams > 1 || path == STO_PATH_MULTI || path == STO_PATH_BATCH) {
         // the persistent multi-stream kernel when it can run the reservoir,
         // else one launch per stage (both couplings, any n)
-        const bool multi_ok = !xyz && sto::multi_fits((int)n, (int)streams, nullptr, nullptr);
+        const bool multi_ok = sto::multi_fits((int)n, (int)streams, xyz, nullptr, nullptr);
         const char* why = nullptr;
         if (prm->dtype != STO_F32) why = "the multi-stream paths compute in FP32";
-        else if (path == STO_PATH_MULTI && xyz) why = "the persistent multi-stream path couples m^x only";
         else if (path == STO_PATH_MULTI && !multi_ok)
             why = "n x streams does not fit the persistent multi-stream kernel (n <= 1024, all tiles co-resident)";
         else if (path != STO_PATH_AUTO && path != STO_PATH_MULTI && path != STO_PATH_BATCH)
@@ -675,7 +674,7 @@ sto_status reservoir_create_streams(int64_t n, int64_t n_in, int64_t streams, co
     if (path == STO_PATH_RESIDENT) {
         ALLOC(r->xchg, 3 * vec);
     } else if (path == STO_PATH_MULTI) {
-        ALLOC(r->xchg, 3 * (size_t)streams * r->ld * r->elem);
+        ALLOC(r->xchg, 3 * (size_t)(xyz ? 3 : 1) * streams * r->ld * r->elem);
     }
     ALLOC(r->bad, sizeof(int));
     ALLOC(r->sync, 256);

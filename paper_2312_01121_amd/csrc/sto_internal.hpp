@@ -102,7 +102,7 @@ template <typename T> hipError_t run_small(const DevState<T>& d, const Coef<T>& 
 template <typename T> hipError_t run_resident(const DevState<T>& d, const Coef<T>& k, const RunSpec& r);
 
 // MULTI path (S streams, FP32 MFMA): whether n x streams fits and runs.
-bool multi_fits(int n, int streams, int* grid_x, int* grid_y);
+bool multi_fits(int n, int streams, int xyz, int* grid_x, int* grid_y);
 hipError_t run_multi(const DevState<float>& d, const Coef<float>& k, const RunSpec& r, int streams);
 
 // SWEEP path launcher (one launch per RK4 stage over every reservoir).

@@ -2,23 +2,30 @@
 // matrix W, one set of constants, S states).  Per RK4 stage the coupling of
 // all streams is one matrix product, C = a_cp * W X with X the N x S block of
 // stage inputs m^x (paper, Eq. (coup); Sec. 3.3 writes the single-stream
-// case as W^cp x), evaluated with FP32 MFMA (v_mfma_f32_16x16x4f32, FP32
+// case as W^cp x), or the N x 3S block of all three components under the
+// isotropic coupling, evaluated with FP32 MFMA (v_mfma_f32_16x16x4f32, FP32
 // accumulation) and fused with the pointwise right-hand side of Eq. (gov)
 // and the RK4 bookkeeping (Sec. 3.2).
 //
-// Tiling.  Workgroup (bi, bj) owns the 16 x 16 output tile of nodes
-// 16 bi..16 bi + 15 and streams 16 bj..16 bj + 15 for the whole run.  Its four
+// Tiling.  The columns of X are (stream, component) pairs.  Workgroup
+// (bi, bj) owns the 16-row output tile of nodes 16 bi..16 bi + 15 against the
+// 16 columns of SPW streams (16 streams of one component, or 5 streams of
+// three components with the 16th column empty) for the whole run.  Its four
 // waves split the contraction dimension into quarters; each wave keeps its
 // 16 rows x N/4 slice of W in registers as MFMA A operands (one element per
-// lane per MFMA), reads the stage inputs of its 16 streams from LDS as B
+// lane per MFMA), reads the stage inputs of its columns from LDS as B
 // operands, and the four partial tiles are summed in LDS in a fixed order.
-// Thread t then owns the pair (node 16 bi + t/16, stream 16 bj + t%16): its
-// state, RK4 accumulator and stage input stay in registers.
+// One thread per (node, stream) pair then takes the pair's C coupling sums:
+// its state, RK4 accumulator and stage input stay in registers.
 //
-// Stage inputs are exchanged through three rotating global buffers, laid out
-// [stream][node], whose unpublished entries hold a sentinel bit pattern; the
-// protocol (poll, re-arm two stages ahead, compute while those stores
-// complete, wait for them, publish) is the one of the resident kernel.  Every wait is bounded and
+// Exchange.  Stage inputs move through three rotating global buffers, laid
+// out [component][stream][node], whose unpublished entries hold a sentinel
+// bit pattern.  Each workgroup waits for the entries of its columns of the
+// current buffer, re-arms its own entries of the buffer two stages ahead
+// (every workgroup has finished reading that buffer: the gather just saw all
+// outputs of the previous stage, each published after its workgroup's own
+// gather), computes while those stores complete, waits for them and then
+// publishes its outputs into the next buffer.  Every wait is bounded and
 // raises a sticky abort flag when it expires.
 
 #include <climits>
@@ -33,44 +40,75 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBlock = 256;
 constexpr int kTile = 16;
+// LDS row pitch of the gathered stage inputs: 17 (odd), so that the gather's
+// writes (consecutive threads on consecutive nodes of one column) fall in
+// distinct banks; the MFMA operand reads (16 columns of 4 nodes) then meet
+// at most 2-way conflicts.
+constexpr int kXP = kTile + 1;
 constexpr int kSpinLimit = 1 << 20;
+// 4-byte loads in flight per thread in the gather, at most.
+constexpr int kMaxInFlight = 64;
 
-// Wait until the stage inputs of the workgroup's streams are published and
-// store them K-major in LDS: xs[k * 16 + j] for node k and local stream j.
-// Each thread keeps Q loads in flight per round, so a round trip to memory
-// covers Q * 256 entries.
-constexpr int kQ = 16;
-__device__ bool gather_multi(const float* xb, int64_t ld, int n, int s0, int ns, float* xs, int* abort_flag) {
+// Streams per workgroup: the 16 columns hold SPW streams of C components.
+template <bool XYZ> constexpr int streams_per_group() { return XYZ ? 5 : 16; }
+
+// Wait until the stage inputs of the workgroup's columns are published and
+// store them K-major in LDS: xs[k * kXP + js * C + c] for node k, local
+// stream js and component c.  Component c of stream s, node k sits at
+// xb[c * cstride + s * ld + k].  The columns are SPW C rows (js, c) of n
+// entries; thread t covers entries t, t + 256, ... (KI of them) of every
+// row, so all indices but its own column are compile-time constants.  Up to
+// kMaxInFlight loads per thread are in flight in one round trip to memory.
+template <int C, int SPW, int KI>
+__device__ bool gather_multi(const float* xb, int64_t ld, int64_t cstride, int n, int s0, int ns, float* xs,
+                             int* abort_flag) {
+    constexpr int kRows = C * SPW;
+    constexpr int kRpr = kRows < kMaxInFlight / KI ? kRows : kMaxInFlight / KI;   // rows per round
+    constexpr int KQ = kRpr * KI;
+    constexpr int kWords = (KQ + 31) / 32;
     const unsigned* src = reinterpret_cast<const unsigned*>(xb);
-    const int total = ns * n;
+    const int t = threadIdx.x;
     bool ok = true;
-    for (int e0 = 0; e0 < total && ok; e0 += kQ * kBlock) {
-        unsigned v[kQ];
-        unsigned todo = 0;   // bit q: entry q of this round is still unpublished
+    for (int r0 = 0; r0 < kRows && ok; r0 += kRpr) {
+        unsigned v[KQ];
+        unsigned todo[kWords];   // bit q: entry q of this round is still unpublished
 #pragma unroll
-        for (int q = 0; q < kQ; ++q)
-            if (e0 + q * kBlock + (int)threadIdx.x < total) todo |= 1u << q;
+        for (int w = 0; w < kWords; ++w) todo[w] = 0u;
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+            const int row = r0 + q / KI, k = t + kBlock * (q % KI);
+            if (row < kRows && row / C < ns && k < n) todo[q / 32] |= 1u << (q % 32);
+        }
+        auto pending = [&] {
+            unsigned any = 0u;
+#pragma unroll
+            for (int w = 0; w < kWords; ++w) any |= todo[w];
+            return any != 0u;
+        };
         int rounds = 0;
-        while (todo) {
+        while (pending()) {
+            // the addresses are recomputed in every poll round from a copy of
+            // the base that the compiler cannot hoist, instead of holding KQ
+            // 64-bit addresses in registers
+            const unsigned* base = src + (int64_t)s0 * ld + t;
+            asm volatile("" : "+v"(base));
 #pragma unroll
-            for (int q = 0; q < kQ; ++q) {
-                if (todo & (1u << q)) {
-                    const int e = e0 + q * kBlock + threadIdx.x;
-                    const int j = e / n, k = e - j * n;
-                    v[q] = __hip_atomic_load(src + (int64_t)(s0 + j) * ld + k, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
+            for (int q = 0; q < KQ; ++q) {
+                if (todo[q / 32] & (1u << (q % 32))) {
+                    const int row = r0 + q / KI, js = row / C, c = row % C;
+                    v[q] = __hip_atomic_load(base + (c * cstride + (int64_t)js * ld + kBlock * (q % KI)),
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
 #pragma unroll
-            for (int q = 0; q < kQ; ++q) {
-                if ((todo & (1u << q)) && v[q] != ~0u) {
-                    const int e = e0 + q * kBlock + threadIdx.x;
-                    const int j = e / n, k = e - j * n;
-                    xs[k * kTile + j] = __builtin_bit_cast(float, v[q]);
-                    todo &= ~(1u << q);
+            for (int q = 0; q < KQ; ++q) {
+                if ((todo[q / 32] & (1u << (q % 32))) && v[q] != ~0u) {
+                    const int row = r0 + q / KI, k = t + kBlock * (q % KI);
+                    xs[k * kXP + row] = __builtin_bit_cast(float, v[q]);
+                    todo[q / 32] &= ~(1u << (q % 32));
                 }
             }
-            if (todo && (++rounds & 255) == 0) {
+            if (pending() && (++rounds & 255) == 0) {
                 if (rounds > kSpinLimit) {
                     __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     ok = false;
@@ -86,26 +124,30 @@ __device__ bool gather_multi(const float* xb, int64_t ld, int n, int s0, int ns,
     return ok;
 }
 
-// KREG: MFMA steps per wave, >= ceil(N/16) (each step contracts 4 nodes).
-template <int KREG>
+// KREG: MFMA steps per wave, >= ceil(N/16) (each step contracts 4 nodes;
+// N <= 16 KREG).  XYZ: all three components coupled, else m^x only.
+template <int KREG, bool XYZ>
 __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float> k, const double* __restrict__ u,
                                                   float* __restrict__ states, int streams, int samples,
                                                   int substeps, int renorm) {
+    constexpr int C = XYZ ? 3 : 1;
+    constexpr int SPW = streams_per_group<XYZ>();
+    constexpr int KI = KREG <= 16 ? 1 : KREG / 16;   // gather entries per row and thread: 256 KI >= 16 KREG >= N
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int ok_lds;
     const int n = d.n;
     const int64_t ld = d.ld;
     const int kp = (n + kTile - 1) / kTile * kTile;             // contraction length padded to 16
-    float* xs = reinterpret_cast<float*>(smem_raw);              // [kp][16]
-    float* cs = xs + (int64_t)kp * kTile;                        // [4 waves][16][16] partial tiles
+    float* xs = reinterpret_cast<float*>(smem_raw);              // [kp][kXP]
+    float* cs = xs + (int64_t)kp * kXP;                          // [4 waves][16][16] partial tiles
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int row0 = blockIdx.x * kTile;
-    const int s0 = blockIdx.y * kTile;
-    const int ns = min(kTile, streams - s0);
+    const int s0 = blockIdx.y * SPW;
+    const int ns = min(SPW, streams - s0);
     int* abort_flag = d.sync + kSyncAbortWord;
     if (threadIdx.x == 0) ok_lds = 1;
-    for (int i = threadIdx.x; i < kp * kTile; i += kBlock) xs[i] = 0.0f;   // padded nodes/streams stay 0
+    for (int i = threadIdx.x; i < kp * kXP; i += kBlock) xs[i] = 0.0f;   // padded nodes and columns stay 0
 
     // A operands: this wave's quarter of the contraction for the tile's rows.
     const int kq = kp / 4;                                       // nodes per wave (multiple of 4)
@@ -120,16 +162,20 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
         }
     }
 
-    // the (node, stream) pair of this thread
-    const int node = row0 + (threadIdx.x >> 4);
-    const int strm = s0 + (threadIdx.x & 15);
-    const bool mine = node < n && strm < streams;
+    // the (node, stream) pair of this thread: output row ti, first column tj
+    // of the stream's C columns
+    const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
+    const int js = tj / C;
+    const int node = row0 + ti;
+    const int strm = s0 + js;
+    const bool mine = tj % C == 0 && js < ns && node < n;
     const int nd = min(node, n - 1), sd = min(strm, streams - 1);
     const float* m_in = d.m + (int64_t)sd * 3 * ld;
     float mx = m_in[nd], my = m_in[ld + nd], mz = m_in[2 * ld + nd];
     float sx = mx, sy = my, sz = mz, ax = 0.f, ay = 0.f, az = 0.f;
-    float* xbuf = d.xchg;                                        // [3][streams][ld]
-    const int64_t bstride = (int64_t)streams * ld;
+    float* xbuf = d.xchg;                                        // [3 buffers][C][streams][ld]
+    const int64_t cstride = (int64_t)streams * ld;               // one component of one buffer
+    const int64_t bstride = C * cstride;                         // one buffer
 
     int sigma = 0;
     for (int s = 0; s < samples; ++s) {
@@ -141,36 +187,44 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
                 float* xout = xbuf + (int64_t)((sigma + 1) % 3) * bstride;
                 float* xold = xbuf + (int64_t)((sigma + 2) % 3) * bstride;
                 __syncthreads();
-                if (!gather_multi(xin, ld, n, s0, ns, xs, abort_flag)) ok_lds = 0;
+                if (!gather_multi<C, SPW, KI>(xin, ld, cstride, n, s0, ns, xs, abort_flag)) ok_lds = 0;
                 __syncthreads();
                 if (ok_lds == 0) return;
-                // re-arm this pair's entry of the buffer two stages ahead now:
-                // every workgroup finished reading it (the gather just saw all
-                // outputs of the previous stage, each published after its
-                // workgroup's own gather), and its store then completes while
-                // the stage is computed
-                if (mine)
-                    __hip_atomic_store(reinterpret_cast<unsigned*>(xold + (int64_t)strm * ld + node), ~0u,
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                // partial tile of this wave: D[i][j] = sum over its nodes of W[row0+i][k] X[k][s0+j]
+                // re-arm this pair's entries of the buffer two stages ahead now;
+                // the stores complete while the stage is computed
+                if (mine) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+                        __hip_atomic_store(reinterpret_cast<unsigned*>(xold + c * cstride + (int64_t)strm * ld + node),
+                                           ~0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                // partial tile of this wave: D[i][col] = sum over its nodes of
+                // W[row0+i][k] X[k][col]
                 f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int t = 0; t < KREG; ++t) {
                     if (t < steps) {
                         const int kk = wave * kq + 4 * t + (lane >> 4);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[t], xs[kk * kTile + (lane & 15)], acc, 0, 0,
-                                                                   0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[t], xs[kk * kXP + (lane & 15)], acc, 0, 0, 0);
                     }
                 }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) cs[(wave * kTile + 4 * (lane >> 4) + r) * kTile + (lane & 15)] = acc[r];
                 __syncthreads();
-                const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
-                const float dot = ((cs[(0 * kTile + ti) * kTile + tj] + cs[(1 * kTile + ti) * kTile + tj]) +
-                                   cs[(2 * kTile + ti) * kTile + tj]) +
-                                  cs[(3 * kTile + ti) * kTile + tj];
+                float dot[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const int col = min(tj + c, kTile - 1);   // stays in the tile for threads that own no pair
+                    dot[c] = ((cs[(0 * kTile + ti) * kTile + col] + cs[(1 * kTile + ti) * kTile + col]) +
+                              cs[(2 * kTile + ti) * kTile + col]) +
+                             cs[(3 * kTile + ti) * kTile + col];
+                }
                 float fx, fy, fz;
-                llg_rhs<float, false>(k, sx, sy, sz, k.a_cp * dot, 0.f, 0.f, hin, fx, fy, fz);
+                if constexpr (XYZ)
+                    llg_rhs<float, true>(k, sx, sy, sz, k.a_cp * dot[0], k.a_cp * dot[1], k.a_cp * dot[2], hin, fx,
+                                         fy, fz);
+                else
+                    llg_rhs<float, false>(k, sx, sy, sz, k.a_cp * dot[0], 0.f, 0.f, hin, fx, fy, fz);
                 float nx = rk4_update(k, stage, mx, ax, fx);
                 float ny = rk4_update(k, stage, my, ay, fy);
                 float nz = rk4_update(k, stage, mz, az, fz);
@@ -185,9 +239,13 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
                 sz = nz;
                 if (mine) {
                     const int64_t o = (int64_t)strm * ld + node;
-                    // the re-arm store must complete before the publish
+                    // the re-arm stores must complete before the publish
                     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
                     __hip_atomic_store(xout + o, nx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if constexpr (XYZ) {
+                        __hip_atomic_store(xout + cstride + o, ny, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(xout + 2 * cstride + o, nz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
                 }
             }
         }
@@ -209,15 +267,17 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
     }
 }
 
-__global__ void k_multi_prologue(const float* m, float* xchg, int streams, int64_t ld) {
-    // buffer 0 <- m^x of every stream; buffers 1 and 2 <- sentinel
+__global__ void k_multi_prologue(const float* m, float* xchg, int streams, int64_t ld, int C) {
+    // buffer 0 <- the coupled components of every stream ([C][streams][ld]);
+    // buffers 1 and 2 <- sentinel
     const int64_t per = (int64_t)streams * ld;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 3 * per;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 3 * C * per;
          i += (int64_t)gridDim.x * blockDim.x) {
         unsigned v = ~0u;
-        if (i < per) {
-            const int64_t st = i / ld, node = i - st * ld;
-            v = __builtin_bit_cast(unsigned, m[st * 3 * ld + node]);
+        if (i < C * per) {
+            const int64_t c = i / per, r = i - c * per;
+            const int64_t st = r / ld, node = r - st * ld;
+            v = __builtin_bit_cast(unsigned, m[st * 3 * ld + c * ld + node]);
         }
         reinterpret_cast<unsigned*>(xchg)[i] = v;
     }
@@ -232,23 +292,60 @@ int kreg_for(int n) {
     return 0;
 }
 
+template <int KREG>
+const void* multi_kernel(int xyz) {
+    return xyz ? reinterpret_cast<const void*>(&k_multi<KREG, true>)
+               : reinterpret_cast<const void*>(&k_multi<KREG, false>);
+}
+
 }  // namespace
 
 size_t multi_lds_bytes(int n) {
     const int kp = (n + kTile - 1) / kTile * kTile;
-    return ((size_t)kp * kTile + 4 * kTile * kTile) * sizeof(float);
+    return ((size_t)kp * kXP + 4 * kTile * kTile) * sizeof(float);
 }
 
-bool multi_fits(int n, int streams, int* grid_x, int* grid_y) {
-    if (n < 1 || streams < 1 || kreg_for(n) == 0 || n > 16 * kMaxKreg) return false;
-    const int gx = (n + kTile - 1) / kTile, gy = (streams + kTile - 1) / kTile;
+namespace {
+
+// The kernel instance for n nodes, with its dynamic LDS limit raised to what
+// it needs; nullptr when n is out of range.
+const void* multi_fn(int n, int xyz) {
+    const void* fn = nullptr;
+    switch (kreg_for(n)) {
+        case 4: fn = multi_kernel<4>(xyz); break;
+        case 8: fn = multi_kernel<8>(xyz); break;
+        case 16: fn = multi_kernel<16>(xyz); break;
+        case 32: fn = multi_kernel<32>(xyz); break;
+        case 64: fn = multi_kernel<64>(xyz); break;
+        default: return nullptr;
+    }
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)multi_lds_bytes(n)) != hipSuccess)
+        return nullptr;
+    return fn;
+}
+
+int stream_groups(int streams, int xyz) {
+    const int spw = xyz ? streams_per_group<true>() : streams_per_group<false>();
+    return (streams + spw - 1) / spw;
+}
+
+}  // namespace
+
+// Whether every tile can be co-resident (the cooperative launch needs all of
+// them): the LDS fits and the grid is within the occupancy the runtime
+// reports for this kernel instance.
+bool multi_fits(int n, int streams, int xyz, int* grid_x, int* grid_y) {
+    if (n < 1 || streams < 1 || n > 16 * kMaxKreg) return false;
+    const int gx = (n + kTile - 1) / kTile, gy = stream_groups(streams, xyz);
+    const size_t lds = multi_lds_bytes(n);
+    if (lds + 64 > 160 * 1024) return false;
+    const void* fn = multi_fn(n, xyz);
+    if (!fn) return false;
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return false;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
-    const size_t lds = multi_lds_bytes(n);
-    if (lds + 64 > 160 * 1024) return false;
-    per_cu = (int)std::min<size_t>(8, (160 * 1024) / (lds + 64));
-    if ((int64_t)gx * gy > (int64_t)cus * per_cu) return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, lds) != hipSuccess) return false;
+    if (per_cu < 1 || (int64_t)gx * gy > (int64_t)cus * per_cu) return false;
     if (grid_x) *grid_x = gx;
     if (grid_y) *grid_y = gy;
     return true;
@@ -256,11 +353,12 @@ bool multi_fits(int n, int streams, int* grid_x, int* grid_y) {
 
 hipError_t run_multi(const DevState<float>& d, const Coef<float>& k, const RunSpec& r, int streams) {
     int gx = 0, gy = 0;
-    if (!multi_fits(d.n, streams, &gx, &gy)) return hipErrorInvalidValue;
+    if (!multi_fits(d.n, streams, r.xyz, &gx, &gy)) return hipErrorInvalidValue;
     const size_t lds = multi_lds_bytes(d.n);
     hipError_t e = hipMemsetAsync(d.sync, 0, 256, r.stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_multi_prologue, dim3(64), dim3(256), 0, r.stream, (const float*)d.m, d.xchg, streams, d.ld);
+    hipLaunchKernelGGL(k_multi_prologue, dim3(64), dim3(256), 0, r.stream, (const float*)d.m, d.xchg, streams, d.ld,
+                       r.xyz ? 3 : 1);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     DevState<float> dd = d;
@@ -269,16 +367,8 @@ hipError_t run_multi(const DevState<float>& d, const Coef<float>& k, const RunSp
     float* states = static_cast<float*>(r.states);
     int st = streams, samples = r.samples, substeps = r.substeps, renorm = r.renorm;
     void* args[] = {&dd, &kk, &u, &states, &st, &samples, &substeps, &renorm};
-    const void* fn = nullptr;
-    switch (kreg_for(d.n)) {
-        case 4: fn = reinterpret_cast<const void*>(&k_multi<4>); break;
-        case 8: fn = reinterpret_cast<const void*>(&k_multi<8>); break;
-        case 16: fn = reinterpret_cast<const void*>(&k_multi<16>); break;
-        case 32: fn = reinterpret_cast<const void*>(&k_multi<32>); break;
-        default: fn = reinterpret_cast<const void*>(&k_multi<64>); break;
-    }
-    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+    const void* fn = multi_fn(d.n, r.xyz);
+    if (!fn) return hipErrorInvalidValue;
     e = hipLaunchCooperativeKernel(fn, dim3(gx, gy), dim3(kBlock), args, (unsigned)lds, r.stream);
     if (e != hipSuccess) return e;
     return hipGetLastError();

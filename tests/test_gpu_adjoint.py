@@ -290,7 +290,7 @@ def test_adjoint_streams64_xyz_oracle_and_central_fd(stx):
     say("adjoint streams64 xyz")
     ref = oracle_streams_adjoint(w, w_in, m0_ref, a["u"], prm, g_rec, None)
     with stx.Reservoir(w, w_in, m0s, lib_params(prm, "f32"), streams=S) as r:
-        assert r.path == "batch"
+        assert r.path == "multi"
         got = r.adjoint(m0s, a["u"], g_rec, checkpoint_every=2)
     compare(got, ref, F32_TOL, "streams64 xyz")
 

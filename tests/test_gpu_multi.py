@@ -38,34 +38,51 @@ def stream_case(n, streams, seed, samples):
     return w, w_in, m0, u
 
 
-@pytest.mark.parametrize("n,streams", [(16, 2), (100, 5), (257, 17), (512, 64)])
-def test_multi_one_step_matches_oracle(stx, n, streams):
-    """One RK4 step per stream from the same FP32-representable state."""
+def distinct_states(rng, streams, n):
+    m0s = np.empty((streams, n, 3))
+    for s in range(streams):
+        v = rng.standard_normal((n, 3)) * 0.05
+        v[:, 2] += 1.0
+        m0s[s] = v / np.linalg.norm(v, axis=1, keepdims=True)
+    return m0s
+
+
+@pytest.mark.parametrize("n,streams,coupling", [(16, 2, "x"), (100, 5, "x"), (257, 17, "x"), (512, 64, "x"),
+                                                (16, 2, "xyz"), (100, 5, "xyz"), (257, 17, "xyz"),
+                                                (512, 64, "xyz"), (700, 20, "xyz"), (1000, 7, "xyz"),
+                                                (1024, 33, "x")])
+def test_multi_one_step_matches_oracle(stx, n, streams, coupling):
+    """One RK4 step per stream from the same FP32-representable state (every
+    stream its own initial state), both couplings; several tiles and ragged
+    node and stream tails."""
     w, w_in, m0, u = stream_case(n, streams, seed=n, samples=1)
-    prm = oracle_params(a_cp=0.3, substeps=1)
-    say("multi one step", n, streams)
-    m0s = np.broadcast_to(m0, (streams, n, 3)).copy()
+    prm = oracle_params(a_cp=0.3, substeps=1, coupling=coupling)
+    say("multi one step", n, streams, coupling)
+    m0s = distinct_states(np.random.default_rng(n + 7), streams, n)
     with stx.Reservoir(w, w_in, m0s, lib_params(prm, dtype="f32"), streams=streams) as r:
         assert r.path == "multi"
         rec = r.run(u)
     worst = 0.0
     for s in (range(streams) if streams <= 8 else (0, 1, streams // 2, streams - 1)):
-        rec_o, _ = sto.run(f32(w), f32(w_in), f32(m0), u[:, s], prm)
+        rec_o, _ = sto.run(f32(w), f32(w_in), f32(m0s[s]), u[:, s], prm)
         worst = max(worst, float(np.max(np.abs(rec[:, s] - rec_o))))
     say("  max diff", worst)
     assert worst <= F32_TOL
 
 
-def test_multi_streams64_lyapunov_horizon(stx):
+@pytest.mark.parametrize("coupling", ["x", "xyz"])
+def test_multi_streams64_lyapunov_horizon(stx, coupling):
     """The 64-stream, 512-node workload over ~one Lyapunov time (8 samples =
-    160 steps), checked per stream against the FP64 oracle."""
+    160 steps), checked per stream against the FP64 oracle, for the paper's
+    coupling and the isotropic one (the N x 192 product)."""
     wl = WORKLOADS["streams64"]
     S = STREAMS["streams64"]
     a = make_stream_arrays(wl, S, samples=8)
-    prm = oracle_params(a_cp=wl.a_cp, a_in=wl.a_in)
+    prm = oracle_params(a_cp=wl.a_cp, a_in=wl.a_in, coupling=coupling)
     m0s = np.broadcast_to(a["m0"], (S, wl.n, 3)).copy()
-    say("streams64 horizon")
+    say("streams64 horizon", coupling)
     with stx.Reservoir(a["W"], a["w_in"], m0s, lib_params(prm, dtype="f32"), streams=S) as r:
+        assert r.path == "multi"
         rec = r.run(a["u"])
     worst = 0.0
     for s in (0, 7, 31, 63):
@@ -75,10 +92,11 @@ def test_multi_streams64_lyapunov_horizon(stx):
     assert worst <= F32_TOL
 
 
-def test_multi_continuation_and_state(stx):
+@pytest.mark.parametrize("coupling", ["x", "xyz"])
+def test_multi_continuation_and_state(stx, coupling):
     n, S = 70, 9
     w, w_in, m0, u = stream_case(n, S, seed=3, samples=6)
-    prm = oracle_params(a_cp=0.3)
+    prm = oracle_params(a_cp=0.3, coupling=coupling)
     rng = np.random.default_rng(4)
     m0s = np.empty((S, n, 3))
     for s in range(S):
@@ -106,14 +124,21 @@ def test_multi_continuation_and_state(stx):
 def test_multi_rejects_unsupported(stx):
     w, w_in, m0, _ = random_case(20, seed=5, samples=1)
     m0s = np.broadcast_to(m0, (3, 20, 3)).copy()
-    for kw in (dict(dtype="f64"), dict(dtype="f32", coupling="xyz", path="multi")):
-        prm = oracle_params(coupling=kw.get("coupling", "x"))
+    with pytest.raises(stx.StoError) as ei:
+        stx.Reservoir(w, w_in, m0s, lib_params(oracle_params(), dtype="f64"), streams=3)
+    assert ei.value.status == stx.STO_E_UNSUPPORTED
+    # beyond the persistent kernel (N > 1024: its W slice no longer fits the
+    # registers): path="multi" is refused, the automatic choice is the
+    # per-stage batch path
+    for n, coupling in ((1100, "x"), (1100, "xyz")):
+        w, w_in, m0, _ = random_case(n, seed=5, samples=1)
+        m0s = np.broadcast_to(m0, (3, n, 3)).copy()
+        prm = oracle_params(coupling=coupling)
         with pytest.raises(stx.StoError) as ei:
-            stx.Reservoir(w, w_in, m0s, lib_params(prm, dtype=kw["dtype"], path=kw.get("path", "auto")), streams=3)
+            stx.Reservoir(w, w_in, m0s, lib_params(prm, dtype="f32", path="multi"), streams=3)
         assert ei.value.status == stx.STO_E_UNSUPPORTED
-    # isotropic coupling with several streams runs on the per-stage batch path
-    with stx.Reservoir(w, w_in, m0s, lib_params(oracle_params(coupling="xyz"), dtype="f32"), streams=3) as r:
-        assert r.path == "batch"
+        with stx.Reservoir(w, w_in, m0s, lib_params(prm, dtype="f32"), streams=3) as r:
+            assert r.path == "batch"
 
 
 # ---------------------------------------------------------------------------
@@ -153,7 +178,7 @@ def test_batch_streams64_xyz_lyapunov_horizon(stx):
     prm = oracle_params(a_cp=wl.a_cp, a_in=wl.a_in, coupling="xyz")
     m0s = np.broadcast_to(a["m0"], (S, wl.n, 3)).copy()
     say("streams64 xyz horizon")
-    with stx.Reservoir(a["W"], a["w_in"], m0s, lib_params(prm, dtype="f32"), streams=S) as r:
+    with stx.Reservoir(a["W"], a["w_in"], m0s, lib_params(prm, dtype="f32", path="batch"), streams=S) as r:
         assert r.path == "batch"
         rec = r.run(a["u"])
     worst = 0.0
@@ -164,12 +189,13 @@ def test_batch_streams64_xyz_lyapunov_horizon(stx):
     assert worst <= F32_TOL
 
 
-def test_batch_continuation_and_agreement(stx):
+@pytest.mark.parametrize("coupling", ["x", "xyz"])
+def test_batch_continuation_and_agreement(stx, coupling):
     """Split runs equal the whole run bitwise; the batch and the persistent
     multi-stream paths agree to FP32 rounding."""
     n, S = 70, 9
     w, w_in, m0, u = stream_case(n, S, seed=3, samples=6)
-    prm = oracle_params(a_cp=0.3)
+    prm = oracle_params(a_cp=0.3, coupling=coupling)
     m0s = np.broadcast_to(m0, (S, n, 3)).copy()
     with stx.Reservoir(w, w_in, m0s, lib_params(prm, dtype="f32", path="batch"), streams=S) as r:
         whole = r.run(u)

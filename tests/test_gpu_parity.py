@@ -196,6 +196,61 @@ def test_steps_validation_and_noop(stx):
 
 
 # ---------------------------------------------------------------------------
+# The largest size of each path and the first size past it
+# ---------------------------------------------------------------------------
+def auto_path(stx, n, dtype, coupling):
+    w, w_in, m0, _ = random_case(n, seed=1, samples=1)
+    with make(stx, w, w_in, m0, oracle_params(coupling=coupling), dtype=dtype) as r:
+        return r.path
+
+
+def last_n_on(stx, path, lo, hi, dtype, coupling):
+    """Largest n in [lo, hi) that the automatic choice sends to ``path``,
+    by bisection (the choice is monotone in n: the small kernel's LDS, the
+    resident kernel's rows per workgroup and LDS all grow with n)."""
+    assert auto_path(stx, lo, dtype, coupling) == path
+    assert auto_path(stx, hi, dtype, coupling) != path
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if auto_path(stx, mid, dtype, coupling) == path:
+            lo = mid
+        else:
+            hi = mid
+    return lo
+
+
+@pytest.mark.parametrize("dtype,coupling", [("f64", "x"), ("f32", "x"), ("f64", "xyz")])
+def test_path_limits_match_oracle(stx, dtype, coupling):
+    """At the largest N of the small and resident kernels, and one node past
+    each (where the automatic choice moves to the next path), the records
+    match the oracle: FP64 over 8 RK4 steps, FP32 over one step from the same
+    FP32-representable inputs."""
+    n_small = last_n_on(stx, "small", 1, 512, dtype, coupling)
+    n_res = last_n_on(stx, "resident", n_small + 1, 4097, dtype, coupling)
+    say("limits", dtype, coupling, "small <=", n_small, "resident <=", n_res)
+    expect = {n_small: "small", n_small + 1: "resident", n_res: "resident", n_res + 1: "stream"}
+    f32 = lambda x: np.asarray(x, dtype=np.float32).astype(np.float64)  # noqa: E731
+    for n, path in expect.items():
+        w, w_in, m0, u = random_case(n, seed=n, samples=2)
+        if dtype == "f64":
+            prm = oracle_params(a_cp=0.3, substeps=4, coupling=coupling)
+            rec_o, fin_o = sto.run(w, w_in, m0, u, prm)
+            tol = F64_TOL
+        else:
+            prm = oracle_params(a_cp=0.3, substeps=1, coupling=coupling)
+            u = u[:1]
+            rec_o, fin_o = sto.run(f32(w), f32(w_in), f32(m0), u, prm)
+            tol = F32_TOL
+        with make(stx, w, w_in, m0, prm, dtype=dtype) as r:
+            assert r.path == path, (n, r.path, path)
+            rec = r.run(u)
+            fin = r.get_state()
+        d = max(maxdiff(rec, rec_o), maxdiff(fin, fin_o))
+        say("  n", n, path, "max diff", d)
+        assert d <= tol
+
+
+# ---------------------------------------------------------------------------
 # FP32
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("name,path", [("sto16", "auto"), ("sto1k", "auto"), ("sto1k", "stream"),
