@@ -51,7 +51,7 @@ template <int C> constexpr int batch_spw() { return C == 3 ? 5 : 16; }
 // c for the pair (node i0 + t/16, stream s0 + (t%16)/C) on the threads t <
 // 256 whose t%16 is the pair's first column.
 constexpr int kWaves = 8;
-constexpr int kJB = 256;          // contraction rows per LDS block
+constexpr int kJB = 512;          // contraction rows per LDS block
 constexpr int kXP = kJB + 4;      // padded row of the X block
 
 struct TileLds {
@@ -69,19 +69,20 @@ __device__ __forceinline__ void tile_product(const float* __restrict__ M, int64_
     const int kr = lane >> 4, c16 = lane & 15;
     bf4 acc = bf4{0.f, 0.f, 0.f, 0.f};
     for (int jb = 0; jb < n; jb += kJB) {
-        // A block: kJB rows x 16 floats, one float4 per thread and pass
-        for (int e = tid; e < kJB * kT / 4; e += 64 * kWaves) {
+        const int tb = (min(kJB, n - jb) + 3) / 4;   // MFMA steps of this block (4 rows each)
+        // A block: 4 tb rows x 16 floats, one float4 per thread and pass
+        for (int e = tid; e < tb * kT; e += 64 * kWaves) {
             const int r = e >> 2, q = e & 3;
             const int j = jb + r;
             bf4 v = bf4{0.f, 0.f, 0.f, 0.f};
             if (j < n) v = *reinterpret_cast<const bf4*>(M + (int64_t)j * ld + i0 + 4 * q);
             *reinterpret_cast<bf4*>(&sh.a[r][4 * q]) = v;
         }
-        // X block: 16 column rows of kJB floats; the empty column, streams
+        // X block: 16 column rows of 4 tb floats; the empty column, streams
         // beyond S and nodes beyond n read as zero (X's rows are ld >= n long
         // and 16-byte aligned)
-        for (int e = tid; e < kT * kJB / 4; e += 64 * kWaves) {
-            const int col = e / (kJB / 4), q = e - col * (kJB / 4);
+        for (int e = tid; e < kT * tb; e += 64 * kWaves) {
+            const int col = e / tb, q = e - col * tb;
             const int sl = col / C, c = col - sl * C;
             const int j = jb + 4 * q;
             bf4 v = bf4{0.f, 0.f, 0.f, 0.f};
@@ -91,7 +92,7 @@ __device__ __forceinline__ void tile_product(const float* __restrict__ M, int64_
         }
         __syncthreads();
         // MFMA steps of 4 rows: wave w takes steps w, w + 8, ...
-        for (int t = wave; t < kJB / 4; t += kWaves) {
+        for (int t = wave; t < tb; t += kWaves) {
             const int jl = 4 * t + kr;
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(sh.a[jl][c16], sh.x[c16][jl], acc, 0, 0, 0);
         }
