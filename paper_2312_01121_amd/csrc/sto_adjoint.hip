@@ -429,18 +429,21 @@ __global__ void __launch_bounds__(256) k_adj_scalars(const double* __restrict__ 
 
 // Launch shapes of the two streaming kernels (rows of W per wave x unroll
 // of the column loop); STO_ADJ_ROWS / STO_ADJ_UNROLL choose one for
-// measurements, otherwise 2 rows and unroll 2 (measured fastest at N = 10^4
-// in FP32 and FP64 among the compiled shapes).
+// measurements.  Otherwise 1 row with unroll 4 below 4096 nodes (more waves
+// for a small matrix: at N = 10^3 FP64 the adjoint took 99.7 ms against
+// 117.2 with 2 x 2; one row split over the four waves of a workgroup was
+// slower still, 111.4) and 2 rows with unroll 2 above (at N = 10^4 FP32,
+// 202 ms against 227 with 1 x 4).
 int env_int(const char* name, int dflt) {
     const char* v = getenv(name);
     return v ? atoi(v) : dflt;
 }
 
 template <typename T>
-void adj_shape(int* rows, int* unroll) {
+void adj_shape(int n, int* rows, int* unroll) {
     static const int r = env_int("STO_ADJ_ROWS", 0), u = env_int("STO_ADJ_UNROLL", 0);
-    *rows = 2;
-    *unroll = 2;
+    *rows = n < 4096 ? 1 : 2;
+    *unroll = n < 4096 ? 4 : 2;
     const int ok[][2] = {{1, 4}, {2, 2}, {2, 4}, {4, 1}, {4, 2}};
     for (const auto& v : ok)
         if (v[0] == r && v[1] == u) {
@@ -510,8 +513,8 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
     constexpr int C = XYZ ? 3 : 1;
     const hipStream_t st = a.stream;
     int rows = 2, unroll = 2;
-    adj_shape<T>(&rows, &unroll);
     const int n = a.n, NS = a.streams;
+    adj_shape<T>(n, &rows, &unroll);
     const int64_t ld = a.ld, NSTEP = a.steps;
     const int64_t K = std::max<int64_t>(1, std::min<int64_t>(a.seg_steps, NSTEP));
     const int64_t nseg = (NSTEP + K - 1) / K;
