@@ -239,7 +239,7 @@ def run_streams_workload(stx, torch, name: str, steps: int, warmup: int, couplin
     y = np.nan_to_num(a["y"], nan=0.0)
     y_d = [torch.from_numpy(np.ascontiguousarray(y[:, st])).cuda() for st in range(S)]
     states = torch.empty((wl.samples, S, wl.n, 3), dtype=torch.float32, device="cuda")
-    w_out = torch.empty(wl.n + 1, dtype=torch.float64, device="cuda")
+    w_outs = [torch.empty(wl.n + 1, dtype=torch.float64, device="cuda") for _ in range(S)]
     wash = washout_of(wl.samples)
     stream = torch.cuda.current_stream()
 
@@ -248,11 +248,10 @@ def run_streams_workload(stx, torch, name: str, steps: int, warmup: int, couplin
         e0.record(stream)
         r.run_device(u_d, states, stream)
         e1.record(stream)
-        nm = []
-        for st in range(S):
-            rec = states[:, st].contiguous()
-            nm.append(stx.readout_fit_device(rec, y_d[st], wash, wl.ridge, 0, w_out, stream)[1])
-        return e0, e1, nm
+        # one readout per stream, all fitted in one batched call
+        _, nm = stx.readout_fit_batch_device([states[:, st] for st in range(S)], y_d, wash, wl.ridge, 0, w_outs,
+                                             stream)
+        return e0, e1, list(nm)
 
     for _ in range(warmup):
         one_step()
@@ -337,10 +336,11 @@ def run_streams_adjoint_workload(stx, torch, name: str, coupling: str, steps: in
         r.run_device(u_d, states, stream)
         ev[1].record(stream)
         loss = 0.0
+        w_ds, _ = stx.readout_fit_batch_device([states[:, st] for st in range(S)], y_d, wash, wl.ridge, 0, None,
+                                               stream)
         for st in range(S):
             rec = states[:, st].contiguous()
-            w_d, _ = stx.readout_fit_device(rec, y_d[st], wash, wl.ridge, 0, None, stream)
-            g, j = stx.readout_grad_device(rec, y_d[st], wash, wl.ridge, w_d, 0, None, stream)
+            g, j = stx.readout_grad_device(rec, y_d[st], wash, wl.ridge, w_ds[st], 0, None, stream)
             g_rec[:, st] = g
             loss += j
         ev[2].record(stream)
@@ -403,7 +403,7 @@ def run_sweep_workload(stx, torch, name: str, steps: int, warmup: int, plain_sam
     u_d = torch.from_numpy(a["u"]).cuda()
     y_d = torch.from_numpy(np.nan_to_num(a["y"], nan=0.0)).cuda()
     states = torch.empty(T * sw.nodes * 3, dtype=torch.float32, device="cuda")
-    w_out = torch.empty(max(sw.ns) + 1, dtype=torch.float64, device="cuda")
+    w_outs = [torch.empty(n + 1, dtype=torch.float64, device="cuda") for n in sw.ns]
     wash = washout_of(T)
     stream = torch.cuda.current_stream()
 
@@ -412,11 +412,11 @@ def run_sweep_workload(stx, torch, name: str, steps: int, warmup: int, plain_sam
         e0.record(stream)
         sw.run_device(u_d, states, stream)
         e1.record(stream)
-        nm = []
-        for i, n in enumerate(sw.ns):
-            rec = states[T * 3 * int(sw.offsets[i]): T * 3 * int(sw.offsets[i + 1])].view(T, n, 3)
-            nm.append(stx.readout_fit_device(rec, y_d, wash, sw_def.ridge, 0, w_out[: n + 1], stream)[1])
-        return e0, e1, nm
+        # one readout per reservoir, all fitted in one batched call
+        recs = [states[T * 3 * int(sw.offsets[i]): T * 3 * int(sw.offsets[i + 1])].view(T, n, 3)
+                for i, n in enumerate(sw.ns)]
+        _, nm = stx.readout_fit_batch_device(recs, y_d, wash, sw_def.ridge, 0, w_outs, stream)
+        return e0, e1, list(nm)
 
     for _ in range(warmup):
         one_step()

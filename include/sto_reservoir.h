@@ -313,6 +313,35 @@ sto_status readout_fit_device(const void *states_dev, int32_t dtype, int64_t T, 
                               void *w_out_dev, double *nmse_out, void *hip_stream);
 
 /*
+ * readout_fit_batch_device -- readout_fit_device for `count` record sets,
+ * each with its own target series (which may be one shared buffer), fitted
+ * together: the readouts of a sweep's reservoirs, or of the S streams of a
+ * multi-stream reservoir.  Item q is
+ * fitted exactly as readout_fit_device fits one record set; the kernels
+ * cover all items at once, so the launch count does not grow with `count`.
+ *   count       number of record sets, >= 1
+ *   states_dev  host array of `count` device pointers: record t of item q
+ *               (n[q] x 3 elements of dtype, AoS) starts at element
+ *               t * row_stride[q] of states_dev[q]
+ *   row_stride  host array of `count` strides in elements (>= 3 n[q]), or
+ *               NULL (or 0 entries) for contiguous records, 3 n[q]; e.g.
+ *               3 n S for stream q of a multi-stream reservoir's states
+ *   dtype, T, washout, lambda, features  as readout_fit_device
+ *   n           host array of `count` node counts
+ *   y_dev       host array of `count` device pointers, T doubles each
+ *   w_out_dev   host array of `count` device pointers, each F_q + 1 doubles
+ *   nmse_out    host, `count` doubles
+ *   hip_stream  hipStream_t to enqueue on; returns after the stream finished
+ * Device memory of about 8 (T - washout) sum_q (F_q + 1) bytes for the
+ * design matrices plus the Gram matrices is allocated for the call.
+ * Errors as readout_fit_device; the message names the first item concerned.
+ */
+sto_status readout_fit_batch_device(int32_t count, const void *const *states_dev, const int64_t *row_stride,
+                                    int32_t dtype, int64_t T, const int64_t *n, const void *const *y_dev,
+                                    int64_t washout, double lambda, int32_t features,
+                                    double *const *w_out_dev, double *nmse_out, void *hip_stream);
+
+/*
  * readout_grad_device -- the ridge objective at its optimum and its gradient
  * with respect to the records, the loss to feed reservoir_adjoint_device.
  *   J = (|Phi w - y|^2 + lambda |w|^2) / T', T' = T - washout fitted rows,

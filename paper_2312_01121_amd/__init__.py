@@ -97,6 +97,11 @@ def _load():
     lib.readout_fit_device.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, vp, ctypes.c_int64,
                                        ctypes.c_double, ctypes.c_int32, vp, dp, vp]
     lib.readout_fit_device.restype = ctypes.c_int
+    lib.readout_fit_batch_device.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.POINTER(vp), ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
+                                             ctypes.POINTER(vp), dp, vp]
+    lib.readout_fit_batch_device.restype = ctypes.c_int
     pp = ctypes.POINTER(dp)
     lib.sweep_create.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64,
                                  ctypes.POINTER(sto_params), pp, pp, pp, ctypes.POINTER(H)]
@@ -133,7 +138,7 @@ _lib = _load()
 
 EXPORTED = ("reservoir_create", "reservoir_create_streams", "reservoir_streams", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
             "reservoir_set_state", "reservoir_path", "reservoir_destroy", "readout_fit", "readout_fit_device",
-            "sweep_create", "sweep_nodes", "sweep_run", "sweep_run_device", "sweep_get_state", "sweep_destroy",
+            "readout_fit_batch_device", "sweep_create", "sweep_nodes", "sweep_run", "sweep_run_device", "sweep_get_state", "sweep_destroy",
             "reservoir_adjoint", "reservoir_adjoint_device", "readout_grad_device",
             "sto_read_bandwidth", "sto_set_stream_variant", "sto_last_error")
 
@@ -253,6 +258,53 @@ def readout_fit_device(states_dev, y_dev, washout: int, lam: float, features: in
                                    ctypes.c_void_p(y_dev.data_ptr()), washout, lam, features,
                                    ctypes.c_void_p(w_out_dev.data_ptr()), _dptr(nmse), ctypes.c_void_p(s)))
     return w_out_dev, float(nmse[0])
+
+
+def readout_fit_batch_device(states_list, y_dev, washout: int, lam: float, features: int = 0, w_list=None,
+                             stream=None):
+    """Fit one readout per record set, all at once.  states_list: CUDA
+    float32/float64 tensors of shape (T, n_q, 3) with contiguous records
+    (strides (r, 3, 1) for any row stride r, e.g. states[:, q] of a
+    (T, S, n, 3) multi-stream record tensor); y_dev: one CUDA float64 (T,)
+    target tensor shared by all, or a list of one per record set; w_list:
+    CUDA float64 tensors of F_q + 1 weights (allocated if None).  Returns
+    (w_list, nmse array)."""
+    import torch
+    assert len(states_list) >= 1
+    y_list = list(y_dev) if isinstance(y_dev, (list, tuple)) else [y_dev] * len(states_list)
+    assert len(y_list) == len(states_list)
+    T = states_list[0].shape[0]
+    dt = states_list[0].dtype
+    count = len(states_list)
+    ptrs = (ctypes.c_void_p * count)()
+    strides = (ctypes.c_int64 * count)()
+    ns = (ctypes.c_int64 * count)()
+    if w_list is None:
+        w_list = [None] * count
+    w_list = list(w_list)
+    wptrs = (ctypes.c_void_p * count)()
+    yptrs = (ctypes.c_void_p * count)()
+    for q, st in enumerate(states_list):
+        yq = y_list[q]
+        assert yq.is_cuda and yq.dtype == torch.float64 and yq.is_contiguous() and yq.numel() == T
+        yptrs[q] = yq.data_ptr()
+        assert st.is_cuda and st.dim() == 3 and st.shape[0] == T and st.shape[2] == 3 and st.dtype == dt
+        assert st.stride(2) == 1 and st.stride(1) == 3, "records of one row must be contiguous (n, 3)"
+        n = st.shape[1]
+        cols = (3 * n if features else n) + 1
+        if w_list[q] is None:
+            w_list[q] = torch.empty(cols, dtype=torch.float64, device=st.device)
+        assert w_list[q].dtype == torch.float64 and w_list[q].numel() == cols and w_list[q].is_contiguous()
+        ptrs[q] = st.data_ptr()
+        strides[q] = st.stride(0)
+        ns[q] = n
+        wptrs[q] = w_list[q].data_ptr()
+    dtype = {torch.float64: STO_F64, torch.float32: STO_F32}[dt]
+    nmse = np.empty(count)
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    _check(_lib.readout_fit_batch_device(count, ptrs, strides, dtype, T, ns, yptrs, washout, lam, features, wptrs,
+                                         _dptr(nmse), ctypes.c_void_p(s)))
+    return w_list, nmse
 
 
 def _vp(t):

@@ -16,6 +16,7 @@
 
 #include "../../include/sto_reservoir.h"
 #include "sto_adjoint.hpp"
+#include "readout_batch.hpp"
 #include "sto_internal.hpp"
 #include "sto_sweep.hpp"
 #include "stream_tune.hpp"
@@ -905,6 +906,37 @@ sto_status readout_fit_device(const void* states_dev, int32_t dtype, int64_t T, 
     return rc == 0 ? STO_OK : readout_status(rc, err);
 }
 
+
+sto_status readout_fit_batch_device(int32_t count, const void* const* states_dev, const int64_t* row_stride,
+                                    int32_t dtype, int64_t T, const int64_t* n, const void* const* y_dev, int64_t washout,
+                                    double lambda, int32_t features, double* const* w_out_dev, double* nmse_out,
+                                    void* hip_stream) {
+    if (count < 1 || !states_dev || !n || !y_dev || !w_out_dev || !nmse_out)
+        return fail(STO_E_INVALID, "count >= 1 and non-NULL arguments");
+    if (dtype != STO_F64 && dtype != STO_F32) return fail(STO_E_INVALID, "unknown dtype %d", dtype);
+    const size_t elem = dtype == STO_F64 ? 8 : 4;
+    std::vector<const void*> rec(count);
+    std::vector<const double*> y(count);
+    std::vector<int64_t> stride(count);
+    for (int32_t q = 0; q < count; ++q) {
+        sto_status st = readout_check(T, n[q], washout, lambda, features);
+        if (st != STO_OK) return st;
+        if (!states_dev[q] || !w_out_dev[q] || !y_dev[q]) return fail(STO_E_INVALID, "item %d: NULL pointer", q);
+        stride[q] = row_stride && row_stride[q] ? row_stride[q] : 3 * n[q];
+        if (stride[q] < 3 * n[q]) return fail(STO_E_INVALID, "item %d: row_stride below 3 n", q);
+        rec[q] = static_cast<const char*>(states_dev[q]) + (size_t)washout * stride[q] * elem;
+        y[q] = static_cast<const double*>(y_dev[q]) + washout;
+    }
+    const char* err = nullptr;
+    int bad = -1;
+    int rc = sto::readout_solve_batch(count, rec.data(), stride.data(), dtype == STO_F32, (int)(T - washout), n,
+                                      features, y.data(), lambda, w_out_dev, nmse_out,
+                                      static_cast<hipStream_t>(hip_stream), &err, &bad);
+    if (rc == 0) return STO_OK;
+    if (rc == 1) return fail(STO_E_INVALID, "readout of item %d: %s", bad, err ? err : "not positive definite");
+    if (rc == 3) return fail(STO_E_NONFINITE, "readout of item %d: %s", bad, err ? err : "non-finite input");
+    return fail(STO_E_DEVICE, "readout: %s", err ? err : "device error");
+}
 
 sto_status sweep_create(int32_t count, const int64_t* n, int64_t n_in, const sto_params* prm, const double* const* W,
                         const double* const* w_in, const double* const* m0, sto_sweep** out) {

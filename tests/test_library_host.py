@@ -140,3 +140,22 @@ def test_adjoint_rejects_bad_arguments(stx):
                                         None) == stx.STO_E_INVALID
     assert lib.readout_grad_device(None, 0, 10, 3, None, 2, 1e-6, 0, None, None, None, None) == stx.STO_E_INVALID
 
+
+
+def test_readout_batch_rejects_bad_arguments(stx):
+    """Argument errors of the batched readout come back before any device
+    work: no items, NULL arrays, a stride below 3 n, a bad washout."""
+    lib = stx.lib()
+    vp = ctypes.c_void_p
+    one = (vp * 1)(vp(16))
+    n = (ctypes.c_int64 * 1)(4)
+    w = (vp * 1)(vp(16))
+    nmse = np.zeros(1)
+    nm = nmse.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    y = (vp * 1)(vp(16))
+    assert lib.readout_fit_batch_device(0, one, None, 0, 10, n, y, 2, 1e-6, 0, w, nm, None) == stx.STO_E_INVALID
+    assert lib.readout_fit_batch_device(1, None, None, 0, 10, n, y, 2, 1e-6, 0, w, nm, None) == stx.STO_E_INVALID
+    assert lib.readout_fit_batch_device(1, one, None, 0, 10, n, None, 2, 1e-6, 0, w, nm, None) == stx.STO_E_INVALID
+    short = (ctypes.c_int64 * 1)(11)
+    assert lib.readout_fit_batch_device(1, one, short, 0, 10, n, y, 2, 1e-6, 0, w, nm, None) == stx.STO_E_INVALID
+    assert lib.readout_fit_batch_device(1, one, None, 0, 10, n, y, 10, 1e-6, 0, w, nm, None) == stx.STO_E_INVALID
