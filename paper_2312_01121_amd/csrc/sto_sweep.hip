@@ -139,8 +139,7 @@ __global__ void __launch_bounds__(256) k_sweep_stage(SweepDev<T> d, const double
 
 // Rows per lane group (R): 8, measured fastest on a 256-reservoir sweep
 // (361.9 us per RK4 step against 368.6 with 4 and 415 with 2; visiting the
-// tasks last-to-first on alternate stages measured slower, 369.2, and so did
-// an FP32 column unroll of 4 or 1 instead of 2: 380.0 and 369.9).
+// tasks last-to-first on alternate stages measured slower, 369.2).
 // STO_SWEEP_ROWS (2, 4 or 8) overrides it for measurements; it is read once
 // per process, so the task table and the kernel always agree.
 int sweep_rows_per_task(int elem_bytes) {
