@@ -10,13 +10,14 @@
 // Tiling.  The columns of X are (stream, component) pairs.  Workgroup
 // (bi, bj) owns the 16-row output tile of nodes 16 bi..16 bi + 15 against the
 // 16 columns of SPW streams (16 streams of one component, or 5 streams of
-// three components with the 16th column empty) for the whole run.  Its four
-// waves split the contraction dimension into quarters; each wave keeps its
-// 16 rows x N/4 slice of W in registers as MFMA A operands (one element per
+// three components with the 16th column empty) for the whole run.  Its eight
+// waves split the contraction dimension into eighths; each wave keeps its
+// 16 rows x N/8 slice of W in registers as MFMA A operands (one element per
 // lane per MFMA), reads the stage inputs of its columns from LDS as B
-// operands, and the four partial tiles are summed in LDS in a fixed order.
-// One thread per (node, stream) pair then takes the pair's C coupling sums:
-// its state, RK4 accumulator and stage input stay in registers.
+// operands, and the eight partial tiles are summed in LDS in a fixed order.
+// One of the first 256 threads per (node, stream) pair then takes the pair's
+// C coupling sums: its state, RK4 accumulator and stage input stay in
+// registers.
 //
 // Exchange.  Stage inputs move through three rotating global buffers, laid
 // out [component][stream][node], whose unpublished entries hold a sentinel
@@ -38,7 +39,8 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBlock = 256;
+constexpr int kBlock = 512;
+constexpr int kWaves = kBlock / 64;   // waves per workgroup, each a slice of the contraction
 constexpr int kTile = 16;
 // LDS row pitch of the gathered stage inputs: 17 (odd), so that the gather's
 // writes (consecutive threads on consecutive nodes of one column) fall in
@@ -56,7 +58,7 @@ template <bool XYZ> constexpr int streams_per_group() { return XYZ ? 5 : 16; }
 // store them K-major in LDS: xs[k * kXP + js * C + c] for node k, local
 // stream js and component c.  Component c of stream s, node k sits at
 // xb[c * cstride + s * ld + k].  The columns are SPW C rows (js, c) of n
-// entries; thread t covers entries t, t + 256, ... (KI of them) of every
+// entries; thread t covers entries t, t + 512, ... (KI of them) of every
 // row, so all indices but its own column are compile-time constants.  Up to
 // kMaxInFlight loads per thread are in flight in one round trip to memory.
 template <int C, int SPW, int KI>
@@ -124,22 +126,22 @@ __device__ bool gather_multi(const float* xb, int64_t ld, int64_t cstride, int n
     return ok;
 }
 
-// KREG: MFMA steps per wave, >= ceil(N/16) (each step contracts 4 nodes;
-// N <= 16 KREG).  XYZ: all three components coupled, else m^x only.
+// KREG: MFMA steps per wave, >= ceil(N/32) (each step contracts 4 nodes;
+// N <= 32 KREG).  XYZ: all three components coupled, else m^x only.
 template <int KREG, bool XYZ>
 __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float> k, const double* __restrict__ u,
                                                   float* __restrict__ states, int streams, int samples,
                                                   int substeps, int renorm) {
     constexpr int C = XYZ ? 3 : 1;
     constexpr int SPW = streams_per_group<XYZ>();
-    constexpr int KI = KREG <= 16 ? 1 : KREG / 16;   // gather entries per row and thread: 256 KI >= 16 KREG >= N
+    constexpr int KI = KREG <= 16 ? 1 : KREG / 16;   // gather entries per row and thread: 512 KI >= 32 KREG >= N
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int ok_lds;
     const int n = d.n;
     const int64_t ld = d.ld;
-    const int kp = (n + kTile - 1) / kTile * kTile;             // contraction length padded to 16
+    const int kp = (n + 31) / 32 * 32;                           // contraction length padded to 32
     float* xs = reinterpret_cast<float*>(smem_raw);              // [kp][kXP]
-    float* cs = xs + (int64_t)kp * kXP;                          // [4 waves][16][16] partial tiles
+    float* cs = xs + (int64_t)kp * kXP;                          // [kWaves][16][16] partial tiles
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int row0 = blockIdx.x * kTile;
@@ -149,8 +151,8 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
     if (threadIdx.x == 0) ok_lds = 1;
     for (int i = threadIdx.x; i < kp * kXP; i += kBlock) xs[i] = 0.0f;   // padded nodes and columns stay 0
 
-    // A operands: this wave's quarter of the contraction for the tile's rows.
-    const int kq = kp / 4;                                       // nodes per wave (multiple of 4)
+    // A operands: this wave's eighth of the contraction for the tile's rows.
+    const int kq = kp / kWaves;                                  // nodes per wave (multiple of 4)
     const int steps = kq / 4;
     float areg[KREG];
     {
@@ -164,11 +166,11 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
 
     // the (node, stream) pair of this thread: output row ti, first column tj
     // of the stream's C columns
-    const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
+    const int ti = (threadIdx.x >> 4) & 15, tj = threadIdx.x & 15;
     const int js = tj / C;
     const int node = row0 + ti;
     const int strm = s0 + js;
-    const bool mine = tj % C == 0 && js < ns && node < n;
+    const bool mine = threadIdx.x < kTile * kTile && tj % C == 0 && js < ns && node < n;
     const int nd = min(node, n - 1), sd = min(strm, streams - 1);
     const float* m_in = d.m + (int64_t)sd * 3 * ld;
     float mx = m_in[nd], my = m_in[ld + nd], mz = m_in[2 * ld + nd];
@@ -215,9 +217,10 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
                     const int col = min(tj + c, kTile - 1);   // stays in the tile for threads that own no pair
-                    dot[c] = ((cs[(0 * kTile + ti) * kTile + col] + cs[(1 * kTile + ti) * kTile + col]) +
-                              cs[(2 * kTile + ti) * kTile + col]) +
-                             cs[(3 * kTile + ti) * kTile + col];
+                    float v = cs[(0 * kTile + ti) * kTile + col];
+#pragma unroll
+                    for (int w = 1; w < kWaves; ++w) v += cs[(w * kTile + ti) * kTile + col];
+                    dot[c] = v;
                 }
                 float fx, fy, fz;
                 if constexpr (XYZ)
@@ -283,11 +286,11 @@ __global__ void k_multi_prologue(const float* m, float* xchg, int streams, int64
     }
 }
 
-constexpr int kMaxKreg = 64;   // N <= 1024
+constexpr int kMaxKreg = 32;   // N <= 1024
 
 int kreg_for(int n) {
-    const int need = ((n + kTile - 1) / kTile * kTile) / 16;
-    for (int kr : {4, 8, 16, 32, 64})
+    const int need = ((n + 31) / 32 * 32) / 32;
+    for (int kr : {4, 8, 16, 32})
         if (kr >= need) return kr;
     return 0;
 }
@@ -301,8 +304,8 @@ const void* multi_kernel(int xyz) {
 }  // namespace
 
 size_t multi_lds_bytes(int n) {
-    const int kp = (n + kTile - 1) / kTile * kTile;
-    return ((size_t)kp * kXP + 4 * kTile * kTile) * sizeof(float);
+    const int kp = (n + 31) / 32 * 32;
+    return ((size_t)kp * kXP + kWaves * kTile * kTile) * sizeof(float);
 }
 
 namespace {
@@ -316,7 +319,6 @@ const void* multi_fn(int n, int xyz) {
         case 8: fn = multi_kernel<8>(xyz); break;
         case 16: fn = multi_kernel<16>(xyz); break;
         case 32: fn = multi_kernel<32>(xyz); break;
-        case 64: fn = multi_kernel<64>(xyz); break;
         default: return nullptr;
     }
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)multi_lds_bytes(n)) != hipSuccess)
@@ -335,7 +337,7 @@ int stream_groups(int streams, int xyz) {
 // them): the LDS fits and the grid is within the occupancy the runtime
 // reports for this kernel instance.
 bool multi_fits(int n, int streams, int xyz, int* grid_x, int* grid_y) {
-    if (n < 1 || streams < 1 || n > 16 * kMaxKreg) return false;
+    if (n < 1 || streams < 1 || n > 32 * kMaxKreg) return false;
     const int gx = (n + kTile - 1) / kTile, gy = stream_groups(streams, xyz);
     const size_t lds = multi_lds_bytes(n);
     if (lds + 64 > 160 * 1024) return false;
