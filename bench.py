@@ -604,8 +604,7 @@ def main():
                     help="first copy MIB MiB device-to-device with a plain copy kernel (scales HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the workloads here are single-GPU problems "
-              "(multi-GPU sharding is a design note, not part of this build); use --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: every workload here fits one GPU; use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -36,7 +36,7 @@ typedef enum {
     STO_E_NOMEM = -2,        /* device or host allocation failed             */
     STO_E_DEVICE = -3,       /* a HIP call failed                            */
     STO_E_NONFINITE = -4,    /* the state became NaN or infinite             */
-    STO_E_UNSUPPORTED = -5   /* valid request this build does not provide    */
+    STO_E_UNSUPPORTED = -5   /* valid request the library does not provide   */
 } sto_status;
 
 typedef enum { STO_F64 = 0, STO_F32 = 1 } sto_dtype;
