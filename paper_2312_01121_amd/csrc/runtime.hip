@@ -71,7 +71,9 @@ int env_int(const char* name, int dflt) {
 
 namespace sto {
 static Tune& tune_mut() {
-    static Tune t = {env_flag("STO_STREAM_ALTERNATE", 0), env_flag("STO_STREAM_NT", 1), env_int("STO_STREAM_ROWS", 0),
+    // STO_STREAM_NT: 1 non-temporal loads of W, 0 cached loads, unset: by the
+    // size of W (the stream kernel's choice)
+    static Tune t = {env_flag("STO_STREAM_ALTERNATE", 0), env_int("STO_STREAM_NT", -1), env_int("STO_STREAM_ROWS", 0),
                      env_int("STO_STREAM_UNROLL", 0)};
     return t;
 }

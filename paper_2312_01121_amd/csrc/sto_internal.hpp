@@ -86,7 +86,7 @@ struct RunSpec {
 // STO_STREAM_ROWS, STO_STREAM_UNROLL: a compiled variant).
 struct Tune {
     int stream_alternate;    // reverse the row order of the stream kernel on odd stages
-    int stream_nontemporal;  // stream W with non-temporal loads
+    int stream_nontemporal;  // W loads: 1 non-temporal, 0 cached, -1 by the size of W
     int stream_rows;         // rows per wave of the stream kernel (0: default)
     int stream_unroll;       // column-loop unroll of the stream kernel (0: default)
 };

@@ -185,11 +185,23 @@ static void launch_stage_rv(int rows, int unroll, hipStream_t st, const DevState
     launch_stage<T, XYZ, NT, sizeof(T) == 8 ? 2 : 4, 2>(st, d, k, u_s, rec, s, stage, c, renorm, reverse);
 }
 
+// Non-temporal loads of W unless W fits the 256 MB memory-side cache with
+// room to spare for little else: between 96 and 256 MB, cached loads keep
+// much of W there from one stage to the next (N = 5,000 FP64, 200 MB: 126.9
+// against 145.0 us per RK4 step), while smaller matrices (50 MB: 47.2
+// against 43.9) and larger ones (400 MB: 250.3 against 237.4) stream faster
+// with non-temporal loads.
+static bool stream_nt(int64_t w_bytes, int forced) {
+    if (forced >= 0) return forced != 0;
+    return !(w_bytes > (int64_t)96 << 20 && w_bytes <= (int64_t)256 << 20);
+}
+
 template <typename T>
 hipError_t run_stream(const DevState<T>& d, const Coef<T>& k, const RunSpec& r) {
     const Tune& t = tune();
     int rows = 2, unroll = 2;
     stream_shape((int)sizeof(T), d.n, &rows, &unroll);
+    const bool nt = stream_nt((int64_t)d.n * d.ld * (int64_t)sizeof(T), t.stream_nontemporal);
     T* states = static_cast<T*>(r.states);
     int cur = r.cur;
     int64_t sigma = 0;
@@ -202,10 +214,10 @@ hipError_t run_stream(const DevState<T>& d, const Coef<T>& k, const RunSpec& r) 
                 const int c = cur ^ (stage & 1);
                 const int rev = t.stream_alternate ? (int)(sigma & 1) : 0;
                 if (r.xyz) {
-                    if (t.stream_nontemporal) launch_stage_rv<T, true, true>(rows, unroll, r.stream, d, k, u_s, rec, s, stage, c, r.renorm, rev);
+                    if (nt) launch_stage_rv<T, true, true>(rows, unroll, r.stream, d, k, u_s, rec, s, stage, c, r.renorm, rev);
                     else launch_stage_rv<T, true, false>(rows, unroll, r.stream, d, k, u_s, rec, s, stage, c, r.renorm, rev);
                 } else {
-                    if (t.stream_nontemporal) launch_stage_rv<T, false, true>(rows, unroll, r.stream, d, k, u_s, rec, s, stage, c, r.renorm, rev);
+                    if (nt) launch_stage_rv<T, false, true>(rows, unroll, r.stream, d, k, u_s, rec, s, stage, c, r.renorm, rev);
                     else launch_stage_rv<T, false, false>(rows, unroll, r.stream, d, k, u_s, rec, s, stage, c, r.renorm, rev);
                 }
             }

@@ -195,6 +195,31 @@ def test_steps_validation_and_noop(stx):
         assert np.array_equal(r.get_state(), m0)
 
 
+@pytest.mark.parametrize("n,dtype", [(4000, "f64"), (5800, "f32")])
+def test_stream_cached_loads_match_oracle(stx, n, dtype):
+    """The stream kernel reads W with cached loads when it fits the
+    memory-side cache (96 to 256 MB: 128 MB FP64 at N = 4,000, 135 MB FP32
+    at N = 5,800); records against the oracle over 8 RK4 steps (FP64) or
+    one step from FP32-representable inputs."""
+    w, w_in, m0, u = random_case(n, seed=n, samples=2)
+    f32 = lambda x: np.asarray(x, dtype=np.float32).astype(np.float64)  # noqa: E731
+    say("stream cached loads", n, dtype)
+    if dtype == "f64":
+        prm = oracle_params(a_cp=0.3, substeps=4)
+        rec_o, _ = sto.run(w, w_in, m0, u, prm)
+        tol = F64_TOL
+    else:
+        prm = oracle_params(a_cp=0.3, substeps=1)
+        u = u[:1]
+        rec_o, _ = sto.run(f32(w), f32(w_in), f32(m0), u, prm)
+        tol = F32_TOL
+    with make(stx, w, w_in, m0, prm, dtype=dtype, path="stream") as r:
+        rec = r.run(u)
+    d = maxdiff(rec, rec_o)
+    say("  max diff", d)
+    assert d <= tol
+
+
 # ---------------------------------------------------------------------------
 # The largest size of each path and the first size past it
 # ---------------------------------------------------------------------------
