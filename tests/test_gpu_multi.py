@@ -70,6 +70,31 @@ def test_multi_one_step_matches_oracle(stx, n, streams, coupling):
     assert worst <= F32_TOL
 
 
+@pytest.mark.parametrize("path", ["multi", "batch"])
+@pytest.mark.parametrize("coupling", ["x", "xyz"])
+def test_streams_renormalize_and_several_inputs(stx, path, coupling):
+    """Renormalisation after every step and three inputs per stream, over
+    two samples of 4 RK4 steps, per stream against the oracle on the same
+    FP32-representable inputs."""
+    n, S, n_in = 100, 7, 3
+    w, w_in, m0, _ = random_case(n, n_in=n_in, seed=11, samples=1)
+    u = np.random.default_rng(12).uniform(-1, 1, (2, S, n_in))
+    prm = oracle_params(a_cp=0.3, substeps=4, coupling=coupling, renormalize=True)
+    m0s = distinct_states(np.random.default_rng(13), S, n)
+    say("streams renorm + inputs", path, coupling)
+    with stx.Reservoir(w, w_in, m0s, lib_params(prm, dtype="f32", path=path), streams=S) as r:
+        assert r.path == path
+        rec = r.run(u)
+    worst = 0.0
+    for s in range(S):
+        rec_o, _ = sto.run(f32(w), f32(w_in), f32(m0s[s]), u[:, s], prm)
+        worst = max(worst, float(np.max(np.abs(rec[:, s] - rec_o))))
+        # renormalised records have unit norm to FP32 rounding
+        assert float(np.max(np.abs(np.linalg.norm(rec[:, s], axis=-1) - 1.0))) <= 1e-6
+    say("  max diff", worst)
+    assert worst <= F32_TOL
+
+
 @pytest.mark.parametrize("coupling", ["x", "xyz"])
 def test_multi_streams64_lyapunov_horizon(stx, coupling):
     """The 64-stream, 512-node workload over ~one Lyapunov time (8 samples =
