@@ -319,7 +319,7 @@ sto_status readout_fit_device(const void *states_dev, int32_t dtype, int64_t T, 
  * multi-stream reservoir.  Item q is
  * fitted exactly as readout_fit_device fits one record set; the kernels
  * cover all items at once, so the launch count does not grow with `count`.
- *   count       number of record sets, >= 1
+ *   count       number of record sets, 1 ... 65535
  *   states_dev  host array of `count` device pointers: record t of item q
  *               (n[q] x 3 elements of dtype, AoS) starts at element
  *               t * row_stride[q] of states_dev[q]

@@ -269,17 +269,33 @@ __global__ void k_bsolve(const RItem* __restrict__ items, const double* __restri
     }
 }
 
+// Residuals y - Phi w of every fitted row, one wave per row (its columns
+// read along the row, the products summed by a butterfly in a fixed order).
+__global__ void __launch_bounds__(256) k_bresid(const RItem* __restrict__ items, int rows,
+                                                const double* __restrict__ phi_base, double* __restrict__ res_base,
+                                                const int* bad) {
+    const int q = blockIdx.y;
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= rows || (bad[2 * q] | bad[2 * q + 1])) return;   // wave-uniform
+    const RItem it = items[q];
+    const double* row = phi_base + it.phi + (int64_t)r * it.cols;
+    double p = 0.0;
+    for (int j = lane; j < it.cols; j += 64) p = __builtin_fma(row[j], it.w[j], p);
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) p += __shfl_xor(p, m, 64);
+    if (lane == 0) res_base[(int64_t)q * rows + r] = it.y[r] - p;
+}
+
 // sums[2 q] = sum of squared residuals, sums[2 q + 1] = sum of (y - mean y)^2.
 __global__ void __launch_bounds__(1024) k_bnmse(const RItem* __restrict__ items, int rows,
-                                                const double* __restrict__ phi_base, double* sums, const int* bad) {
+                                                const double* __restrict__ res_base, double* sums, const int* bad) {
     __shared__ double red[1024];
     const int q = blockIdx.x;
     const RItem it = items[q];
-    const double* y = it.y;
     if (bad[2 * q] | bad[2 * q + 1]) return;   // block-uniform
-    const double* phi = phi_base + it.phi;
-    const double* w = it.w;
-    const int cols = it.cols;
+    const double* y = it.y;
+    const double* res = res_base + (int64_t)q * rows;
     auto block_sum = [&](double v) {
         red[threadIdx.x] = v;
         __syncthreads();
@@ -296,9 +312,7 @@ __global__ void __launch_bounds__(1024) k_bnmse(const RItem* __restrict__ items,
     const double ybar = block_sum(s) / rows;
     double rr = 0.0, dd = 0.0;
     for (int r = threadIdx.x; r < rows; r += blockDim.x) {
-        double p = 0.0;
-        for (int j = 0; j < cols; ++j) p = __builtin_fma(phi[(int64_t)r * cols + j], w[j], p);
-        const double e = y[r] - p;
+        const double e = res[r];
         const double d = y[r] - ybar;
         rr += e * e;
         dd += d * d;
@@ -358,7 +372,7 @@ int readout_solve_batch(int count, const void* const* rec, const int64_t* stride
 
     RItem* items_d = nullptr;
     int64_t *gstart_d = nullptr, *ustart_d = nullptr;
-    double *phi = nullptr, *C = nullptr, *rhs = nullptr, *sums = nullptr;
+    double *phi = nullptr, *C = nullptr, *rhs = nullptr, *res = nullptr, *sums = nullptr;
     int* bad = nullptr;
     int rc = 0;
     auto check = [&](hipError_t e) {
@@ -373,7 +387,8 @@ int readout_solve_batch(int count, const void* const* rec, const int64_t* stride
     if (check(hipMalloc(&items_d, sizeof(RItem) * count)) && check(hipMalloc(&gstart_d, 8 * gstart.size())) &&
         check(hipMalloc(&ustart_d, 8 * std::max<size_t>(1, ustart.size()))) &&
         check(hipMalloc(&phi, (size_t)phi_total * 8)) && check(hipMalloc(&C, (size_t)c_total * 8)) &&
-        check(hipMalloc(&rhs, (size_t)rhs_total * 8)) && check(hipMalloc(&sums, (size_t)count * 16)) &&
+        check(hipMalloc(&rhs, (size_t)rhs_total * 8)) && check(hipMalloc(&res, (size_t)count * rows * 8)) &&
+        check(hipMalloc(&sums, (size_t)count * 16)) &&
         check(hipMalloc(&bad, (size_t)count * 2 * sizeof(int))) &&
         check(hipMemcpyAsync(items_d, items.data(), sizeof(RItem) * count, hipMemcpyHostToDevice, stream)) &&
         check(hipMemcpyAsync(gstart_d, gstart.data(), 8 * gstart.size(), hipMemcpyHostToDevice, stream)) &&
@@ -399,7 +414,8 @@ int readout_solve_batch(int count, const void* const* rec, const int64_t* stride
         hipLaunchKernelGGL(k_bsolve, dim3(count), dim3(1024), 0, stream, items_d, C, rhs, bad);
         hipLaunchKernelGGL(k_bvec, dim3((max_cols + 255) / 256, count), dim3(256), 0, stream, items_d, rows, phi, rhs,
                            1, bad);
-        hipLaunchKernelGGL(k_bnmse, dim3(count), dim3(1024), 0, stream, items_d, rows, phi, sums, bad);
+        hipLaunchKernelGGL(k_bresid, dim3((rows + 3) / 4, count), dim3(256), 0, stream, items_d, rows, phi, res, bad);
+        hipLaunchKernelGGL(k_bnmse, dim3(count), dim3(1024), 0, stream, items_d, rows, res, sums, bad);
         check(hipGetLastError());
         check(hipMemcpyAsync(hbad.data(), bad, (size_t)count * 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
         check(hipMemcpyAsync(hsums.data(), sums, (size_t)count * 16, hipMemcpyDeviceToHost, stream));
@@ -420,8 +436,8 @@ int readout_solve_batch(int count, const void* const* rec, const int64_t* stride
         if (rc == 0)
             for (int q = 0; q < count; ++q) nmse_host[q] = hsums[2 * q] / hsums[2 * q + 1];
     }
-    for (void* p : {(void*)items_d, (void*)gstart_d, (void*)ustart_d, (void*)phi, (void*)C, (void*)rhs, (void*)sums,
-                    (void*)bad})
+    for (void* p : {(void*)items_d, (void*)gstart_d, (void*)ustart_d, (void*)phi, (void*)C, (void*)rhs, (void*)res,
+                    (void*)sums, (void*)bad})
         if (p) (void)hipFree(p);
     return rc;
 }

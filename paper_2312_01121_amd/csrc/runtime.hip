@@ -915,6 +915,7 @@ sto_status readout_fit_batch_device(int32_t count, const void* const* states_dev
                                     void* hip_stream) {
     if (count < 1 || !states_dev || !n || !y_dev || !w_out_dev || !nmse_out)
         return fail(STO_E_INVALID, "count >= 1 and non-NULL arguments");
+    if (count > 65535) return fail(STO_E_INVALID, "at most 65535 record sets per call");
     if (dtype != STO_F64 && dtype != STO_F32) return fail(STO_E_INVALID, "unknown dtype %d", dtype);
     const size_t elem = dtype == STO_F64 ? 8 : 4;
     std::vector<const void*> rec(count);

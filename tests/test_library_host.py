@@ -159,3 +159,4 @@ def test_readout_batch_rejects_bad_arguments(stx):
     short = (ctypes.c_int64 * 1)(11)
     assert lib.readout_fit_batch_device(1, one, short, 0, 10, n, y, 2, 1e-6, 0, w, nm, None) == stx.STO_E_INVALID
     assert lib.readout_fit_batch_device(1, one, None, 0, 10, n, y, 10, 1e-6, 0, w, nm, None) == stx.STO_E_INVALID
+    assert lib.readout_fit_batch_device(65536, one, None, 0, 10, n, y, 2, 1e-6, 0, w, nm, None) == stx.STO_E_INVALID
