@@ -39,6 +39,7 @@
 
 #include "sto_adjoint.hpp"
 #include "sto_adjoint_dev.hpp"
+#include "sto_multi.hpp"
 
 namespace sto {
 
@@ -586,10 +587,52 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
             launch_batch_rev(d, k, kk, stage, XYZ, st);
         }
     };
+    // S streams in FP32 with segments of whole samples: the forward runs on
+    // the persistent multi-stream kernel (the arithmetic of the plain
+    // multi-stream run), one cooperative launch per segment, writing the
+    // stage trace where the reverse needs it
+    bool use_multi = false;
+    float* xchg = nullptr;
+    int* msync = nullptr;
+    if constexpr (sizeof(T) == 4) {
+        use_multi = NS > 1 && K % a.substeps == 0 && multi_fits(n, NS, XYZ, nullptr, nullptr) &&
+                    multi_segment_fits(n, NS, XYZ);
+        if (use_multi) {
+            ADJ_TRY(mem.get(&xchg, (size_t)3 * C * NS * ld * sizeof(float)));
+            ADJ_TRY(mem.get(&msync, 256));
+        }
+    }
     // forward over local steps [0, kn) of the segment starting at j0; the
     // state is in m and ms[0] (cur = 0 between steps)
     auto forward = [&](int64_t j0, int64_t kn, int trace) -> hipError_t {
         d.j0 = j0;
+        if constexpr (sizeof(T) == 4) {
+            if (use_multi) {
+                DevState<float> ds{};
+                ds.W = a.W;
+                ds.w_in = a.w_in;
+                ds.m = d.m;
+                ds.xchg = xchg;
+                ds.bad = a.bad;
+                ds.sync = msync;
+                ds.n = n;
+                ds.n_in = a.n_in;
+                ds.ld = ld;
+                RunSpec rs{};
+                rs.u = a.u + (j0 / a.substeps) * NS * a.n_in;
+                rs.states = nullptr;
+                rs.samples = (int)(kn / a.substeps);
+                rs.substeps = a.substeps;
+                rs.cur = 0;
+                rs.renorm = a.renorm;
+                rs.xyz = XYZ;
+                rs.stream = st;
+                const MultiTrace tr{trace ? d.xt : nullptr, d.wx, d.pn};
+                ADJ_TRY(run_multi_segment(ds, k, rs, NS, (int)(j0 / a.substeps), tr));
+                ADJ_TRY(hipMemcpyAsync(d.ms[0], d.m, vec, hipMemcpyDeviceToDevice, st));
+                return hipGetLastError();
+            }
+        }
         for (int64_t kk = 0; kk < kn; ++kk)
             for (int stage = 0; stage < 4; ++stage) fwd_stage((int)kk, stage, trace);
         return hipGetLastError();

@@ -32,6 +32,7 @@
 #include <climits>
 
 #include "sto_internal.hpp"
+#include "sto_multi.hpp"
 
 namespace sto {
 
@@ -127,11 +128,13 @@ __device__ bool gather_multi(const float* xb, int64_t ld, int64_t cstride, int n
 }
 
 // KREG: MFMA steps per wave, >= ceil(N/32) (each step contracts 4 nodes;
-// N <= 32 KREG).  XYZ: all three components coupled, else m^x only.
-template <int KREG, bool XYZ>
+// N <= 32 KREG).  XYZ: all three components coupled, else m^x only.  TRACE:
+// write the stage trace of the adjoint (tr); sample0 offsets the sample
+// index reported on a non-finite state.
+template <int KREG, bool XYZ, bool TRACE>
 __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float> k, const double* __restrict__ u,
                                                   float* __restrict__ states, int streams, int samples,
-                                                  int substeps, int renorm) {
+                                                  int substeps, int renorm, int sample0, MultiTrace tr) {
     constexpr int C = XYZ ? 3 : 1;
     constexpr int SPW = streams_per_group<XYZ>();
     constexpr int KI = KREG <= 16 ? 1 : KREG / 16;   // gather entries per row and thread: 512 KI >= 32 KREG >= N
@@ -222,6 +225,18 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
                     for (int w = 1; w < kWaves; ++w) v += cs[(w * kTile + ti) * kTile + col];
                     dot[c] = v;
                 }
+                if constexpr (TRACE) {
+                    if (mine) {
+                        const int64_t slot = ((int64_t)(s * substeps + sub) * 4 + stage) * streams + strm;
+                        float* x = tr.xt + slot * 3 * ld;
+                        x[node] = sx;
+                        x[ld + node] = sy;
+                        x[2 * ld + node] = sz;
+                        float* w = tr.wx + slot * C * ld;
+#pragma unroll
+                        for (int c = 0; c < C; ++c) w[c * ld + node] = dot[c];
+                    }
+                }
                 float fx, fy, fz;
                 if constexpr (XYZ)
                     llg_rhs<float, true>(k, sx, sy, sz, k.a_cp * dot[0], k.a_cp * dot[1], k.a_cp * dot[2], hin, fx,
@@ -232,7 +247,16 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
                 float ny = rk4_update(k, stage, my, ay, fy);
                 float nz = rk4_update(k, stage, mz, az, fz);
                 if (stage == 3) {
-                    if (renorm) renormalize(nx, ny, nz);
+                    if (renorm) {
+                        if constexpr (TRACE) {
+                            if (mine) {
+                                const double ex = nx, ey = ny, ez = nz;
+                                tr.pn[((int64_t)(s * substeps + sub) * streams + strm) * ld + node] =
+                                    (float)__builtin_sqrt((ex * ex + ey * ey) + ez * ez);
+                            }
+                        }
+                        renormalize(nx, ny, nz);
+                    }
                     mx = nx;
                     my = ny;
                     mz = nz;
@@ -259,7 +283,7 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
                 rec[1] = my;
                 rec[2] = mz;
             }
-            if (!finite3(mx, my, mz)) atomicMin(d.bad, s);
+            if (!finite3(mx, my, mz)) atomicMin(d.bad, sample0 + s);
         }
     }
     if (mine) {
@@ -296,9 +320,12 @@ int kreg_for(int n) {
 }
 
 template <int KREG>
-const void* multi_kernel(int xyz) {
-    return xyz ? reinterpret_cast<const void*>(&k_multi<KREG, true>)
-               : reinterpret_cast<const void*>(&k_multi<KREG, false>);
+const void* multi_kernel(int xyz, int trace) {
+    if (trace)
+        return xyz ? reinterpret_cast<const void*>(&k_multi<KREG, true, true>)
+                   : reinterpret_cast<const void*>(&k_multi<KREG, false, true>);
+    return xyz ? reinterpret_cast<const void*>(&k_multi<KREG, true, false>)
+               : reinterpret_cast<const void*>(&k_multi<KREG, false, false>);
 }
 
 }  // namespace
@@ -312,13 +339,13 @@ namespace {
 
 // The kernel instance for n nodes, with its dynamic LDS limit raised to what
 // it needs; nullptr when n is out of range.
-const void* multi_fn(int n, int xyz) {
+const void* multi_fn(int n, int xyz, int trace = 0) {
     const void* fn = nullptr;
     switch (kreg_for(n)) {
-        case 4: fn = multi_kernel<4>(xyz); break;
-        case 8: fn = multi_kernel<8>(xyz); break;
-        case 16: fn = multi_kernel<16>(xyz); break;
-        case 32: fn = multi_kernel<32>(xyz); break;
+        case 4: fn = multi_kernel<4>(xyz, trace); break;
+        case 8: fn = multi_kernel<8>(xyz, trace); break;
+        case 16: fn = multi_kernel<16>(xyz, trace); break;
+        case 32: fn = multi_kernel<32>(xyz, trace); break;
         default: return nullptr;
     }
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)multi_lds_bytes(n)) != hipSuccess)
@@ -333,15 +360,17 @@ int stream_groups(int streams, int xyz) {
 
 }  // namespace
 
+namespace {
+
 // Whether every tile can be co-resident (the cooperative launch needs all of
 // them): the LDS fits and the grid is within the occupancy the runtime
 // reports for this kernel instance.
-bool multi_fits(int n, int streams, int xyz, int* grid_x, int* grid_y) {
+bool fits(int n, int streams, int xyz, int trace, int* grid_x, int* grid_y) {
     if (n < 1 || streams < 1 || n > 32 * kMaxKreg) return false;
     const int gx = (n + kTile - 1) / kTile, gy = stream_groups(streams, xyz);
     const size_t lds = multi_lds_bytes(n);
     if (lds + 64 > 160 * 1024) return false;
-    const void* fn = multi_fn(n, xyz);
+    const void* fn = multi_fn(n, xyz, trace);
     if (!fn) return false;
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return false;
@@ -353,9 +382,10 @@ bool multi_fits(int n, int streams, int xyz, int* grid_x, int* grid_y) {
     return true;
 }
 
-hipError_t run_multi(const DevState<float>& d, const Coef<float>& k, const RunSpec& r, int streams) {
+hipError_t launch_multi(const DevState<float>& d, const Coef<float>& k, const RunSpec& r, int streams, int sample0,
+                        const MultiTrace& tr) {
     int gx = 0, gy = 0;
-    if (!multi_fits(d.n, streams, r.xyz, &gx, &gy)) return hipErrorInvalidValue;
+    if (!fits(d.n, streams, r.xyz, tr.xt != nullptr, &gx, &gy)) return hipErrorInvalidValue;
     const size_t lds = multi_lds_bytes(d.n);
     hipError_t e = hipMemsetAsync(d.sync, 0, 256, r.stream);
     if (e != hipSuccess) return e;
@@ -367,13 +397,31 @@ hipError_t run_multi(const DevState<float>& d, const Coef<float>& k, const RunSp
     Coef<float> kk = k;
     const double* u = r.u;
     float* states = static_cast<float*>(r.states);
-    int st = streams, samples = r.samples, substeps = r.substeps, renorm = r.renorm;
-    void* args[] = {&dd, &kk, &u, &states, &st, &samples, &substeps, &renorm};
-    const void* fn = multi_fn(d.n, r.xyz);
+    int st = streams, samples = r.samples, substeps = r.substeps, renorm = r.renorm, s0 = sample0;
+    MultiTrace t = tr;
+    void* args[] = {&dd, &kk, &u, &states, &st, &samples, &substeps, &renorm, &s0, &t};
+    const void* fn = multi_fn(d.n, r.xyz, tr.xt != nullptr);
     if (!fn) return hipErrorInvalidValue;
     e = hipLaunchCooperativeKernel(fn, dim3(gx, gy), dim3(kBlock), args, (unsigned)lds, r.stream);
     if (e != hipSuccess) return e;
     return hipGetLastError();
+}
+
+}  // namespace
+
+bool multi_fits(int n, int streams, int xyz, int* grid_x, int* grid_y) {
+    return fits(n, streams, xyz, 0, grid_x, grid_y);
+}
+
+bool multi_segment_fits(int n, int streams, int xyz) { return fits(n, streams, xyz, 1, nullptr, nullptr); }
+
+hipError_t run_multi(const DevState<float>& d, const Coef<float>& k, const RunSpec& r, int streams) {
+    return launch_multi(d, k, r, streams, 0, MultiTrace{nullptr, nullptr, nullptr});
+}
+
+hipError_t run_multi_segment(const DevState<float>& d, const Coef<float>& k, const RunSpec& r, int streams,
+                             int sample0, const MultiTrace& tr) {
+    return launch_multi(d, k, r, streams, sample0, tr);
 }
 
 }  // namespace sto

@@ -253,18 +253,21 @@ def unit_states(rng, streams, n, spread=0.3):
     return v / np.linalg.norm(v, axis=2, keepdims=True)
 
 
-@pytest.mark.parametrize("coupling,seg", [("x", 0), ("xyz", 3)])
-def test_adjoint_streams_matches_oracle(stx, coupling, seg):
+# Segments of whole samples (0: the whole run, 4, 8) run the forward on the
+# persistent multi-stream kernel; a 3-step segment on the per-stage kernels.
+@pytest.mark.parametrize("coupling,seg,renorm", [("x", 0, False), ("xyz", 3, False), ("xyz", 4, False),
+                                                 ("x", 8, False), ("xyz", 4, True), ("x", 3, True)])
+def test_adjoint_streams_matches_oracle(stx, coupling, seg, renorm):
     n, S, samples, sub = 40, 3, 3, 4
     w, w_in, _, _ = random_case(n, seed=21, samples=1, spread=0.3)
     rng = np.random.default_rng(22)
     m0s = unit_states(rng, S, n)
     u = rng.uniform(-1, 1, (samples, S, 1))
-    prm = oracle_params(a_cp=0.3, a_in=0.7, substeps=sub, coupling=coupling)
+    prm = oracle_params(a_cp=0.3, a_in=0.7, substeps=sub, coupling=coupling, renormalize=renorm)
     g_rec = np.float32(rng.standard_normal((samples, S, n, 3))).astype(np.float64)
     g_fin = np.float32(rng.standard_normal((S, n, 3))).astype(np.float64)
     w, w_in = (np.float32(a).astype(np.float64) for a in (w, w_in))
-    say(f"adjoint streams S={S} n={n} {coupling} seg={seg}")
+    say(f"adjoint streams S={S} n={n} {coupling} seg={seg} renorm={renorm}")
     ref = oracle_streams_adjoint(w, w_in, np.float32(m0s).astype(np.float64), u, prm, g_rec, g_fin)
     with stx.Reservoir(w, w_in, m0s, lib_params(prm, "f32"), streams=S) as r:
         got = r.adjoint(m0s, u, g_rec, g_fin, checkpoint_every=seg)
