@@ -203,7 +203,9 @@ __global__ void __launch_bounds__(256) k_adj_prep(AdjDev<T> d, Coef<T> k, int kk
     const int64_t ld = d.ld;
     const int64_t sb = (int64_t)s * 3 * ld;
     const T pn = d.renorm ? d.pn[((int64_t)kk * d.S + s) * ld + i] : T(1);
-    prep_step<T, XYZ>(d, k, i, s, kk, d.m + sb, pn, d.mbar[sb + i], d.mbar[sb + ld + i], d.mbar[sb + 2 * ld + i]);
+    GlobalSink sink;
+    prep_step<T, XYZ>(d, k, i, s, kk, d.m + sb, pn, d.mbar[sb + i], d.mbar[sb + ld + i], d.mbar[sb + 2 * ld + i],
+                      sink);
 }
 
 // ---------------------------------------------------------------------------
@@ -440,6 +442,12 @@ int env_int(const char* name, int dflt) {
     return v ? atoi(v) : dflt;
 }
 
+// sticky |= the abort word of the last persistent launch (whose own word
+// is cleared at the start of every launch).
+__global__ void k_keep_abort(const int* word, int* sticky) {
+    if (threadIdx.x == 0 && *word) *sticky = 1;
+}
+
 template <typename T>
 void adj_shape(int n, int* rows, int* unroll) {
     static const int r = env_int("STO_ADJ_ROWS", 0), u = env_int("STO_ADJ_UNROLL", 0);
@@ -591,17 +599,26 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
     // the persistent multi-stream kernel (the arithmetic of the plain
     // multi-stream run), one cooperative launch per segment, writing the
     // stage trace where the reverse needs it
-    bool use_multi = false;
+    // The reversed stages of a segment run the same way (k_multi_rev) when
+    // that kernel is co-resident too; STO_MULTI_REVERSE=0 keeps them on the
+    // per-stage kernels, for measurements.
+    bool use_multi = false, use_multi_rev = false;
     float* xchg = nullptr;
-    int* msync = nullptr;
+    int* msync = nullptr;   // [0, 64): the launches' words; [64]: sticky abort
     if constexpr (sizeof(T) == 4) {
         use_multi = NS > 1 && K % a.substeps == 0 && multi_fits(n, NS, XYZ, nullptr, nullptr) &&
                     multi_segment_fits(n, NS, XYZ);
+        use_multi_rev = use_multi && env_int("STO_MULTI_REVERSE", 1) != 0 && multi_reverse_fits(n, NS, XYZ, a.n_in);
         if (use_multi) {
             ADJ_TRY(mem.get(&xchg, (size_t)3 * C * NS * ld * sizeof(float)));
-            ADJ_TRY(mem.get(&msync, 256));
+            ADJ_TRY(mem.get(&msync, 512));
+            ADJ_TRY(hipMemsetAsync(msync, 0, 512, st));
         }
     }
+    auto keep_abort = [&]() -> hipError_t {
+        hipLaunchKernelGGL(k_keep_abort, dim3(1), dim3(64), 0, st, msync + kSyncAbortWord, msync + 64);
+        return hipGetLastError();
+    };
     // forward over local steps [0, kn) of the segment starting at j0; the
     // state is in m and ms[0] (cur = 0 between steps)
     auto forward = [&](int64_t j0, int64_t kn, int trace) -> hipError_t {
@@ -629,6 +646,7 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
                 rs.stream = st;
                 const MultiTrace tr{trace ? d.xt : nullptr, d.wx, d.pn};
                 ADJ_TRY(run_multi_segment(ds, k, rs, NS, (int)(j0 / a.substeps), tr));
+                ADJ_TRY(keep_abort());
                 ADJ_TRY(hipMemcpyAsync(d.ms[0], d.m, vec, hipMemcpyDeviceToDevice, st));
                 return hipGetLastError();
             }
@@ -657,8 +675,18 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
         }
         d.j0 = j0;
         hipLaunchKernelGGL((k_adj_prep<T, XYZ>), pgrid, pblock, 0, st, d, k, (int)(kn - 1));
-        for (int64_t kk = kn - 1; kk >= 0; --kk)
-            for (int stage = 3; stage >= 0; --stage) rev_stage((int)kk, stage);
+        bool reversed = false;
+        if constexpr (sizeof(T) == 4) {
+            if (use_multi_rev) {
+                ADJ_TRY(hipGetLastError());
+                ADJ_TRY(run_multi_reverse(d, k, (int)kn, XYZ, xchg, msync, st));
+                ADJ_TRY(keep_abort());
+                reversed = true;
+            }
+        }
+        if (!reversed)
+            for (int64_t kk = kn - 1; kk >= 0; --kk)
+                for (int stage = 3; stage >= 0; --stage) rev_stage((int)kk, stage);
         ADJ_TRY(hipGetLastError());
         if (a.g_W) {
             // rows of the panels: (step, stage, stream, component), pitch ld
@@ -704,7 +732,11 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
         ADJ_TRY(hipGetLastError());
     }
     // the workspace is freed on return: wait for the work that uses it
-    return hipStreamSynchronize(st);
+    int aborted = 0;
+    if (msync) ADJ_TRY(hipMemcpyAsync(&aborted, msync + 64, sizeof(int), hipMemcpyDeviceToHost, st));
+    ADJ_TRY(hipStreamSynchronize(st));
+    // a persistent launch whose exchange timed out left its results incomplete
+    return aborted ? hipErrorLaunchTimeOut : hipSuccess;
 }
 
 }  // namespace

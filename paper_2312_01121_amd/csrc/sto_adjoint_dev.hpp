@@ -128,12 +128,29 @@ __device__ __forceinline__ VjpIn<T> vjp_load(const AdjDev<T>& d, int i, int s, i
     return in;
 }
 
+// Where the pointwise adjoint of a stage leaves the node's parameter
+// partials (d/da_cp, d/da_in, d/dh_s, d/dh_appl and A_in b_x, the factor of
+// dL/dw_in against the input u_s): added to gacc / gwin at once.
+struct GlobalSink {
+    template <typename T, typename V>
+    __device__ __forceinline__ void add(const AdjDev<T>& d, int64_t gi, double pcp, double pin, double phs,
+                                        double pap, double ab, const double* u_s, V, V, V) {
+        const int64_t gs = (int64_t)d.S * d.ld;
+        d.gacc[gi] += pcp;
+        d.gacc[gs + gi] += pin;
+        d.gacc[2 * gs + gi] += phs;
+        d.gacc[3 * gs + gi] += pap;
+        for (int q = 0; q < d.n_in; ++q) d.gwin[q * gs + gi] += ab * u_s[q];
+    }
+};
+
 // Pointwise adjoint of stage `stage` of local step kk at node i of stream s,
-// applied to v: stores the pointwise part of xbar (loc), the coupling
-// adjoint (st) and adds the node's parameter partials.
-template <typename T, bool XYZ>
+// applied to v: stores the pointwise part of xbar (loc) and the coupling
+// adjoint (st), and hands the node's parameter partials and the coupling
+// adjoint to the sink.
+template <typename T, bool XYZ, class Sink>
 __device__ __forceinline__ void vjp_apply(const AdjDev<T>& d, const Coef<T>& k, int i, int s, int kk, int stage,
-                                          const VjpIn<T>& in, T vx, T vy, T vz) {
+                                          const VjpIn<T>& in, T vx, T vy, T vz, Sink& sink) {
     constexpr int C = XYZ ? 3 : 1;
     const int64_t ld = d.ld;
     const int S = d.S;
@@ -153,18 +170,14 @@ __device__ __forceinline__ void vjp_apply(const AdjDev<T>& d, const Coef<T>& k, 
     }
     double pcp = (double)bx * (double)in.wxx;
     if (XYZ) pcp += (double)by * (double)in.wxy + (double)bz * (double)in.wxz;
-    const int64_t gs = (int64_t)S * ld, gi = (int64_t)s * ld + i;
-    d.gacc[gi] += pcp;
-    d.gacc[gs + gi] += (double)bx * (double)in.raw;
-    d.gacc[2 * gs + gi] += (double)hsp;
-    d.gacc[3 * gs + gi] += (double)bz;
-    for (int q = 0; q < d.n_in; ++q) d.gwin[q * gs + gi] += (double)k.a_in * (double)bx * in.u_s[q];
+    sink.add(d, (int64_t)s * ld + i, pcp, (double)bx * (double)in.raw, (double)hsp, (double)bz,
+             (double)k.a_in * (double)bx, in.u_s, bx, by, bz);
 }
 
-template <typename T, bool XYZ>
+template <typename T, bool XYZ, class Sink>
 __device__ __forceinline__ void stage_vjp(const AdjDev<T>& d, const Coef<T>& k, int i, int s, int kk, int stage,
-                                          T vx, T vy, T vz) {
-    vjp_apply<T, XYZ>(d, k, i, s, kk, stage, vjp_load<T, XYZ>(d, i, s, kk, stage), vx, vy, vz);
+                                          T vx, T vy, T vz, Sink& sink) {
+    vjp_apply<T, XYZ>(d, k, i, s, kk, stage, vjp_load<T, XYZ>(d, i, s, kk, stage), vx, vy, vz, sink);
 }
 
 // Start reversing local step kk (global step j = j0 + kk) of stream s:
@@ -172,9 +185,9 @@ __device__ __forceinline__ void stage_vjp(const AdjDev<T>& d, const Coef<T>& k, 
 // through the optional projection; then the pointwise adjoint of its last
 // stage.  mhat: the state m_{j+1} (after projection) of stream s, [3][ld];
 // pn: the norm of m_{j+1} before projection.
-template <typename T, bool XYZ>
+template <typename T, bool XYZ, class Sink>
 __device__ __forceinline__ void prep_step(const AdjDev<T>& d, const Coef<T>& k, int i, int s, int kk, const T* mhat,
-                                          T pn, T cx, T cy, T cz) {
+                                          T pn, T cx, T cy, T cz, Sink& sink) {
     const int64_t ld = d.ld;
     const int64_t jn = d.j0 + kk + 1;   // index of the state this step produces
     T a[3] = {cx, cy, cz};
@@ -202,7 +215,7 @@ __device__ __forceinline__ void prep_step(const AdjDev<T>& d, const Coef<T>& k, 
         d.abar[sb + c * ld + i] = a[c];
         d.mbar[sb + c * ld + i] = a[c];
     }
-    stage_vjp<T, XYZ>(d, k, i, s, kk, 3, k.h6 * a[0], k.h6 * a[1], k.h6 * a[2]);
+    stage_vjp<T, XYZ>(d, k, i, s, kk, 3, k.h6 * a[0], k.h6 * a[1], k.h6 * a[2], sink);
 }
 
 // Inputs of a forward stage's epilogue at node i of stream s (stage input,
@@ -334,9 +347,9 @@ __device__ __forceinline__ RevIn<T> rev_load(const AdjDev<T>& d, int i, int s, i
 // t = (W^T bbar) of the stage: xbar = loc + a_cp t along the coupled
 // components, dL/dm += xbar, then the pointwise adjoint of the next stage to
 // reverse (or, after the first stage, the start of the previous step).
-template <typename T, bool XYZ>
+template <typename T, bool XYZ, class Sink>
 __device__ __forceinline__ void rev_finish(const AdjDev<T>& d, const Coef<T>& k, int i, int s, int kk, int stage,
-                                           const RevIn<T>& in, T tx, T ty, T tz) {
+                                           const RevIn<T>& in, T tx, T ty, T tz, Sink& sink) {
     const int64_t ld = d.ld;
     const int64_t sb = (int64_t)s * 3 * ld;
     T xb[3] = {in.lc[0] + k.a_cp * tx, in.lc[1], in.lc[2]};
@@ -356,20 +369,21 @@ __device__ __forceinline__ void rev_finish(const AdjDev<T>& d, const Coef<T>& k,
         const T v0 = wgt * in.ab[0] + hst * xb[0];
         const T v1 = wgt * in.ab[1] + hst * xb[1];
         const T v2 = wgt * in.ab[2] + hst * xb[2];
-        vjp_apply<T, XYZ>(d, k, i, s, kk, stage - 1, in.v, v0, v1, v2);
+        vjp_apply<T, XYZ>(d, k, i, s, kk, stage - 1, in.v, v0, v1, v2, sink);
     } else if (kk > 0) {
         // step j = j0 + kk is reversed: mbar = dL/dm_j.  Start step j - 1,
         // whose output m_j is the first stage input of step j.
         const T* mhat = d.xt + adj_slot<3>(kk, 0, d.S, ld) + sb;
         const T pn = d.renorm ? d.pn[((int64_t)(kk - 1) * d.S + s) * ld + i] : T(1);
-        prep_step<T, XYZ>(d, k, i, s, kk - 1, mhat, pn, mb[0], mb[1], mb[2]);
+        prep_step<T, XYZ>(d, k, i, s, kk - 1, mhat, pn, mb[0], mb[1], mb[2], sink);
     }
 }
 
 template <typename T, bool XYZ>
 __device__ __forceinline__ void rev_epilogue(const AdjDev<T>& d, const Coef<T>& k, int i, int s, int kk, int stage,
                                              T tx, T ty, T tz) {
-    rev_finish<T, XYZ>(d, k, i, s, kk, stage, rev_load<T, XYZ>(d, i, s, kk, stage), tx, ty, tz);
+    GlobalSink sink;
+    rev_finish<T, XYZ>(d, k, i, s, kk, stage, rev_load<T, XYZ>(d, i, s, kk, stage), tx, ty, tz, sink);
 }
 
 // Launchers of the multi-stream (S > 1) stage kernels, FP32 (sto_batch.hip).

@@ -157,7 +157,8 @@ __global__ void __launch_bounds__(512) k_brev(AdjDev<float> d, Coef<float> k, in
     const float* bbar = d.st + adj_slot<C>(kk, stage, d.S, d.ld);
     float out[3] = {0.f, 0.f, 0.f};
     tile_product<C>(d.W, d.ld, d.n, blockIdx.x * kT, bbar, C * d.ld, d.ld, d.S, blockIdx.y * batch_spw<C>(), sh, out);
-    if (p.own) rev_finish<float, XYZ>(d, k, p.i, p.s, kk, stage, in, out[0], out[1], out[2]);
+    GlobalSink sink;
+    if (p.own) rev_finish<float, XYZ>(d, k, p.i, p.s, kk, stage, in, out[0], out[1], out[2], sink);
 }
 
 }  // namespace

@@ -31,6 +31,7 @@
 
 #include <climits>
 
+#include "sto_adjoint_dev.hpp"
 #include "sto_internal.hpp"
 #include "sto_multi.hpp"
 
@@ -294,6 +295,179 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
     }
 }
 
+// Parameter partials of one (node, stream) pair summed in registers over a
+// segment (up to kRegIn input channels) and added to gacc / gwin once at the
+// end; the last coupling adjoint the epilogue produced is kept for the
+// exchange.
+constexpr int kRegIn = 4;
+
+struct RegSink {
+    double g[4] = {0.0, 0.0, 0.0, 0.0};
+    double w[kRegIn] = {0.0, 0.0, 0.0, 0.0};
+    float b[3] = {0.f, 0.f, 0.f};
+    __device__ __forceinline__ void add(const AdjDev<float>& d, int64_t, double pcp, double pin, double phs,
+                                        double pap, double ab, const double* u_s, float bx, float by, float bz) {
+        g[0] += pcp;
+        g[1] += pin;
+        g[2] += phs;
+        g[3] += pap;
+#pragma unroll
+        for (int q = 0; q < kRegIn; ++q)
+            if (q < d.n_in) w[q] += ab * u_s[q];
+        b[0] = bx;
+        b[1] = by;
+        b[2] = bz;
+    }
+    __device__ __forceinline__ void flush(const AdjDev<float>& d, int64_t gi) {
+        const int64_t gs = (int64_t)d.S * d.ld;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) d.gacc[c * gs + gi] += g[c];
+#pragma unroll
+        for (int q = 0; q < kRegIn; ++q)
+            if (q < d.n_in) d.gwin[q * gs + gi] += w[q];
+    }
+};
+
+// Row tiles of 16 nodes per workgroup of the reverse kernel: both share the
+// gathered columns, and every thread of the workgroup owns a pair.
+constexpr int kRevTiles = 2;
+
+// Reversed stages of one adjoint segment in one cooperative launch: per
+// stage t = W^T bbar for all streams (the exchange of k_multi, with the
+// transpose of W as the A operands and two row tiles per workgroup), then
+// each pair's adjoint epilogue (rev_load / rev_finish, as the per-stage
+// kernels run it).  Each pair's epilogue inputs are loaded before the
+// gather, so their latency hides behind the wait for the other workgroups;
+// its parameter partials stay in registers until the end.  The epilogue
+// leaves the next stage's bbar in the trace of coupling adjoints and
+// publishes it through the rotating buffers.  Stages run from (kn - 1, 3)
+// down to (0, 0); buffer 0 starts with the bbar of (kn - 1, 3).
+template <int KREG, bool XYZ>
+__global__ void __launch_bounds__(kBlock) k_multi_rev(AdjDev<float> d, Coef<float> k, float* __restrict__ xbuf,
+                                                      int* sync, int kn) {
+    constexpr int C = XYZ ? 3 : 1;
+    constexpr int SPW = streams_per_group<XYZ>();
+    constexpr int KI = KREG <= 16 ? 1 : KREG / 16;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int ok_lds;
+    const int n = d.n;
+    const int64_t ld = d.ld;
+    const int streams = d.S;
+    const int kp = (n + 31) / 32 * 32;
+    float* xs = reinterpret_cast<float*>(smem_raw);              // [kp][kXP]
+    float* cs = xs + (int64_t)kp * kXP;                          // [kRevTiles][kWaves][16][16]
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int row0 = blockIdx.x * kTile * kRevTiles;
+    const int s0 = blockIdx.y * SPW;
+    const int ns = min(SPW, streams - s0);
+    int* abort_flag = sync + kSyncAbortWord;
+    if (threadIdx.x == 0) ok_lds = 1;
+    for (int i = threadIdx.x; i < kp * kXP; i += kBlock) xs[i] = 0.0f;
+
+    const int kq = kp / kWaves;
+    const int steps = kq / 4;
+    float areg[kRevTiles][KREG];
+#pragma unroll
+    for (int rt = 0; rt < kRevTiles; ++rt) {
+        const int r = row0 + rt * kTile + (lane & 15);
+#pragma unroll
+        for (int t = 0; t < KREG; ++t) {
+            const int kk = wave * kq + 4 * t + (lane >> 4);
+            areg[rt][t] = (t < steps && r < n && kk < n) ? d.Wt[(int64_t)r * ld + kk] : 0.0f;
+        }
+    }
+    // the pair of this thread: row tile tt, row ti, first column tj
+    const int tt = threadIdx.x >> 8, ti = (threadIdx.x >> 4) & 15, tj = threadIdx.x & 15;
+    const int js = tj / C;
+    const int node = row0 + tt * kTile + ti;
+    const int strm = s0 + js;
+    const bool mine = tj % C == 0 && js < ns && node < n;
+    const int64_t cstride = (int64_t)streams * ld;
+    const int64_t bstride = C * cstride;
+    RegSink sink;
+
+    int sigma = 0;
+    for (int kk = kn - 1; kk >= 0; --kk) {
+        for (int stage = 3; stage >= 0; --stage, ++sigma) {
+            const float* xin = xbuf + (int64_t)(sigma % 3) * bstride;
+            float* xout = xbuf + (int64_t)((sigma + 1) % 3) * bstride;
+            float* xold = xbuf + (int64_t)((sigma + 2) % 3) * bstride;
+            // the epilogue's inputs depend neither on the product nor on the
+            // other workgroups: load them before waiting for the exchange
+            RevIn<float> in{};
+            if (mine) in = rev_load<float, XYZ>(d, node, strm, kk, stage);
+            __syncthreads();
+            if (!gather_multi<C, SPW, KI>(xin, ld, cstride, n, s0, ns, xs, abort_flag)) ok_lds = 0;
+            __syncthreads();
+            if (ok_lds == 0) return;
+            if (mine) {
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    __hip_atomic_store(reinterpret_cast<unsigned*>(xold + c * cstride + (int64_t)strm * ld + node), ~0u,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            f4 acc[kRevTiles];
+#pragma unroll
+            for (int rt = 0; rt < kRevTiles; ++rt) acc[rt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int t = 0; t < KREG; ++t) {
+                if (t < steps) {
+                    const int kr = wave * kq + 4 * t + (lane >> 4);
+                    const float b = xs[kr * kXP + (lane & 15)];
+#pragma unroll
+                    for (int rt = 0; rt < kRevTiles; ++rt)
+                        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[rt][t], b, acc[rt], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int rt = 0; rt < kRevTiles; ++rt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    cs[((rt * kWaves + wave) * kTile + 4 * (lane >> 4) + r) * kTile + (lane & 15)] = acc[rt][r];
+            __syncthreads();
+            float t3[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int col = min(tj + c, kTile - 1);
+                float v = 0.f;
+#pragma unroll
+                for (int w = 0; w < kWaves; ++w) v += cs[((tt * kWaves + w) * kTile + ti) * kTile + col];
+                t3[c] = v;
+            }
+            // the re-arm stores must complete before the publish below; the
+            // epilogue's own stores need not
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            if (mine) {
+                rev_finish<float, XYZ>(d, k, node, strm, kk, stage, in, t3[0], t3[1], t3[2], sink);
+                if (kk > 0 || stage > 0) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+                        __hip_atomic_store(xout + c * cstride + (int64_t)strm * ld + node, sink.b[c], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
+    }
+    if (mine) sink.flush(d, (int64_t)strm * ld + node);
+}
+
+// Buffer 0 <- the bbar slot [stream][C][ld] rearranged as [C][stream][ld];
+// buffers 1 and 2 <- sentinel.
+__global__ void k_multi_rev_prologue(const float* slot, float* xchg, int streams, int64_t ld, int C) {
+    const int64_t per = (int64_t)streams * ld;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 3 * C * per;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        unsigned v = ~0u;
+        if (i < C * per) {
+            const int64_t c = i / per, r = i - c * per;
+            const int64_t st = r / ld, node = r - st * ld;
+            v = __builtin_bit_cast(unsigned, slot[(st * C + c) * ld + node]);
+        }
+        reinterpret_cast<unsigned*>(xchg)[i] = v;
+    }
+}
+
 __global__ void k_multi_prologue(const float* m, float* xchg, int streams, int64_t ld, int C) {
     // buffer 0 <- the coupled components of every stream ([C][streams][ld]);
     // buffers 1 and 2 <- sentinel
@@ -320,6 +494,12 @@ int kreg_for(int n) {
 }
 
 template <int KREG>
+const void* multi_rev_kernel(int xyz) {
+    return xyz ? reinterpret_cast<const void*>(&k_multi_rev<KREG, true>)
+               : reinterpret_cast<const void*>(&k_multi_rev<KREG, false>);
+}
+
+template <int KREG>
 const void* multi_kernel(int xyz, int trace) {
     if (trace)
         return xyz ? reinterpret_cast<const void*>(&k_multi<KREG, true, true>)
@@ -337,18 +517,30 @@ size_t multi_lds_bytes(int n) {
 
 namespace {
 
+// LDS of a kernel instance: the reverse holds kRevTiles partial tiles per wave.
+size_t lds_bytes(int n, int trace) {
+    const int kp = (n + 31) / 32 * 32;
+    const int tiles = trace == 2 ? kRevTiles : 1;
+    return ((size_t)kp * kXP + tiles * kWaves * kTile * kTile) * sizeof(float);
+}
+
+}  // namespace
+
+namespace {
+
 // The kernel instance for n nodes, with its dynamic LDS limit raised to what
 // it needs; nullptr when n is out of range.
+// trace: 0 forward, 1 forward with the adjoint's trace, 2 reversed stages.
 const void* multi_fn(int n, int xyz, int trace = 0) {
     const void* fn = nullptr;
     switch (kreg_for(n)) {
-        case 4: fn = multi_kernel<4>(xyz, trace); break;
-        case 8: fn = multi_kernel<8>(xyz, trace); break;
-        case 16: fn = multi_kernel<16>(xyz, trace); break;
-        case 32: fn = multi_kernel<32>(xyz, trace); break;
+        case 4: fn = trace == 2 ? multi_rev_kernel<4>(xyz) : multi_kernel<4>(xyz, trace); break;
+        case 8: fn = trace == 2 ? multi_rev_kernel<8>(xyz) : multi_kernel<8>(xyz, trace); break;
+        case 16: fn = trace == 2 ? multi_rev_kernel<16>(xyz) : multi_kernel<16>(xyz, trace); break;
+        case 32: fn = trace == 2 ? multi_rev_kernel<32>(xyz) : multi_kernel<32>(xyz, trace); break;
         default: return nullptr;
     }
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)multi_lds_bytes(n)) != hipSuccess)
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes(n, trace)) != hipSuccess)
         return nullptr;
     return fn;
 }
@@ -367,8 +559,9 @@ namespace {
 // reports for this kernel instance.
 bool fits(int n, int streams, int xyz, int trace, int* grid_x, int* grid_y) {
     if (n < 1 || streams < 1 || n > 32 * kMaxKreg) return false;
-    const int gx = (n + kTile - 1) / kTile, gy = stream_groups(streams, xyz);
-    const size_t lds = multi_lds_bytes(n);
+    const int rows = trace == 2 ? kTile * kRevTiles : kTile;
+    const int gx = (n + rows - 1) / rows, gy = stream_groups(streams, xyz);
+    const size_t lds = lds_bytes(n, trace);
     if (lds + 64 > 160 * 1024) return false;
     const void* fn = multi_fn(n, xyz, trace);
     if (!fn) return false;
@@ -415,6 +608,10 @@ bool multi_fits(int n, int streams, int xyz, int* grid_x, int* grid_y) {
 
 bool multi_segment_fits(int n, int streams, int xyz) { return fits(n, streams, xyz, 1, nullptr, nullptr); }
 
+bool multi_reverse_fits(int n, int streams, int xyz, int n_in) {
+    return n_in >= 1 && n_in <= kRegIn && fits(n, streams, xyz, 2, nullptr, nullptr);
+}
+
 hipError_t run_multi(const DevState<float>& d, const Coef<float>& k, const RunSpec& r, int streams) {
     return launch_multi(d, k, r, streams, 0, MultiTrace{nullptr, nullptr, nullptr});
 }
@@ -422,6 +619,35 @@ hipError_t run_multi(const DevState<float>& d, const Coef<float>& k, const RunSp
 hipError_t run_multi_segment(const DevState<float>& d, const Coef<float>& k, const RunSpec& r, int streams,
                              int sample0, const MultiTrace& tr) {
     return launch_multi(d, k, r, streams, sample0, tr);
+}
+
+}  // namespace sto
+
+namespace sto {
+
+hipError_t run_multi_reverse(const AdjDev<float>& d, const Coef<float>& k, int kn, int xyz, float* xchg, int* sync,
+                             hipStream_t stream) {
+    int gx = 0, gy = 0;
+    if (d.n_in < 1 || d.n_in > kRegIn || !fits(d.n, d.S, xyz, 2, &gx, &gy)) return hipErrorInvalidValue;
+    const size_t lds = lds_bytes(d.n, 2);
+    const int C = xyz ? 3 : 1;
+    hipError_t e = hipMemsetAsync(sync, 0, 256, stream);
+    if (e != hipSuccess) return e;
+    const float* slot = d.st + (xyz ? adj_slot<3>(kn - 1, 3, d.S, d.ld) : adj_slot<1>(kn - 1, 3, d.S, d.ld));
+    hipLaunchKernelGGL(k_multi_rev_prologue, dim3(64), dim3(256), 0, stream, slot, xchg, d.S, d.ld, C);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    AdjDev<float> dd = d;
+    Coef<float> kk = k;
+    float* xb = xchg;
+    int* sy = sync;
+    int knn = kn;
+    void* args[] = {&dd, &kk, &xb, &sy, &knn};
+    const void* fn = multi_fn(d.n, xyz, 2);
+    if (!fn) return hipErrorInvalidValue;
+    e = hipLaunchCooperativeKernel(fn, dim3(gx, gy), dim3(kBlock), args, (unsigned)lds, stream);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
 }
 
 }  // namespace sto

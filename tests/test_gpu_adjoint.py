@@ -274,6 +274,34 @@ def test_adjoint_streams_matches_oracle(stx, coupling, seg, renorm):
     compare(got, ref, F32_TOL, f"streams {coupling}")
 
 
+@pytest.mark.parametrize("coupling,n,S,seg,renorm", [("xyz", 300, 7, 0, True), ("x", 130, 20, 8, False),
+                                                     ("xyz", 40, 3, 4, False)])
+def test_adjoint_streams_reverse_kernels_agree(stx, coupling, n, S, seg, renorm, monkeypatch):
+    """The reversed stages on the persistent kernel (several 16-node tiles
+    and stream groups with a ragged last group) and on the per-stage
+    kernels (STO_MULTI_REVERSE=0), both against the oracle and against
+    each other."""
+    samples, sub = 2, 4
+    w, w_in, _, _ = random_case(n, seed=31, samples=1, spread=0.3)
+    rng = np.random.default_rng(32)
+    m0s = unit_states(rng, S, n)
+    u = rng.uniform(-1, 1, (samples, S, 1))
+    prm = oracle_params(a_cp=0.3, a_in=0.7, substeps=sub, coupling=coupling, renormalize=renorm)
+    g_rec = np.float32(rng.standard_normal((samples, S, n, 3))).astype(np.float64)
+    g_fin = np.float32(rng.standard_normal((S, n, 3))).astype(np.float64)
+    w, w_in = (np.float32(a).astype(np.float64) for a in (w, w_in))
+    ref = oracle_streams_adjoint(w, w_in, np.float32(m0s).astype(np.float64), u, prm, g_rec, g_fin)
+    got = {}
+    for rev in ("1", "0"):
+        monkeypatch.setenv("STO_MULTI_REVERSE", rev)
+        say(f"adjoint streams reverse={rev} S={S} n={n} {coupling} seg={seg} renorm={renorm}")
+        with stx.Reservoir(w, w_in, m0s, lib_params(prm, "f32"), streams=S) as r:
+            assert r.path == "multi"
+            got[rev] = r.adjoint(m0s, u, g_rec, g_fin, checkpoint_every=seg)
+        compare(got[rev], ref, F32_TOL, f"streams reverse={rev} {coupling}")
+    compare(got["1"], got["0"], F32_TOL, "persistent vs per-stage reverse")
+
+
 def test_adjoint_streams64_xyz_oracle_and_central_fd(stx):
     """The differentiation workload's shape: N = 512, 64 input streams sharing
     W, all three components coupled (the N x 192 product), one input sample
