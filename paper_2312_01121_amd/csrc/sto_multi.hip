@@ -30,6 +30,7 @@
 // raises a sticky abort flag when it expires.
 
 #include <climits>
+#include <cstdlib>
 
 #include "sto_adjoint_dev.hpp"
 #include "sto_internal.hpp"
@@ -131,8 +132,9 @@ __device__ bool gather_multi(const float* xb, int64_t ld, int64_t cstride, int n
 // KREG: MFMA steps per wave, >= ceil(N/32) (each step contracts 4 nodes;
 // N <= 32 KREG).  XYZ: all three components coupled, else m^x only.  TRACE:
 // write the stage trace of the adjoint (tr); sample0 offsets the sample
-// index reported on a non-finite state.
-template <int KREG, bool XYZ, bool TRACE>
+// index reported on a non-finite state.  RT: 16-node row tiles per
+// workgroup (1 or 2), which share the gathered columns.
+template <int KREG, bool XYZ, bool TRACE, int RT>
 __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float> k, const double* __restrict__ u,
                                                   float* __restrict__ states, int streams, int samples,
                                                   int substeps, int renorm, int sample0, MultiTrace tr) {
@@ -145,10 +147,10 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
     const int64_t ld = d.ld;
     const int kp = (n + 31) / 32 * 32;                           // contraction length padded to 32
     float* xs = reinterpret_cast<float*>(smem_raw);              // [kp][kXP]
-    float* cs = xs + (int64_t)kp * kXP;                          // [kWaves][16][16] partial tiles
+    float* cs = xs + (int64_t)kp * kXP;                          // [RT][kWaves][16][16] partial tiles
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int row0 = blockIdx.x * kTile;
+    const int row0 = blockIdx.x * kTile * RT;
     const int s0 = blockIdx.y * SPW;
     const int ns = min(SPW, streams - s0);
     int* abort_flag = d.sync + kSyncAbortWord;
@@ -158,23 +160,24 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
     // A operands: this wave's eighth of the contraction for the tile's rows.
     const int kq = kp / kWaves;                                  // nodes per wave (multiple of 4)
     const int steps = kq / 4;
-    float areg[KREG];
-    {
-        const int r = row0 + (lane & 15);
+    float areg[RT][KREG];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+        const int r = row0 + rt * kTile + (lane & 15);
 #pragma unroll
         for (int t = 0; t < KREG; ++t) {
             const int kk = wave * kq + 4 * t + (lane >> 4);
-            areg[t] = (t < steps && r < n && kk < n) ? d.W[(int64_t)r * ld + kk] : 0.0f;
+            areg[rt][t] = (t < steps && r < n && kk < n) ? d.W[(int64_t)r * ld + kk] : 0.0f;
         }
     }
 
-    // the (node, stream) pair of this thread: output row ti, first column tj
-    // of the stream's C columns
-    const int ti = (threadIdx.x >> 4) & 15, tj = threadIdx.x & 15;
+    // the (node, stream) pair of this thread: row tile tt, output row ti,
+    // first column tj of the stream's C columns
+    const int tt = threadIdx.x >> 8, ti = (threadIdx.x >> 4) & 15, tj = threadIdx.x & 15;
     const int js = tj / C;
-    const int node = row0 + ti;
+    const int node = row0 + tt * kTile + ti;
     const int strm = s0 + js;
-    const bool mine = threadIdx.x < kTile * kTile && tj % C == 0 && js < ns && node < n;
+    const bool mine = tt < RT && tj % C == 0 && js < ns && node < n;
     const int nd = min(node, n - 1), sd = min(strm, streams - 1);
     const float* m_in = d.m + (int64_t)sd * 3 * ld;
     float mx = m_in[nd], my = m_in[ld + nd], mz = m_in[2 * ld + nd];
@@ -206,24 +209,33 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
                 }
                 // partial tile of this wave: D[i][col] = sum over its nodes of
                 // W[row0+i][k] X[k][col]
-                f4 acc = {0.f, 0.f, 0.f, 0.f};
+                f4 acc[RT];
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) acc[rt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int t = 0; t < KREG; ++t) {
                     if (t < steps) {
                         const int kk = wave * kq + 4 * t + (lane >> 4);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[t], xs[kk * kXP + (lane & 15)], acc, 0, 0, 0);
+                        const float b = xs[kk * kXP + (lane & 15)];
+#pragma unroll
+                        for (int rt = 0; rt < RT; ++rt)
+                            acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[rt][t], b, acc[rt], 0, 0, 0);
                     }
                 }
 #pragma unroll
-                for (int r = 0; r < 4; ++r) cs[(wave * kTile + 4 * (lane >> 4) + r) * kTile + (lane & 15)] = acc[r];
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        cs[((rt * kWaves + wave) * kTile + 4 * (lane >> 4) + r) * kTile + (lane & 15)] = acc[rt][r];
                 __syncthreads();
                 float dot[C];
+                const int tc = min(tt, RT - 1);   // stays in the partial tiles for threads that own no pair
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    const int col = min(tj + c, kTile - 1);   // stays in the tile for threads that own no pair
-                    float v = cs[(0 * kTile + ti) * kTile + col];
+                    const int col = min(tj + c, kTile - 1);
+                    float v = cs[((tc * kWaves + 0) * kTile + ti) * kTile + col];
 #pragma unroll
-                    for (int w = 1; w < kWaves; ++w) v += cs[(w * kTile + ti) * kTile + col];
+                    for (int w = 1; w < kWaves; ++w) v += cs[((tc * kWaves + w) * kTile + ti) * kTile + col];
                     dot[c] = v;
                 }
                 if constexpr (TRACE) {
@@ -499,48 +511,49 @@ const void* multi_rev_kernel(int xyz) {
                : reinterpret_cast<const void*>(&k_multi_rev<KREG, false>);
 }
 
-template <int KREG>
+template <int KREG, int RT>
 const void* multi_kernel(int xyz, int trace) {
     if (trace)
-        return xyz ? reinterpret_cast<const void*>(&k_multi<KREG, true, true>)
-                   : reinterpret_cast<const void*>(&k_multi<KREG, false, true>);
-    return xyz ? reinterpret_cast<const void*>(&k_multi<KREG, true, false>)
-               : reinterpret_cast<const void*>(&k_multi<KREG, false, false>);
+        return xyz ? reinterpret_cast<const void*>(&k_multi<KREG, true, true, RT>)
+                   : reinterpret_cast<const void*>(&k_multi<KREG, false, true, RT>);
+    return xyz ? reinterpret_cast<const void*>(&k_multi<KREG, true, false, RT>)
+               : reinterpret_cast<const void*>(&k_multi<KREG, false, false, RT>);
 }
 
-}  // namespace
-
-size_t multi_lds_bytes(int n) {
-    const int kp = (n + 31) / 32 * 32;
-    return ((size_t)kp * kXP + kWaves * kTile * kTile) * sizeof(float);
-}
-
-namespace {
-
-// LDS of a kernel instance: the reverse holds kRevTiles partial tiles per wave.
-size_t lds_bytes(int n, int trace) {
-    const int kp = (n + 31) / 32 * 32;
-    const int tiles = trace == 2 ? kRevTiles : 1;
-    return ((size_t)kp * kXP + tiles * kWaves * kTile * kTile) * sizeof(float);
+template <int KREG>
+const void* multi_kernel(int xyz, int trace, int rt) {
+    return rt == 2 ? multi_kernel<KREG, 2>(xyz, trace) : multi_kernel<KREG, 1>(xyz, trace);
 }
 
 }  // namespace
 
 namespace {
 
-// The kernel instance for n nodes, with its dynamic LDS limit raised to what
-// it needs; nullptr when n is out of range.
+// LDS of a kernel instance: the columns and one partial tile per wave and
+// row tile.
+size_t lds_bytes(int n, int rt) {
+    const int kp = (n + 31) / 32 * 32;
+    return ((size_t)kp * kXP + rt * kWaves * kTile * kTile) * sizeof(float);
+}
+
+}  // namespace
+
+namespace {
+
+// The kernel instance for n nodes and rt row tiles, with its dynamic LDS
+// limit raised to what it needs; nullptr when n is out of range.
 // trace: 0 forward, 1 forward with the adjoint's trace, 2 reversed stages.
-const void* multi_fn(int n, int xyz, int trace = 0) {
+const void* multi_fn(int n, int xyz, int trace, int rt) {
+    if (trace == 2 && rt != kRevTiles) return nullptr;
     const void* fn = nullptr;
     switch (kreg_for(n)) {
-        case 4: fn = trace == 2 ? multi_rev_kernel<4>(xyz) : multi_kernel<4>(xyz, trace); break;
-        case 8: fn = trace == 2 ? multi_rev_kernel<8>(xyz) : multi_kernel<8>(xyz, trace); break;
-        case 16: fn = trace == 2 ? multi_rev_kernel<16>(xyz) : multi_kernel<16>(xyz, trace); break;
-        case 32: fn = trace == 2 ? multi_rev_kernel<32>(xyz) : multi_kernel<32>(xyz, trace); break;
+        case 4: fn = trace == 2 ? multi_rev_kernel<4>(xyz) : multi_kernel<4>(xyz, trace, rt); break;
+        case 8: fn = trace == 2 ? multi_rev_kernel<8>(xyz) : multi_kernel<8>(xyz, trace, rt); break;
+        case 16: fn = trace == 2 ? multi_rev_kernel<16>(xyz) : multi_kernel<16>(xyz, trace, rt); break;
+        case 32: fn = trace == 2 ? multi_rev_kernel<32>(xyz) : multi_kernel<32>(xyz, trace, rt); break;
         default: return nullptr;
     }
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes(n, trace)) != hipSuccess)
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes(n, rt)) != hipSuccess)
         return nullptr;
     return fn;
 }
@@ -554,32 +567,57 @@ int stream_groups(int streams, int xyz) {
 
 namespace {
 
-// Whether every tile can be co-resident (the cooperative launch needs all of
-// them): the LDS fits and the grid is within the occupancy the runtime
-// reports for this kernel instance.
-bool fits(int n, int streams, int xyz, int trace, int* grid_x, int* grid_y) {
-    if (n < 1 || streams < 1 || n > 32 * kMaxKreg) return false;
-    const int rows = trace == 2 ? kTile * kRevTiles : kTile;
+// A launch of one kernel instance: row tiles per workgroup, grid, LDS.
+struct Shape {
+    const void* fn;
+    int rt, gx, gy;
+    size_t lds;
+};
+
+// Whether every workgroup of the instance with rt row tiles can be
+// co-resident (the cooperative launch needs all of them): the LDS fits and
+// the grid is within the occupancy the runtime reports for it.
+bool fits_rt(int n, int streams, int xyz, int trace, int rt, Shape* sh) {
+    const int rows = kTile * rt;
     const int gx = (n + rows - 1) / rows, gy = stream_groups(streams, xyz);
-    const size_t lds = lds_bytes(n, trace);
+    const size_t lds = lds_bytes(n, rt);
     if (lds + 64 > 160 * 1024) return false;
-    const void* fn = multi_fn(n, xyz, trace);
+    const void* fn = multi_fn(n, xyz, trace, rt);
     if (!fn) return false;
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return false;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, lds) != hipSuccess) return false;
     if (per_cu < 1 || (int64_t)gx * gy > (int64_t)cus * per_cu) return false;
-    if (grid_x) *grid_x = gx;
-    if (grid_y) *grid_y = gy;
+    if (sh) *sh = Shape{fn, rt, gx, gy, lds};
     return true;
+}
+
+// The launch shape of an instance, or false when none is co-resident.  The
+// reverse takes two row tiles per workgroup.  The forward takes two when a
+// grid of one-tile workgroups would need more than one per CU (the tiles
+// then share one gather of the columns: at 64 streams x N = 512 with
+// isotropic coupling 18.2 us per RK4 step against 24.4), else one (with
+// m^x coupling, 128 one-tile workgroups took 16.8 us per step and 64
+// two-tile ones 18.8); STO_MULTI_TILES=1 or 2 chooses for measurements.
+bool fits(int n, int streams, int xyz, int trace, Shape* sh) {
+    if (n < 1 || streams < 1 || n > 32 * kMaxKreg) return false;
+    if (trace == 2) return fits_rt(n, streams, xyz, trace, kRevTiles, sh);
+    const char* env = getenv("STO_MULTI_TILES");
+    const int forced = env ? atoi(env) : 0;
+    if (forced == 1 || forced == 2) return fits_rt(n, streams, xyz, trace, forced, sh);
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+    const int64_t one = (int64_t)((n + kTile - 1) / kTile) * stream_groups(streams, xyz);
+    const int first = one > cus ? 2 : 1;
+    return fits_rt(n, streams, xyz, trace, first, sh) || fits_rt(n, streams, xyz, trace, 3 - first, sh);
 }
 
 hipError_t launch_multi(const DevState<float>& d, const Coef<float>& k, const RunSpec& r, int streams, int sample0,
                         const MultiTrace& tr) {
-    int gx = 0, gy = 0;
-    if (!fits(d.n, streams, r.xyz, tr.xt != nullptr, &gx, &gy)) return hipErrorInvalidValue;
-    const size_t lds = multi_lds_bytes(d.n);
+    Shape sh{};
+    if (!fits(d.n, streams, r.xyz, tr.xt != nullptr, &sh)) return hipErrorInvalidValue;
     hipError_t e = hipMemsetAsync(d.sync, 0, 256, r.stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_multi_prologue, dim3(64), dim3(256), 0, r.stream, (const float*)d.m, d.xchg, streams, d.ld,
@@ -593,9 +631,7 @@ hipError_t launch_multi(const DevState<float>& d, const Coef<float>& k, const Ru
     int st = streams, samples = r.samples, substeps = r.substeps, renorm = r.renorm, s0 = sample0;
     MultiTrace t = tr;
     void* args[] = {&dd, &kk, &u, &states, &st, &samples, &substeps, &renorm, &s0, &t};
-    const void* fn = multi_fn(d.n, r.xyz, tr.xt != nullptr);
-    if (!fn) return hipErrorInvalidValue;
-    e = hipLaunchCooperativeKernel(fn, dim3(gx, gy), dim3(kBlock), args, (unsigned)lds, r.stream);
+    e = hipLaunchCooperativeKernel(sh.fn, dim3(sh.gx, sh.gy), dim3(kBlock), args, (unsigned)sh.lds, r.stream);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
@@ -603,13 +639,17 @@ hipError_t launch_multi(const DevState<float>& d, const Coef<float>& k, const Ru
 }  // namespace
 
 bool multi_fits(int n, int streams, int xyz, int* grid_x, int* grid_y) {
-    return fits(n, streams, xyz, 0, grid_x, grid_y);
+    Shape sh{};
+    if (!fits(n, streams, xyz, 0, &sh)) return false;
+    if (grid_x) *grid_x = sh.gx;
+    if (grid_y) *grid_y = sh.gy;
+    return true;
 }
 
-bool multi_segment_fits(int n, int streams, int xyz) { return fits(n, streams, xyz, 1, nullptr, nullptr); }
+bool multi_segment_fits(int n, int streams, int xyz) { return fits(n, streams, xyz, 1, nullptr); }
 
 bool multi_reverse_fits(int n, int streams, int xyz, int n_in) {
-    return n_in >= 1 && n_in <= kRegIn && fits(n, streams, xyz, 2, nullptr, nullptr);
+    return n_in >= 1 && n_in <= kRegIn && fits(n, streams, xyz, 2, nullptr);
 }
 
 hipError_t run_multi(const DevState<float>& d, const Coef<float>& k, const RunSpec& r, int streams) {
@@ -627,9 +667,8 @@ namespace sto {
 
 hipError_t run_multi_reverse(const AdjDev<float>& d, const Coef<float>& k, int kn, int xyz, float* xchg, int* sync,
                              hipStream_t stream) {
-    int gx = 0, gy = 0;
-    if (d.n_in < 1 || d.n_in > kRegIn || !fits(d.n, d.S, xyz, 2, &gx, &gy)) return hipErrorInvalidValue;
-    const size_t lds = lds_bytes(d.n, 2);
+    Shape sh{};
+    if (d.n_in < 1 || d.n_in > kRegIn || !fits(d.n, d.S, xyz, 2, &sh)) return hipErrorInvalidValue;
     const int C = xyz ? 3 : 1;
     hipError_t e = hipMemsetAsync(sync, 0, 256, stream);
     if (e != hipSuccess) return e;
@@ -643,9 +682,7 @@ hipError_t run_multi_reverse(const AdjDev<float>& d, const Coef<float>& k, int k
     int* sy = sync;
     int knn = kn;
     void* args[] = {&dd, &kk, &xb, &sy, &knn};
-    const void* fn = multi_fn(d.n, xyz, 2);
-    if (!fn) return hipErrorInvalidValue;
-    e = hipLaunchCooperativeKernel(fn, dim3(gx, gy), dim3(kBlock), args, (unsigned)lds, stream);
+    e = hipLaunchCooperativeKernel(sh.fn, dim3(sh.gx, sh.gy), dim3(kBlock), args, (unsigned)sh.lds, stream);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }

@@ -70,6 +70,30 @@ def test_multi_one_step_matches_oracle(stx, n, streams, coupling):
     assert worst <= F32_TOL
 
 
+@pytest.mark.parametrize("n,streams,coupling", [(300, 7, "xyz"), (257, 17, "x"), (512, 64, "xyz")])
+def test_multi_row_tiles_agree(stx, n, streams, coupling, monkeypatch):
+    """One and two 16-node row tiles per workgroup (STO_MULTI_TILES) give
+    the same bits (each tile's products and wave sums are the same), and
+    both match the oracle; ragged last row tile and stream group."""
+    w, w_in, m0, u = stream_case(n, streams, seed=n + 1, samples=2)
+    prm = oracle_params(a_cp=0.3, substeps=3, coupling=coupling)
+    m0s = distinct_states(np.random.default_rng(n + 9), streams, n)
+    recs = {}
+    for tiles in ("1", "2"):
+        monkeypatch.setenv("STO_MULTI_TILES", tiles)
+        say("multi row tiles", tiles, n, streams, coupling)
+        with stx.Reservoir(w, w_in, m0s, lib_params(prm, dtype="f32"), streams=streams) as r:
+            assert r.path == "multi"
+            recs[tiles] = r.run(u)
+    assert np.array_equal(recs["1"], recs["2"])
+    worst = 0.0
+    for s in (range(streams) if streams <= 8 else (0, streams // 2, streams - 1)):
+        rec_o, _ = sto.run(f32(w), f32(w_in), f32(m0s[s]), u[:, s], prm)
+        worst = max(worst, float(np.max(np.abs(recs["2"][:, s] - rec_o))))
+    say("  max diff", worst)
+    assert worst <= F32_TOL
+
+
 @pytest.mark.parametrize("path", ["multi", "batch"])
 @pytest.mark.parametrize("coupling", ["x", "xyz"])
 def test_streams_renormalize_and_several_inputs(stx, path, coupling):
