@@ -295,13 +295,16 @@ def run_streams_workload(stx, torch, name: str, steps: int, warmup: int, couplin
 
 
 def run_streams_adjoint_workload(stx, torch, name: str, coupling: str, steps: int, warmup: int,
-                                 checkpoint_every: int = 100):
+                                 checkpoint_every: int = 100, own_checkpoints: bool = False):
     """The differentiation workload: S input streams share one reservoir;
     one step is the forward run of every stream, one ridge readout and its
     objective's gradient per stream, and the adjoint of all streams
     (gradients of the summed objective with respect to W, w_in, every
     stream's m0 and the four scalars), with a state checkpoint every
-    `checkpoint_every` RK4 steps.  The coupling is all three components (an
+    `checkpoint_every` RK4 steps.  The checkpoints are the forward run's
+    records (reservoir_adjoint_records_device: each segment is recomputed
+    from its record and reversed), or with own_checkpoints the adjoint's own
+    checkpointing forward pass (reservoir_adjoint_device).  The coupling is all three components (an
     N x N by N x 3S product per stage) or x only.  The coupling and input
     amplitudes are the paper's (A_cp = A_in = 1 Oe): at the workload's
     a_cp = 0.1, a_in = 1 the trajectory is chaotic (largest Lyapunov exponent
@@ -344,7 +347,8 @@ def run_streams_adjoint_workload(stx, torch, name: str, coupling: str, steps: in
             g_rec[:, st] = g
             loss += j
         ev[2].record(stream)
-        out = r.adjoint_device(m0_d, u_d, grad_states_dev=g_rec, checkpoint_every=checkpoint_every, stream=stream)
+        out = r.adjoint_device(m0_d, u_d, grad_states_dev=g_rec, checkpoint_every=checkpoint_every, stream=stream,
+                               records_dev=None if own_checkpoints else states)
         ev[3].record(stream)
         return ev, loss, out
 
@@ -364,12 +368,17 @@ def run_streams_adjoint_workload(stx, torch, name: str, coupling: str, steps: in
     C = 3 if coupling == "xyz" else 1
     segs = (wl.steps + checkpoint_every - 1) // checkpoint_every
     last = wl.steps - (segs - 1) * checkpoint_every
-    products = 4 * (wl.steps + (wl.steps - last) + wl.steps)     # stage products of the adjoint
+    # stage products of the adjoint: [checkpointing forward,] recompute, reverse
+    if own_checkpoints:
+        products = 4 * (wl.steps + (wl.steps - last) + wl.steps)
+    else:
+        products = 4 * (wl.steps + wl.steps)
     flops = products * 2.0 * wl.n * wl.n * S * C + 2.0 * wl.n * wl.n * 4 * wl.steps * S * C   # + dL/dW
     return {
         "workload": f"adjoint/{name}", "n": wl.n, "streams": S, "coupling": coupling, "dtype": "f32",
         "a_cp": amp, "a_in": amp,
         "forward_path": path, "samples": wl.samples, "rk4_steps": wl.steps, "checkpoint_every": checkpoint_every,
+        "checkpoints": "own forward pass" if own_checkpoints else "the run's records",
         "value": S * wl.n * wl.steps / (adj_ms * 1e-3), "unit": "node-steps/s (gradient)",
         "ms_per_step": wall_s * 1e3, "forward_ms": fwd_ms, "loss_ms": loss_ms, "adjoint_ms": adj_ms,
         "adjoint_over_forward": adj_ms / fwd_ms, "us_per_rk4_step": adj_ms * 1e3 / wl.steps,
@@ -592,6 +601,8 @@ def main():
                     help="time only the adjoint line for this workload (e.g. sto10k:f32:50; for the "
                          "multi-stream workload the second field is the coupling: streams64:xyz:0)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--own-checkpoints", action="store_true",
+                    help="multi-stream adjoint: checkpoints from the adjoint's own forward pass, not the records")
     ap.add_argument("--samples", type=int, default=None,
                     help="run only the first SAMPLES input samples of the main workload (short profiled runs)")
     ap.add_argument("--paper-table", type=int, default=0, metavar="STEPS",
@@ -632,7 +643,8 @@ def main():
     if args.adjoint:
         name, dt, samples = args.adjoint.split(":")
         if name in STREAMS:
-            res = run_streams_adjoint_workload(stx, torch, name, dt, args.steps, args.warmup)
+            res = run_streams_adjoint_workload(stx, torch, name, dt, args.steps, args.warmup,
+                                               own_checkpoints=args.own_checkpoints)
         else:
             res = run_adjoint_workload(stx, torch, name, dt, int(samples), args.steps, args.warmup)
         print(json.dumps({"adjoint": res}), flush=True)

@@ -203,6 +203,31 @@ sto_status reservoir_adjoint_device(sto_reservoir *r, const void *m_start_dev, c
                                     int64_t checkpoint_every, void *hip_stream);
 
 /*
+ * reservoir_adjoint_records_device -- reservoir_adjoint_device for a run
+ * whose records the caller still holds (the differentiated map and the
+ * arguments are the same; Sec. 3.1 and 3.2 as above).  A record is the state
+ * after the last step of a sample, so with segments of whole samples the
+ * state at the start of segment g > 0 is the record of sample
+ * g*checkpoint_every/substeps - 1, and the adjoint takes its checkpoints
+ * from the records instead of running the forward once more before the
+ * recompute of every segment.
+ *   records_dev      device, (steps/substeps)*S*n*3 elements of the handle's
+ *                    dtype: the records reservoir_run_device wrote for this
+ *                    m_start, u and handle (same parameters and path); not
+ *                    checked, and gradients of other records are those of a
+ *                    different trajectory.  Read only.
+ *   checkpoint_every a multiple of substeps (else STO_E_INVALID); 0: the
+ *                    library chooses, as above, rounded down to whole samples
+ * Every other argument, the workspace and the errors are those of
+ * reservoir_adjoint_device; records_dev NULL is STO_E_INVALID.
+ */
+sto_status reservoir_adjoint_records_device(sto_reservoir *r, const void *m_start_dev, const void *u_dev,
+                                            int64_t steps, const void *records_dev, const void *grad_states_dev,
+                                            const void *grad_final_dev, void *grad_W_dev, void *grad_w_in_dev,
+                                            void *grad_m0_dev, double *grad_scalars_dev, int64_t checkpoint_every,
+                                            void *hip_stream);
+
+/*
  * reservoir_adjoint -- reservoir_adjoint_device on host arrays of doubles
  * (m_start S*n*3, u (steps/substeps)*S*n_in, grad_states, grad_final, and
  * the outputs grad_W n*n, grad_w_in n*n_in, grad_m0 S*n*3, grad_scalars 4),

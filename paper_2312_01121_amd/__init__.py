@@ -5,7 +5,7 @@ carry the C entry points' names and only marshal arguments; every step of
 the computation runs in the library's HIP kernels.  PyTorch is used only
 for device buffers and streams (``run_device``).  Importing this package
 fails loudly if the shared library has not been built
-(``python -m paper_2312_01121_amd._build``).
+(``python paper_2312_01121_amd/_build.py``).
 """
 
 from __future__ import annotations
@@ -73,7 +73,7 @@ def _load():
     except ImportError:
         pass
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2312_01121_amd._build`")
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2312_01121_amd/_build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     dp = ctypes.POINTER(ctypes.c_double)
     vp = ctypes.c_void_p
@@ -124,6 +124,9 @@ def _load():
     lib.reservoir_adjoint.restype = ctypes.c_int
     lib.reservoir_adjoint_device.argtypes = [H, vp, vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp, ctypes.c_int64, vp]
     lib.reservoir_adjoint_device.restype = ctypes.c_int
+    lib.reservoir_adjoint_records_device.argtypes = [H, vp, vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp,
+                                                     ctypes.c_int64, vp]
+    lib.reservoir_adjoint_records_device.restype = ctypes.c_int
     lib.readout_grad_device.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, vp, ctypes.c_int64,
                                         ctypes.c_double, ctypes.c_int32, vp, vp, dp, vp]
     lib.readout_grad_device.restype = ctypes.c_int
@@ -139,7 +142,7 @@ _lib = _load()
 EXPORTED = ("reservoir_create", "reservoir_create_streams", "reservoir_streams", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
             "reservoir_set_state", "reservoir_path", "reservoir_destroy", "readout_fit", "readout_fit_device",
             "readout_fit_batch_device", "sweep_create", "sweep_nodes", "sweep_run", "sweep_run_device", "sweep_get_state", "sweep_destroy",
-            "reservoir_adjoint", "reservoir_adjoint_device", "readout_grad_device",
+            "reservoir_adjoint", "reservoir_adjoint_device", "reservoir_adjoint_records_device", "readout_grad_device",
             "sto_read_bandwidth", "sto_set_stream_variant", "sto_last_error")
 
 SCALAR_NAMES = ("a_cp", "a_in", "h_s", "h_appl")
@@ -341,14 +344,22 @@ def reservoir_adjoint(h, n: int, n_in: int, substeps: int, m_start, u, steps: in
 
 def reservoir_adjoint_device(h, m_start_dev, u_dev, steps: int, grad_states_dev=None, grad_final_dev=None,
                              grad_W_dev=None, grad_w_in_dev=None, grad_m0_dev=None, grad_scalars_dev=None,
-                             checkpoint_every: int = 0, stream=None):
+                             checkpoint_every: int = 0, stream=None, records_dev=None):
     """CUDA tensors of the handle's dtype (u and the scalars float64); every
-    output tensor may be None to skip it."""
+    output tensor may be None to skip it.  With records_dev (the run's
+    records) the call is reservoir_adjoint_records_device."""
     import torch
     s = (stream or torch.cuda.current_stream()).cuda_stream
-    _check(_lib.reservoir_adjoint_device(h, _vp(m_start_dev), _vp(u_dev), steps, _vp(grad_states_dev),
-                                         _vp(grad_final_dev), _vp(grad_W_dev), _vp(grad_w_in_dev), _vp(grad_m0_dev),
-                                         _vp(grad_scalars_dev), checkpoint_every, ctypes.c_void_p(s)))
+    if records_dev is None:
+        _check(_lib.reservoir_adjoint_device(h, _vp(m_start_dev), _vp(u_dev), steps, _vp(grad_states_dev),
+                                             _vp(grad_final_dev), _vp(grad_W_dev), _vp(grad_w_in_dev),
+                                             _vp(grad_m0_dev), _vp(grad_scalars_dev), checkpoint_every,
+                                             ctypes.c_void_p(s)))
+    else:
+        _check(_lib.reservoir_adjoint_records_device(h, _vp(m_start_dev), _vp(u_dev), steps, _vp(records_dev),
+                                                     _vp(grad_states_dev), _vp(grad_final_dev), _vp(grad_W_dev),
+                                                     _vp(grad_w_in_dev), _vp(grad_m0_dev), _vp(grad_scalars_dev),
+                                                     checkpoint_every, ctypes.c_void_p(s)))
 
 
 def readout_grad_device(states_dev, y_dev, washout: int, lam: float, w_dev, features: int = 0, grad_dev=None,
@@ -438,8 +449,10 @@ class Reservoir:
                                  grad_states, grad_final, checkpoint_every)
 
     def adjoint_device(self, m_start_dev, u_dev, grad_states_dev=None, grad_final_dev=None, want=("W", "w_in", "m0",
-                       "scalars"), checkpoint_every: int = 0, stream=None) -> dict:
-        """Gradients as CUDA tensors of the handle's dtype (scalars: float64 (4,))."""
+                       "scalars"), checkpoint_every: int = 0, stream=None, records_dev=None) -> dict:
+        """Gradients as CUDA tensors of the handle's dtype (scalars: float64 (4,)).
+        records_dev: the records of the run from m_start_dev over u_dev, used
+        as the checkpoints (checkpoint_every a multiple of substeps)."""
         import torch
         dt = torch.float64 if self.dtype == "f64" else torch.float32
         dev = u_dev.device
@@ -458,12 +471,13 @@ class Reservoir:
         per = self.streams * self.n
         assert u_dev.is_cuda and u_dev.dtype == torch.float64 and u_dev.is_contiguous()
         assert u_dev.numel() == samples * self.streams * self.n_in
-        for t, count in ((m_start_dev, per * 3), (grad_states_dev, samples * per * 3), (grad_final_dev, per * 3)):
+        for t, count in ((m_start_dev, per * 3), (grad_states_dev, samples * per * 3), (grad_final_dev, per * 3),
+                         (records_dev, samples * per * 3)):
             if t is not None:
                 assert t.is_cuda and t.dtype == dt and t.is_contiguous() and t.numel() == count
         reservoir_adjoint_device(self.h, m_start_dev, u_dev, samples * self.substeps, grad_states_dev,
                                  grad_final_dev, out.get("W"), out.get("w_in"), out.get("m0"), out.get("scalars"),
-                                 checkpoint_every, stream)
+                                 checkpoint_every, stream, records_dev)
         return out
 
     def get_state(self) -> np.ndarray:

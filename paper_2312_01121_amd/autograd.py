@@ -1,7 +1,9 @@
 """torch.autograd wrappers over the library's forward run, ridge readout and
 adjoint.  Argument marshalling only: the forward is ``reservoir_run_device``,
 the loss is ``readout_fit_device`` + ``readout_grad_device`` and the
-backward is ``reservoir_adjoint_device``.
+backward is ``reservoir_adjoint_records_device`` (the forward's records are
+the checkpoints of its segments; ``reservoir_adjoint_device`` when the
+segments are not whole samples).
 
     records = reservoir_records(W, w_in, m0, a_cp, a_in, h_s, h_appl, u, prm)
     loss = ridge_loss(records, y, washout, lam)
@@ -47,6 +49,7 @@ class ReservoirRecords(torch.autograd.Function):
         records = torch.empty((samples, res.n, 3), dtype=dt, device=dev)
         res.run_device(u, records)
         ctx.res = res
+        ctx.save_for_backward(records)   # the checkpoints of the backward (segments of whole samples)
         ctx.m_start = m0.detach().to(dev, dt).contiguous()
         ctx.u = u
         ctx.checkpoint_every = checkpoint_every
@@ -58,7 +61,9 @@ class ReservoirRecords(torch.autograd.Function):
         res = ctx.res
         dt = torch.float64 if res.dtype == "f64" else torch.float32
         g = grad_records.to(dt).contiguous()
-        out = res.adjoint_device(ctx.m_start, ctx.u, grad_states_dev=g, checkpoint_every=ctx.checkpoint_every)
+        records, = ctx.saved_tensors
+        out = res.adjoint_device(ctx.m_start, ctx.u, grad_states_dev=g, checkpoint_every=ctx.checkpoint_every,
+                                 records_dev=records if ctx.checkpoint_every % res.substeps == 0 else None)
         W, w_in, m0, a_cp, a_in, h_s, h_appl = ctx.like
         cast = lambda x, like: x.to(like.device, like.dtype).reshape(like.shape)
         sc = out["scalars"]

@@ -4,7 +4,7 @@ Times every compiled launch shape (rows of W per wave x unroll of the column
 loop) of the stage kernel on this GPU, for each element type and a ladder of
 sizes, and writes the fastest shape per size bucket into
 ``csrc/stream_tune.hpp`` (the table the library consults).  Rebuild the
-library afterwards (``python -m paper_2312_01121_amd._build``).
+library afterwards (``python paper_2312_01121_amd/_build.py``).
 
 Usage (on the GPU): python -m paper_2312_01121_amd.autotune [--write [PATH]] [--samples S]
 """

@@ -357,7 +357,7 @@ constexpr int64_t kAdjointTraceBudget = int64_t(4) << 30;
 template <typename T>
 sto_status adjoint_dispatch(sto_reservoir* r, const void* m_start, const double* u, int64_t steps, const void* g_rec,
                             const void* g_fin, void* g_W, void* g_win, void* g_m0, double* g_scal, int64_t seg,
-                            hipStream_t stream) {
+                            const void* records, hipStream_t stream) {
     sto::AdjArgs<T> a;
     a.W = static_cast<const T*>(r->W);
     a.Wt = static_cast<const T*>(r->Wt);
@@ -375,6 +375,7 @@ sto_status adjoint_dispatch(sto_reservoir* r, const void* m_start, const double*
     a.m_start = static_cast<const T*>(m_start);
     a.g_rec = static_cast<const T*>(g_rec);
     a.g_fin = static_cast<const T*>(g_fin);
+    a.records = static_cast<const T*>(records);
     a.g_W = static_cast<T*>(g_W);
     a.g_win = static_cast<T*>(g_win);
     a.g_m0 = static_cast<T*>(g_m0);
@@ -387,9 +388,11 @@ sto_status adjoint_dispatch(sto_reservoir* r, const void* m_start, const double*
     return STO_OK;
 }
 
+// records: the run's records as the segments' checkpoints, or nullptr (the
+// checkpoints then come from a forward pass of the adjoint's own).
 sto_status adjoint_device_impl(sto_reservoir* r, const void* m_start, const void* u_dev, int64_t steps,
                                const void* g_rec, const void* g_fin, void* g_W, void* g_win, void* g_m0,
-                               double* g_scal, int64_t checkpoint_every, hipStream_t stream) {
+                               double* g_scal, int64_t checkpoint_every, const void* records, hipStream_t stream) {
     if (!r) return fail(STO_E_INVALID, "handle is NULL");
     if (steps < 0 || steps % r->prm.substeps != 0)
         return fail(STO_E_INVALID, "steps (%lld) must be a non-negative multiple of substeps (%d)",
@@ -398,11 +401,19 @@ sto_status adjoint_device_impl(sto_reservoir* r, const void* m_start, const void
     if (!m_start) return fail(STO_E_INVALID, "m_start is NULL");
     if (steps > 0 && !u_dev) return fail(STO_E_INVALID, "u is NULL");
     if (checkpoint_every < 0) return fail(STO_E_INVALID, "checkpoint_every must be >= 0");
+    const int64_t sub = r->prm.substeps;
+    if (records && checkpoint_every % sub != 0)
+        return fail(STO_E_INVALID,
+                    "checkpoint_every (%lld) must be a multiple of substeps (%lld) when the records are the "
+                    "checkpoints",
+                    (long long)checkpoint_every, (long long)sub);
     int64_t seg = checkpoint_every;
     if (seg == 0) {
         const int64_t per = sto::adjoint_trace_bytes_per_step(r->ld, (int)r->elem, r->prm.coupling == STO_COUPLE_XYZ,
                                                               (int)r->streams);
         seg = std::max<int64_t>(1, std::min<int64_t>(std::max<int64_t>(steps, 1), kAdjointTraceBudget / per));
+        // records are states at sample boundaries: whole samples per segment
+        if (records) seg = std::max<int64_t>(sub, seg / sub * sub);
     }
     {
         sto_status ts = ensure_transpose(r, stream);
@@ -413,9 +424,9 @@ sto_status adjoint_device_impl(sto_reservoir* r, const void* m_start, const void
     const double* u = static_cast<const double*>(u_dev);
     sto_status st = r->dtype == STO_F64
                         ? adjoint_dispatch<double>(r, m_start, u, steps, g_rec, g_fin, g_W, g_win, g_m0, g_scal, seg,
-                                                   stream)
+                                                   records, stream)
                         : adjoint_dispatch<float>(r, m_start, u, steps, g_rec, g_fin, g_W, g_win, g_m0, g_scal, seg,
-                                                  stream);
+                                                  records, stream);
     if (st != STO_OK) return st;
     int bad = none;
     HIP_TRY(hipMemcpyAsync(&bad, r->bad, sizeof(int), hipMemcpyDeviceToHost, stream), "flag read");
@@ -761,7 +772,18 @@ sto_status reservoir_adjoint_device(sto_reservoir* r, const void* m_start_dev, c
                                     void* grad_w_in_dev, void* grad_m0_dev, double* grad_scalars_dev,
                                     int64_t checkpoint_every, void* hip_stream) {
     return adjoint_device_impl(r, m_start_dev, u_dev, steps, grad_states_dev, grad_final_dev, grad_W_dev,
-                               grad_w_in_dev, grad_m0_dev, grad_scalars_dev, checkpoint_every,
+                               grad_w_in_dev, grad_m0_dev, grad_scalars_dev, checkpoint_every, nullptr,
+                               static_cast<hipStream_t>(hip_stream));
+}
+
+sto_status reservoir_adjoint_records_device(sto_reservoir* r, const void* m_start_dev, const void* u_dev,
+                                            int64_t steps, const void* records_dev, const void* grad_states_dev,
+                                            const void* grad_final_dev, void* grad_W_dev, void* grad_w_in_dev,
+                                            void* grad_m0_dev, double* grad_scalars_dev, int64_t checkpoint_every,
+                                            void* hip_stream) {
+    if (!records_dev) return fail(STO_E_INVALID, "records is NULL");
+    return adjoint_device_impl(r, m_start_dev, u_dev, steps, grad_states_dev, grad_final_dev, grad_W_dev,
+                               grad_w_in_dev, grad_m0_dev, grad_scalars_dev, checkpoint_every, records_dev,
                                static_cast<hipStream_t>(hip_stream));
 }
 
@@ -804,7 +826,7 @@ sto_status reservoir_adjoint(sto_reservoir* r, const double* m_start, const doub
         st = fail(STO_E_NOMEM, "hipMalloc scalars");
     if (st == STO_OK)
         st = adjoint_device_impl(r, m_d, u_d, steps, gr_d, gf_d, gw_d, gwin_d, gm_d, gs_d, checkpoint_every,
-                                 r->stream);
+                                 nullptr, r->stream);
     if (st == STO_OK) st = from_device(r, gw_d, n * n, grad_W);
     if (st == STO_OK) st = from_device(r, gwin_d, n * r->n_in, grad_w_in);
     if (st == STO_OK) st = from_device(r, gm_d, S * n * 3, grad_m0);

@@ -554,7 +554,7 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
     ADJ_TRY(mem.get(&d.abar, vec));
     ADJ_TRY(mem.get(&d.mbar, vec));
     ADJ_TRY(mem.get(&d.loc, vec));
-    ADJ_TRY(mem.get(&cps, vec * (size_t)nseg));
+    if (!a.records) ADJ_TRY(mem.get(&cps, vec * (size_t)nseg));
     ADJ_TRY(mem.get(&d.xt, (size_t)K * 4 * 3 * per_stage));
     ADJ_TRY(mem.get(&d.wx, (size_t)K * 4 * C * per_stage));
     ADJ_TRY(mem.get(&d.st, (size_t)K * 4 * C * per_stage));
@@ -659,16 +659,25 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
         hipLaunchKernelGGL(k_load_state<T>, pgrid, pblock, 0, st, a.m_start, d.m, d.ms[0], n, ld);
         ADJ_TRY(hipGetLastError());
     }
-    // pass 1: checkpoints; the last segment is traced directly
-    for (int64_t g = 0; g < nseg; ++g) {
-        const int64_t j0 = g * K, kn = std::min(K, NSTEP - j0);
-        ADJ_TRY(hipMemcpyAsync(cps + (size_t)g * 3 * ld * NS, d.m, vec, hipMemcpyDeviceToDevice, st));
-        ADJ_TRY(forward(j0, kn, g == nseg - 1));
+    // pass 1: checkpoints; the last segment is traced directly.  With the
+    // run's records the state at the start of segment g > 0 is the record
+    // of sample g K / substeps - 1, and pass 1 is not needed.
+    if (!a.records) {
+        for (int64_t g = 0; g < nseg; ++g) {
+            const int64_t j0 = g * K, kn = std::min(K, NSTEP - j0);
+            ADJ_TRY(hipMemcpyAsync(cps + (size_t)g * 3 * ld * NS, d.m, vec, hipMemcpyDeviceToDevice, st));
+            ADJ_TRY(forward(j0, kn, g == nseg - 1));
+        }
     }
     int gw_started = 0;
     for (int64_t g = nseg - 1; g >= 0; --g) {
         const int64_t j0 = g * K, kn = std::min(K, NSTEP - j0);
-        if (g < nseg - 1) {
+        if (a.records) {
+            const T* src = g == 0 ? a.m_start : a.records + (j0 / a.substeps - 1) * (int64_t)NS * n * 3;
+            hipLaunchKernelGGL(k_load_state<T>, pgrid, pblock, 0, st, src, d.m, d.ms[0], n, ld);
+            ADJ_TRY(hipGetLastError());
+            ADJ_TRY(forward(j0, kn, 1));
+        } else if (g < nseg - 1) {
             ADJ_TRY(hipMemcpyAsync(d.m, cps + (size_t)g * 3 * ld * NS, vec, hipMemcpyDeviceToDevice, st));
             ADJ_TRY(hipMemcpyAsync(d.ms[0], d.m, vec, hipMemcpyDeviceToDevice, st));
             ADJ_TRY(forward(j0, kn, 1));

@@ -23,6 +23,8 @@ struct AdjArgs {
     const T* m_start;    // device, S x n x 3 AoS
     const T* g_rec;      // device, (steps / substeps) x S x n x 3 AoS: dL/d(record); or nullptr
     const T* g_fin;      // device, S x n x 3 AoS: dL/d(final state); or nullptr
+    const T* records;    // device, (steps / substeps) x S x n x 3 AoS: the run's records, which then serve as
+                         // the segments' checkpoints (seg_steps a multiple of substeps); or nullptr
     // outputs (device; each may be nullptr)
     T* g_W;              // n x n, row-major, no padding
     T* g_win;            // n x n_in

@@ -153,6 +153,59 @@ def test_adjoint_device_api(stx):
         assert np.array_equal(only["scalars"].cpu().numpy(), out["scalars"].cpu().numpy())
 
 
+@pytest.mark.parametrize("dtype,S,coupling,renorm,seg", [("f64", 1, "x", False, 10), ("f64", 1, "xyz", True, 0),
+                                                         ("f32", 1, "x", False, 15), ("f32", 5, "xyz", True, 10),
+                                                         ("f32", 3, "x", False, 0)])
+def test_adjoint_records_as_checkpoints(stx, dtype, S, coupling, renorm, seg):
+    """reservoir_adjoint_records_device takes its checkpoints from the run's
+    records instead of a forward pass of its own: the same gradients as
+    reservoir_adjoint_device (bitwise in FP64, where every path rounds the
+    stage sums exactly), and the oracle's."""
+    import torch
+    dev = torch.device("cuda")
+    n, samples, sub = 40, 6, 5
+    rng = np.random.default_rng(41)
+    w, w_in, m0, _ = random_case(n, seed=43, samples=1, spread=0.3)
+    m0s = m0 if S == 1 else unit_states(rng, S, n)
+    lead = (samples,) if S == 1 else (samples, S)
+    u = rng.uniform(-1, 1, lead + (1,))
+    prm = oracle_params(a_cp=0.3, a_in=0.7, substeps=sub, coupling=coupling, renormalize=renorm)
+    g_rec = rng.standard_normal(lead + (n, 3))
+    g_fin = rng.standard_normal(m0s.shape)
+    m0_ref = m0s
+    if dtype == "f32":
+        w, w_in, g_rec, g_fin, m0_ref = (np.float32(a).astype(np.float64) for a in (w, w_in, g_rec, g_fin, m0s))
+    say(f"adjoint records {dtype} S={S} {coupling} renorm={renorm} seg={seg}")
+    if S == 1:
+        ref = adjoint.run_adjoint(w, w_in, m0_ref, u, prm, g_rec, g_fin, dot="blas")
+    else:
+        ref = oracle_streams_adjoint(w, w_in, m0_ref, u, prm, g_rec, g_fin)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    t = lambda a, dt=tdt: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+    host = lambda o: {**{k: o[k].cpu().numpy() for k in ("W", "w_in", "m0")},  # noqa: E731
+                      **{k: float(v) for k, v in zip(SCALARS, o["scalars"].cpu().numpy())}}
+    with stx.Reservoir(w, w_in, m0s, lib_params(prm, dtype), streams=S) as r:
+        u_d = t(u, torch.float64)
+        records = torch.empty(lead + (n, 3), dtype=tdt, device=dev)
+        r.run_device(u_d, records)
+        args = dict(grad_states_dev=t(g_rec), grad_final_dev=t(g_fin), checkpoint_every=seg)
+        own = host(r.adjoint_device(t(m0s), u_d, **args))
+        from_rec = host(r.adjoint_device(t(m0s), u_d, records_dev=records, **args))
+        torch.cuda.synchronize()
+        if dtype == "f64":
+            for k in ("W", "w_in", "m0"):
+                assert np.array_equal(from_rec[k], own[k]), k
+            for k in SCALARS:
+                assert from_rec[k] == own[k], k
+        else:
+            compare(from_rec, own, F32_TOL, "records vs own checkpoints")
+        compare(from_rec, ref, F64_TOL if dtype == "f64" else F32_TOL, "records vs oracle")
+        # segments must be whole samples when the records are the checkpoints
+        with pytest.raises(stx.StoError) as ei:
+            r.adjoint_device(t(m0s), u_d, records_dev=records, grad_states_dev=t(g_rec), checkpoint_every=sub + 2)
+        assert ei.value.status == stx.STO_E_INVALID
+
+
 def test_adjoint_zero_steps(stx):
     w, w_in, m0, u, prm, g_rec, g_fin = case(8, seed=4)
     with stx.Reservoir(w, w_in, m0, lib_params(prm, "f64")) as r:

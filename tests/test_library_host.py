@@ -18,9 +18,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 @pytest.fixture(scope="module")
 def stx():
-    from paper_2312_01121_amd import _build
-    if not os.path.exists(_build.LIB):
-        _build.build()
+    if not os.path.exists(os.path.join(ROOT, "paper_2312_01121_amd", "libsto_reservoir.so")):
+        import __graft_entry__
+        __graft_entry__.build()   # loads the build script by path, not through the package
     import paper_2312_01121_amd
     return paper_2312_01121_amd
 
@@ -138,6 +138,11 @@ def test_adjoint_rejects_bad_arguments(stx):
     assert lib.reservoir_adjoint(None, dp(m), dp(u), 20, None, None, None, None, None, None, 0) == stx.STO_E_INVALID
     assert lib.reservoir_adjoint_device(None, None, None, 20, None, None, None, None, None, None, 0,
                                         None) == stx.STO_E_INVALID
+    # the records variant: records NULL, then a NULL handle
+    assert lib.reservoir_adjoint_records_device(None, None, None, 20, None, None, None, None, None, None, None, 0,
+                                                None) == stx.STO_E_INVALID
+    assert lib.reservoir_adjoint_records_device(None, None, None, 20, m.ctypes.data, None, None, None, None, None,
+                                                None, 0, None) == stx.STO_E_INVALID
     assert lib.readout_grad_device(None, 0, 10, 3, None, 2, 1e-6, 0, None, None, None, None) == stx.STO_E_INVALID
 
 
