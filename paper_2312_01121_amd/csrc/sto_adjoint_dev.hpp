@@ -180,42 +180,72 @@ __device__ __forceinline__ void stage_vjp(const AdjDev<T>& d, const Coef<T>& k, 
     vjp_apply<T, XYZ>(d, k, i, s, kk, stage, vjp_load<T, XYZ>(d, i, s, kk, stage), vx, vy, vz, sink);
 }
 
-// Start reversing local step kk (global step j = j0 + kk) of stream s:
-// a = dL/dm_{j+1} (carry plus the loss gradient on m_{j+1}), reversed
-// through the optional projection; then the pointwise adjoint of its last
-// stage.  mhat: the state m_{j+1} (after projection) of stream s, [3][ld];
-// pn: the norm of m_{j+1} before projection.
-template <typename T, bool XYZ, class Sink>
-__device__ __forceinline__ void prep_step(const AdjDev<T>& d, const Coef<T>& k, int i, int s, int kk, const T* mhat,
-                                          T pn, T cx, T cy, T cz, Sink& sink) {
+// Inputs of prep_apply for local step kk at node i of stream s: the loss
+// gradients on m_{j+1} (each read only where it applies), the state m_{j+1}
+// after projection and its norm before it, and the inputs of the pointwise
+// adjoint of the step's last stage; none depends on a coupling sum.
+template <typename T>
+struct PrepIn {
+    T gr[3], gf[3], mh[3], pn;
+    VjpIn<T> v;
+};
+
+// mhat: the state m_{j+1} (after projection) of stream s, [3][ld]; pn: the
+// norm of m_{j+1} before projection.
+template <typename T, bool XYZ>
+__device__ __forceinline__ PrepIn<T> prep_load(const AdjDev<T>& d, int i, int s, int kk, const T* mhat, T pn) {
     const int64_t ld = d.ld;
     const int64_t jn = d.j0 + kk + 1;   // index of the state this step produces
-    T a[3] = {cx, cy, cz};
+    PrepIn<T> in;
+    for (int c = 0; c < 3; ++c) in.gr[c] = in.gf[c] = in.mh[c] = T(0);
     if (d.g_rec && jn % d.substeps == 0) {
         const T* g = d.g_rec + (((jn / d.substeps - 1) * d.S + s) * d.n + i) * 3;
-        a[0] += g[0];
-        a[1] += g[1];
-        a[2] += g[2];
+        for (int c = 0; c < 3; ++c) in.gr[c] = g[c];
     }
     if (d.g_fin && jn == d.steps) {
         const T* g = d.g_fin + ((int64_t)s * d.n + i) * 3;
-        a[0] += g[0];
-        a[1] += g[1];
-        a[2] += g[2];
+        for (int c = 0; c < 3; ++c) in.gf[c] = g[c];
     }
+    if (d.renorm)
+        for (int c = 0; c < 3; ++c) in.mh[c] = mhat[c * ld + i];
+    in.pn = pn;
+    in.v = vjp_load<T, XYZ>(d, i, s, kk, 3);
+    return in;
+}
+
+// Start reversing local step kk (global step j = j0 + kk) of stream s:
+// a = dL/dm_{j+1} (carry plus the loss gradient on m_{j+1}), reversed
+// through the optional projection; then the pointwise adjoint of its last
+// stage.
+template <typename T, bool XYZ, class Sink>
+__device__ __forceinline__ void prep_apply(const AdjDev<T>& d, const Coef<T>& k, int i, int s, int kk,
+                                           const PrepIn<T>& in, T cx, T cy, T cz, Sink& sink) {
+    const int64_t ld = d.ld;
+    const int64_t jn = d.j0 + kk + 1;
+    T a[3] = {cx, cy, cz};
+    if (d.g_rec && jn % d.substeps == 0)
+        for (int c = 0; c < 3; ++c) a[c] += in.gr[c];
+    if (d.g_fin && jn == d.steps)
+        for (int c = 0; c < 3; ++c) a[c] += in.gf[c];
     if (d.renorm) {
-        const T ux = mhat[i], uy = mhat[ld + i], uz = mhat[2 * ld + i];
+        const T ux = in.mh[0], uy = in.mh[1], uz = in.mh[2];
         const T ao = (a[0] * ux + a[1] * uy) + a[2] * uz;
-        a[0] = (a[0] - ao * ux) / pn;
-        a[1] = (a[1] - ao * uy) / pn;
-        a[2] = (a[2] - ao * uz) / pn;
+        a[0] = (a[0] - ao * ux) / in.pn;
+        a[1] = (a[1] - ao * uy) / in.pn;
+        a[2] = (a[2] - ao * uz) / in.pn;
     }
     const int64_t sb = (int64_t)s * 3 * ld;
     for (int c = 0; c < 3; ++c) {
         d.abar[sb + c * ld + i] = a[c];
         d.mbar[sb + c * ld + i] = a[c];
     }
-    stage_vjp<T, XYZ>(d, k, i, s, kk, 3, k.h6 * a[0], k.h6 * a[1], k.h6 * a[2], sink);
+    vjp_apply<T, XYZ>(d, k, i, s, kk, 3, in.v, k.h6 * a[0], k.h6 * a[1], k.h6 * a[2], sink);
+}
+
+template <typename T, bool XYZ, class Sink>
+__device__ __forceinline__ void prep_step(const AdjDev<T>& d, const Coef<T>& k, int i, int s, int kk, const T* mhat,
+                                          T pn, T cx, T cy, T cz, Sink& sink) {
+    prep_apply<T, XYZ>(d, k, i, s, kk, prep_load<T, XYZ>(d, i, s, kk, mhat, pn), cx, cy, cz, sink);
 }
 
 // Inputs of a forward stage's epilogue at node i of stream s (stage input,
@@ -326,7 +356,7 @@ __device__ __forceinline__ void fwd_epilogue(const AdjDev<T>& d, const Coef<T>& 
 template <typename T>
 struct RevIn {
     T lc[3], mb[3], ab[3];
-    VjpIn<T> v;
+    PrepIn<T> p;   // p.v: the next stage's pointwise adjoint inputs; all of p when that stage starts the previous step
 };
 
 template <typename T, bool XYZ>
@@ -339,7 +369,15 @@ __device__ __forceinline__ RevIn<T> rev_load(const AdjDev<T>& d, int i, int s, i
         in.mb[c] = d.mbar[sb + c * ld + i];
         in.ab[c] = d.abar[sb + c * ld + i];
     }
-    if (stage > 0) in.v = vjp_load<T, XYZ>(d, i, s, kk, stage - 1);
+    if (stage > 0) {
+        in.p.v = vjp_load<T, XYZ>(d, i, s, kk, stage - 1);
+    } else if (kk > 0) {
+        // the first stage of step kk is reversed: the previous step starts,
+        // and its output m_{j0+kk} is the traced first stage input of step kk
+        const T* mhat = d.xt + adj_slot<3>(kk, 0, d.S, ld) + sb;
+        const T pn = d.renorm ? d.pn[((int64_t)(kk - 1) * d.S + s) * ld + i] : T(1);
+        in.p = prep_load<T, XYZ>(d, i, s, kk - 1, mhat, pn);
+    }
     return in;
 }
 
@@ -369,13 +407,10 @@ __device__ __forceinline__ void rev_finish(const AdjDev<T>& d, const Coef<T>& k,
         const T v0 = wgt * in.ab[0] + hst * xb[0];
         const T v1 = wgt * in.ab[1] + hst * xb[1];
         const T v2 = wgt * in.ab[2] + hst * xb[2];
-        vjp_apply<T, XYZ>(d, k, i, s, kk, stage - 1, in.v, v0, v1, v2, sink);
+        vjp_apply<T, XYZ>(d, k, i, s, kk, stage - 1, in.p.v, v0, v1, v2, sink);
     } else if (kk > 0) {
-        // step j = j0 + kk is reversed: mbar = dL/dm_j.  Start step j - 1,
-        // whose output m_j is the first stage input of step j.
-        const T* mhat = d.xt + adj_slot<3>(kk, 0, d.S, ld) + sb;
-        const T pn = d.renorm ? d.pn[((int64_t)(kk - 1) * d.S + s) * ld + i] : T(1);
-        prep_step<T, XYZ>(d, k, i, s, kk - 1, mhat, pn, mb[0], mb[1], mb[2], sink);
+        // step j = j0 + kk is reversed: mbar = dL/dm_j.  Start step j - 1.
+        prep_apply<T, XYZ>(d, k, i, s, kk - 1, in.p, mb[0], mb[1], mb[2], sink);
     }
 }
 
