@@ -238,6 +238,9 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
                     for (int w = 1; w < kWaves; ++w) v += cs[((tc * kWaves + w) * kTile + ti) * kTile + col];
                     dot[c] = v;
                 }
+                // the re-arm stores must complete before the publish below;
+                // the trace stores need not
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
                 if constexpr (TRACE) {
                     if (mine) {
                         const int64_t slot = ((int64_t)(s * substeps + sub) * 4 + stage) * streams + strm;
@@ -279,8 +282,6 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
                 sz = nz;
                 if (mine) {
                     const int64_t o = (int64_t)strm * ld + node;
-                    // the re-arm stores must complete before the publish
-                    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
                     __hip_atomic_store(xout + o, nx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if constexpr (XYZ) {
                         __hip_atomic_store(xout + cstride + o, ny, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
