@@ -355,6 +355,33 @@ def test_adjoint_streams_reverse_kernels_agree(stx, coupling, n, S, seg, renorm,
     compare(got["1"], got["0"], F32_TOL, "persistent vs per-stage reverse")
 
 
+@pytest.mark.parametrize("n_in,coupling", [(3, "xyz"), (4, "x"), (5, "xyz")])
+def test_adjoint_streams_several_inputs(stx, n_in, coupling, monkeypatch):
+    """Several input channels: dL/dw_in of every channel (summed in
+    registers over a segment by the persistent reverse for up to 4 channels;
+    5 channels reverse on the per-stage kernels), against the oracle and
+    against the per-stage reverse."""
+    n, S, samples, sub = 60, 6, 2, 4
+    w, w_in, _, _ = random_case(n, n_in=n_in, seed=51, samples=1, spread=0.3)
+    rng = np.random.default_rng(52)
+    m0s = unit_states(rng, S, n)
+    u = rng.uniform(-1, 1, (samples, S, n_in))
+    prm = oracle_params(a_cp=0.3, a_in=0.7, substeps=sub, coupling=coupling, renormalize=False)
+    g_rec = np.float32(rng.standard_normal((samples, S, n, 3))).astype(np.float64)
+    g_fin = np.float32(rng.standard_normal((S, n, 3))).astype(np.float64)
+    w, w_in = (np.float32(a).astype(np.float64) for a in (w, w_in))
+    ref = oracle_streams_adjoint(w, w_in, np.float32(m0s).astype(np.float64), u, prm, g_rec, g_fin)
+    got = {}
+    for rev in ("1", "0"):
+        monkeypatch.setenv("STO_MULTI_REVERSE", rev)
+        say(f"adjoint streams n_in={n_in} {coupling} reverse={rev}")
+        with stx.Reservoir(w, w_in, m0s, lib_params(prm, "f32"), streams=S) as r:
+            assert r.path == "multi"
+            got[rev] = r.adjoint(m0s, u, g_rec, g_fin, checkpoint_every=sub)
+        compare(got[rev], ref, F32_TOL, f"streams n_in={n_in} reverse={rev}")
+    compare(got["1"], got["0"], F32_TOL, "persistent vs per-stage reverse")
+
+
 def test_adjoint_streams64_xyz_oracle_and_central_fd(stx):
     """The differentiation workload's shape: N = 512, 64 input streams sharing
     W, all three components coupled (the N x 192 product), one input sample
