@@ -384,6 +384,10 @@ sto_status adjoint_dispatch(sto_reservoir* r, const void* m_start, const double*
     a.bad = r->bad;
     a.stream = stream;
     hipError_t e = sto::adjoint_run<T>(a);
+    if (e == hipErrorLaunchTimeOut)
+        return fail(STO_E_DEVICE,
+                    "adjoint: the stage exchange of a persistent kernel timed out (its workgroups were not "
+                    "co-resident)");
     if (e != hipSuccess) return hip_fail(e, "adjoint");
     return STO_OK;
 }
