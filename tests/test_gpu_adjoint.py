@@ -328,12 +328,13 @@ def test_adjoint_streams_matches_oracle(stx, coupling, seg, renorm):
 
 
 @pytest.mark.parametrize("coupling,n,S,seg,renorm", [("xyz", 300, 7, 0, True), ("x", 130, 20, 8, False),
-                                                     ("xyz", 40, 3, 4, False)])
+                                                     ("xyz", 40, 3, 4, False), ("xyz", 700, 6, 4, False),
+                                                     ("x", 1000, 3, 0, True)])
 def test_adjoint_streams_reverse_kernels_agree(stx, coupling, n, S, seg, renorm, monkeypatch):
     """The reversed stages on the persistent kernel (several 16-node tiles
-    and stream groups with a ragged last group) and on the per-stage
-    kernels (STO_MULTI_REVERSE=0), both against the oracle and against
-    each other."""
+    and stream groups with a ragged last group; every register-slice size of
+    W, up to N = 1,000) and on the per-stage kernels (STO_MULTI_REVERSE=0),
+    both against the oracle and against each other."""
     samples, sub = 2, 4
     w, w_in, _, _ = random_case(n, seed=31, samples=1, spread=0.3)
     rng = np.random.default_rng(32)
