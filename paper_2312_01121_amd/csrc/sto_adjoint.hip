@@ -569,9 +569,11 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
     ADJ_TRY(hipMemsetAsync(d.gwin, 0, (size_t)std::max(1, a.n_in) * NS * ld * sizeof(double), st));
 
     // FP32 dL/dW: the contraction is split into slices when the output has
-    // too few 128 x 128 tiles to fill the GPU (small n, long segments)
+    // too few 128 x 128 tiles to fill the GPU (small n, long segments); at
+    // most 64 slices, or STO_GW_SPLITS (1 to 256) for measurements
     const int gw_tiles = ((n + 127) / 128) * ((n + 127) / 128);
-    auto gw_splits = [&](int L) { return std::max(1, std::min({64, 2048 / gw_tiles, L / 256})); };
+    const int gw_max = std::min(256, std::max(1, env_int("STO_GW_SPLITS", 64)));
+    auto gw_splits = [&](int L) { return std::max(1, std::min({gw_max, 2048 / gw_tiles, L / 256})); };
     float* gw_part = nullptr;
     if (sizeof(T) == 4 && a.g_W) {
         const int smax = gw_splits((int)(K * 4 * NS * C));
