@@ -341,13 +341,9 @@ struct RegSink {
     }
 };
 
-// Row tiles of 16 nodes per workgroup of the reverse kernel: both share the
-// gathered columns, and every thread of the workgroup owns a pair.
-constexpr int kRevTiles = 2;
-
 // Reversed stages of one adjoint segment in one cooperative launch: per
-// stage t = W^T bbar for all streams (the exchange of k_multi, with the
-// transpose of W as the A operands and two row tiles per workgroup), then
+// stage t = W^T bbar for all streams (the exchange and the RT row tiles per
+// workgroup of k_multi, with the transpose of W as the A operands), then
 // each pair's adjoint epilogue (rev_load / rev_finish, as the per-stage
 // kernels run it).  Each pair's epilogue inputs are loaded before the
 // gather, so their latency hides behind the wait for the other workgroups;
@@ -355,7 +351,7 @@ constexpr int kRevTiles = 2;
 // leaves the next stage's bbar in the trace of coupling adjoints and
 // publishes it through the rotating buffers.  Stages run from (kn - 1, 3)
 // down to (0, 0); buffer 0 starts with the bbar of (kn - 1, 3).
-template <int KREG, bool XYZ>
+template <int KREG, bool XYZ, int RT>
 __global__ void __launch_bounds__(kBlock) k_multi_rev(AdjDev<float> d, Coef<float> k, float* __restrict__ xbuf,
                                                       int* sync, int kn) {
     constexpr int C = XYZ ? 3 : 1;
@@ -368,10 +364,10 @@ __global__ void __launch_bounds__(kBlock) k_multi_rev(AdjDev<float> d, Coef<floa
     const int streams = d.S;
     const int kp = (n + 31) / 32 * 32;
     float* xs = reinterpret_cast<float*>(smem_raw);              // [kp][kXP]
-    float* cs = xs + (int64_t)kp * kXP;                          // [kRevTiles][kWaves][16][16]
+    float* cs = xs + (int64_t)kp * kXP;                          // [RT][kWaves][16][16]
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int row0 = blockIdx.x * kTile * kRevTiles;
+    const int row0 = blockIdx.x * kTile * RT;
     const int s0 = blockIdx.y * SPW;
     const int ns = min(SPW, streams - s0);
     int* abort_flag = sync + kSyncAbortWord;
@@ -380,9 +376,9 @@ __global__ void __launch_bounds__(kBlock) k_multi_rev(AdjDev<float> d, Coef<floa
 
     const int kq = kp / kWaves;
     const int steps = kq / 4;
-    float areg[kRevTiles][KREG];
+    float areg[RT][KREG];
 #pragma unroll
-    for (int rt = 0; rt < kRevTiles; ++rt) {
+    for (int rt = 0; rt < RT; ++rt) {
         const int r = row0 + rt * kTile + (lane & 15);
 #pragma unroll
         for (int t = 0; t < KREG; ++t) {
@@ -395,7 +391,7 @@ __global__ void __launch_bounds__(kBlock) k_multi_rev(AdjDev<float> d, Coef<floa
     const int js = tj / C;
     const int node = row0 + tt * kTile + ti;
     const int strm = s0 + js;
-    const bool mine = tj % C == 0 && js < ns && node < n;
+    const bool mine = tt < RT && tj % C == 0 && js < ns && node < n;
     const int64_t cstride = (int64_t)streams * ld;
     const int64_t bstride = C * cstride;
     RegSink sink;
@@ -420,21 +416,21 @@ __global__ void __launch_bounds__(kBlock) k_multi_rev(AdjDev<float> d, Coef<floa
                     __hip_atomic_store(reinterpret_cast<unsigned*>(xold + c * cstride + (int64_t)strm * ld + node), ~0u,
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            f4 acc[kRevTiles];
+            f4 acc[RT];
 #pragma unroll
-            for (int rt = 0; rt < kRevTiles; ++rt) acc[rt] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int rt = 0; rt < RT; ++rt) acc[rt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int t = 0; t < KREG; ++t) {
                 if (t < steps) {
                     const int kr = wave * kq + 4 * t + (lane >> 4);
                     const float b = xs[kr * kXP + (lane & 15)];
 #pragma unroll
-                    for (int rt = 0; rt < kRevTiles; ++rt)
+                    for (int rt = 0; rt < RT; ++rt)
                         acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[rt][t], b, acc[rt], 0, 0, 0);
                 }
             }
 #pragma unroll
-            for (int rt = 0; rt < kRevTiles; ++rt)
+            for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     cs[((rt * kWaves + wave) * kTile + 4 * (lane >> 4) + r) * kTile + (lane & 15)] = acc[rt][r];
@@ -445,7 +441,7 @@ __global__ void __launch_bounds__(kBlock) k_multi_rev(AdjDev<float> d, Coef<floa
                 const int col = min(tj + c, kTile - 1);
                 float v = 0.f;
 #pragma unroll
-                for (int w = 0; w < kWaves; ++w) v += cs[((tt * kWaves + w) * kTile + ti) * kTile + col];
+                for (int w = 0; w < kWaves; ++w) v += cs[((min(tt, RT - 1) * kWaves + w) * kTile + ti) * kTile + col];
                 t3[c] = v;
             }
             // the re-arm stores must complete before the publish below; the
@@ -507,9 +503,12 @@ int kreg_for(int n) {
 }
 
 template <int KREG>
-const void* multi_rev_kernel(int xyz) {
-    return xyz ? reinterpret_cast<const void*>(&k_multi_rev<KREG, true>)
-               : reinterpret_cast<const void*>(&k_multi_rev<KREG, false>);
+const void* multi_rev_kernel(int xyz, int rt) {
+    if (rt == 2)
+        return xyz ? reinterpret_cast<const void*>(&k_multi_rev<KREG, true, 2>)
+                   : reinterpret_cast<const void*>(&k_multi_rev<KREG, false, 2>);
+    return xyz ? reinterpret_cast<const void*>(&k_multi_rev<KREG, true, 1>)
+               : reinterpret_cast<const void*>(&k_multi_rev<KREG, false, 1>);
 }
 
 template <int KREG, int RT>
@@ -545,13 +544,12 @@ namespace {
 // limit raised to what it needs; nullptr when n is out of range.
 // trace: 0 forward, 1 forward with the adjoint's trace, 2 reversed stages.
 const void* multi_fn(int n, int xyz, int trace, int rt) {
-    if (trace == 2 && rt != kRevTiles) return nullptr;
     const void* fn = nullptr;
     switch (kreg_for(n)) {
-        case 4: fn = trace == 2 ? multi_rev_kernel<4>(xyz) : multi_kernel<4>(xyz, trace, rt); break;
-        case 8: fn = trace == 2 ? multi_rev_kernel<8>(xyz) : multi_kernel<8>(xyz, trace, rt); break;
-        case 16: fn = trace == 2 ? multi_rev_kernel<16>(xyz) : multi_kernel<16>(xyz, trace, rt); break;
-        case 32: fn = trace == 2 ? multi_rev_kernel<32>(xyz) : multi_kernel<32>(xyz, trace, rt); break;
+        case 4: fn = trace == 2 ? multi_rev_kernel<4>(xyz, rt) : multi_kernel<4>(xyz, trace, rt); break;
+        case 8: fn = trace == 2 ? multi_rev_kernel<8>(xyz, rt) : multi_kernel<8>(xyz, trace, rt); break;
+        case 16: fn = trace == 2 ? multi_rev_kernel<16>(xyz, rt) : multi_kernel<16>(xyz, trace, rt); break;
+        case 32: fn = trace == 2 ? multi_rev_kernel<32>(xyz, rt) : multi_kernel<32>(xyz, trace, rt); break;
         default: return nullptr;
     }
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes(n, rt)) != hipSuccess)
@@ -594,16 +592,15 @@ bool fits_rt(int n, int streams, int xyz, int trace, int rt, Shape* sh) {
     return true;
 }
 
-// The launch shape of an instance, or false when none is co-resident.  The
-// reverse takes two row tiles per workgroup.  The forward takes two when a
-// grid of one-tile workgroups would need more than one per CU (the tiles
-// then share one gather of the columns: at 64 streams x N = 512 with
-// isotropic coupling 18.2 us per RK4 step against 24.4), else one (with
-// m^x coupling, 128 one-tile workgroups took 16.8 us per step and 64
-// two-tile ones 18.8); STO_MULTI_TILES=1 or 2 chooses for measurements.
+// The launch shape of an instance, or false when none is co-resident.  Two
+// row tiles per workgroup when a grid of one-tile workgroups would need more
+// than one per CU (the tiles then share one gather of the columns: at 64
+// streams x N = 512 with isotropic coupling 18.2 us per RK4 step against
+// 24.4), else one (with m^x coupling, 128 one-tile workgroups took 16.8 us
+// per step and 64 two-tile ones 18.8); the same for the reverse.
+// STO_MULTI_TILES=1 or 2 chooses for measurements.
 bool fits(int n, int streams, int xyz, int trace, Shape* sh) {
     if (n < 1 || streams < 1 || n > 32 * kMaxKreg) return false;
-    if (trace == 2) return fits_rt(n, streams, xyz, trace, kRevTiles, sh);
     const char* env = getenv("STO_MULTI_TILES");
     const int forced = env ? atoi(env) : 0;
     if (forced == 1 || forced == 2) return fits_rt(n, streams, xyz, trace, forced, sh);

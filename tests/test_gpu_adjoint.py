@@ -333,8 +333,9 @@ def test_adjoint_streams_matches_oracle(stx, coupling, seg, renorm):
 def test_adjoint_streams_reverse_kernels_agree(stx, coupling, n, S, seg, renorm, monkeypatch):
     """The reversed stages on the persistent kernel (several 16-node tiles
     and stream groups with a ragged last group; every register-slice size of
-    W, up to N = 1,000) and on the per-stage kernels (STO_MULTI_REVERSE=0),
-    both against the oracle and against each other."""
+    W, up to N = 1,000; one and two row tiles per workgroup) and on the
+    per-stage kernels (STO_MULTI_REVERSE=0), against the oracle and against
+    each other."""
     samples, sub = 2, 4
     w, w_in, _, _ = random_case(n, seed=31, samples=1, spread=0.3)
     rng = np.random.default_rng(32)
@@ -346,14 +347,21 @@ def test_adjoint_streams_reverse_kernels_agree(stx, coupling, n, S, seg, renorm,
     w, w_in = (np.float32(a).astype(np.float64) for a in (w, w_in))
     ref = oracle_streams_adjoint(w, w_in, np.float32(m0s).astype(np.float64), u, prm, g_rec, g_fin)
     got = {}
-    for rev in ("1", "0"):
+    # persistent reverse with the library's choice of row tiles, with two
+    # row tiles per workgroup forced, and the per-stage reverse
+    for key, rev, tiles in (("auto", "1", None), ("two", "1", "2"), ("stage", "0", None)):
         monkeypatch.setenv("STO_MULTI_REVERSE", rev)
-        say(f"adjoint streams reverse={rev} S={S} n={n} {coupling} seg={seg} renorm={renorm}")
+        if tiles:
+            monkeypatch.setenv("STO_MULTI_TILES", tiles)
+        else:
+            monkeypatch.delenv("STO_MULTI_TILES", raising=False)
+        say(f"adjoint streams {key} S={S} n={n} {coupling} seg={seg} renorm={renorm}")
         with stx.Reservoir(w, w_in, m0s, lib_params(prm, "f32"), streams=S) as r:
             assert r.path == "multi"
-            got[rev] = r.adjoint(m0s, u, g_rec, g_fin, checkpoint_every=seg)
-        compare(got[rev], ref, F32_TOL, f"streams reverse={rev} {coupling}")
-    compare(got["1"], got["0"], F32_TOL, "persistent vs per-stage reverse")
+            got[key] = r.adjoint(m0s, u, g_rec, g_fin, checkpoint_every=seg)
+        compare(got[key], ref, F32_TOL, f"streams {key} {coupling}")
+    compare(got["auto"], got["stage"], F32_TOL, "persistent vs per-stage reverse")
+    compare(got["two"], got["stage"], F32_TOL, "two row tiles vs per-stage reverse")
 
 
 @pytest.mark.parametrize("n_in,coupling", [(3, "xyz"), (4, "x"), (5, "xyz")])
