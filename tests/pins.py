@@ -381,6 +381,103 @@ def pin_continuation(runner=default_runner, rhs=sto.field, step=None, **_):
     assert np.array_equal(np.concatenate([r1, r2]), rec) and np.array_equal(f2, fin)
 
 
+# --------------------------------------------------------------------------
+# Renormalisation: projected precession in closed form
+# --------------------------------------------------------------------------
+def pin_renormalize(rhs=sto.field, step=None, runner=default_runner, **_):
+    """Optional projection after each step (off by default).
+
+    With alpha = 0, h_k = 0, no current, W = 0 and u = 0 one RK4 step maps
+    z = m_x + i m_y to R(i h_appl dt) z and keeps m_z; the projection then
+    divides the whole vector by its length.  Projection keeps the ratio
+    z/m_z, so after n steps z/m_z = R^n z_0/m_z0, and the unit length fixes
+    m_z = sign(m_z0)/sqrt(1 + |R^n z_0/m_z0|^2).  Every record must have unit
+    length to round-off, and the projected run must differ from the plain
+    one (whose length shrinks by |R| per step in the transverse part).
+    """
+    rng = np.random.default_rng(21)
+    n = 4
+    m0 = _unit_random(rng, n, spread=0.8)
+    m0[3] *= -1.0                       # one node in the lower hemisphere
+    prm = _prm(alpha=0.0, h_s=0.0, h_k=0.0, a_cp=0.0, a_in=0.0, dt=0.05, substeps=30,
+               renormalize=True)
+    samples = 40
+    rec, _ = runner(np.zeros((n, n)), np.zeros((n, 1)), m0, np.zeros((samples, 1)), prm,
+                    rhs=rhs, step=step)
+    ratio0 = (m0[:, 0] + 1j * m0[:, 1]) / m0[:, 2]
+    amp = rk4_amplification(1j * prm.h_appl * prm.dt)
+    for s in (0, 7, samples - 1):
+        steps = (s + 1) * prm.substeps
+        r = amp ** steps * ratio0
+        mz = np.sign(m0[:, 2]) / np.sqrt(1.0 + np.abs(r) ** 2)
+        z = r * mz
+        got = rec[s]
+        assert np.max(np.abs(got[:, 2] - mz)) < 1e-13, (s, got[:, 2], mz)
+        assert np.max(np.abs(got[:, 0] + 1j * got[:, 1] - z)) < 1e-13, s
+    lengths = np.sqrt(np.sum(rec * rec, axis=2))
+    assert np.max(np.abs(lengths - 1.0)) < 1e-15, np.max(np.abs(lengths - 1.0))
+    plain, _ = runner(np.zeros((n, n)), np.zeros((n, 1)), m0, np.zeros((samples, 1)),
+                      prm.replace(renormalize=False), rhs=rhs, step=step)
+    assert np.max(np.abs(np.sqrt(np.sum(plain[-1] ** 2, axis=1)) - 1.0)) > 1e-9
+    # the coupled, driven system: unit records, close to the unprojected run
+    w, w_in, m0c, u = _coupled_case(n=6, seed=22)
+    prm = _prm(a_cp=0.3, alpha=0.02, dt=0.01, substeps=20, renormalize=True)
+    rec, _ = runner(w, w_in, m0c, u, prm, rhs=rhs, step=step)
+    plain, _ = runner(w, w_in, m0c, u, prm.replace(renormalize=False), rhs=rhs, step=step)
+    assert np.max(np.abs(np.sqrt(np.sum(rec * rec, axis=2)) - 1.0)) < 1e-15
+    d = np.max(np.abs(rec - plain))
+    assert 0.0 < d < 1e-5, d
+
+
+# --------------------------------------------------------------------------
+# Largest Lyapunov exponent: fixed points with known linearisation
+# --------------------------------------------------------------------------
+def pin_lyapunov(rhs=sto.field, step=None, lyap=sto.lyapunov_max, **_):
+    """Benettin's estimate on an uncoupled, undriven, current-free macrospin.
+
+    At m = s e_z (s = +-1) the field is b = (h_appl + s h_k) e_z =: B e_z and
+    the transverse part z = m_x + i m_y of a nearby state obeys, to first
+    order, dz/dt = mu z with mu = B (i - s alpha)/(1 + alpha^2).  The RK4 map
+    multiplies z by R(mu dt) per step, so the transverse exponent of the
+    discrete map is log|R(mu dt)|/dt.  A perturbation along m itself changes
+    only |m|, which Eq. (gov) conserves, and m stays a fixed point: that
+    direction has exponent 0.  Hence
+
+    * at -e_z with h_appl > h_k the largest exponent is log|R(mu dt)|/dt > 0;
+    * at +e_z it is 0 (the transverse mode decays, at the relaxation rate).
+
+    The initial direction of the twin is random, so the accumulated log
+    growth has a transient; it cancels in the increment between two
+    horizons run from the same seed, which must equal the exponent.  dt and
+    substeps differ from 0.01 and 20 so that a wrong time normalisation
+    shows.
+    """
+    base = _prm(alpha=0.1, h_s=0.0, a_cp=0.0, a_in=0.0, dt=0.02, substeps=7)
+    t1, t2 = 150, 400
+    zero = np.zeros((1, 1))
+    for sgn, h_k, tol in ((-1.0, 0.0, 1e-7), (-1.0, 1.5, 3e-6), (1.0, base.h_k, 2e-5)):
+        prm = base.replace(h_k=h_k)
+        m0 = np.array([[0.0, 0.0, sgn]])
+        l1 = lyap(zero, zero, m0, np.zeros((t1, 1)), prm, rhs=rhs, step=step)
+        l2 = lyap(zero, zero, m0, np.zeros((t2, 1)), prm, rhs=rhs, step=step)
+        span = prm.substeps * prm.dt
+        inc = (l2 * t2 * span - l1 * t1 * span) / ((t2 - t1) * span)
+        big_b = prm.h_appl + prm.h_k * sgn
+        mu = big_b * (1j - sgn * prm.alpha) / (1.0 + prm.alpha ** 2)
+        ex = max(0.0, math.log(abs(rk4_amplification(mu * prm.dt))) / prm.dt)
+        assert abs(inc - ex) < tol, (sgn, h_k, inc, ex)
+    # two uncoupled spins: the unstable one sets the exponent of the pair
+    prm = base.replace(h_k=0.0)
+    m0 = np.array([[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]])
+    z2 = np.zeros((2, 2))
+    l1 = lyap(z2, np.zeros((2, 1)), m0, np.zeros((t1, 1)), prm, rhs=rhs, step=step)
+    l2 = lyap(z2, np.zeros((2, 1)), m0, np.zeros((t2, 1)), prm, rhs=rhs, step=step)
+    inc = (l2 * t2 - l1 * t1) / (t2 - t1)
+    mu = prm.h_appl * (1j + prm.alpha) / (1.0 + prm.alpha ** 2)
+    ex = math.log(abs(rk4_amplification(mu * prm.dt))) / prm.dt
+    assert abs(inc - ex) < 1e-7, (inc, ex)
+
+
 ALL_PINS = [
     pin_field_at_ez,
     pin_coupling_brute_force,
@@ -394,4 +491,6 @@ ALL_PINS = [
     pin_structure,
     pin_units,
     pin_continuation,
+    pin_renormalize,
+    pin_lyapunov,
 ]

@@ -19,7 +19,8 @@ FIELD_MUTANTS = [
     "input_sign", "mmb_order", "no_acp", "mp_component", "bz_no_stt",
     "half_precession", "hk_sign", "input_into_z",
 ]
-STEP_MUTANTS = ["rk4_weight", "rk4_stage3_input", "rk4_stage4_half", "rk4_dt3", "euler"]
+STEP_MUTANTS = ["rk4_weight", "rk4_stage3_input", "rk4_stage4_half", "rk4_dt3", "euler",
+                "renorm_xy_only", "renorm_squared", "renorm_input", "renorm_skipped"]
 RUN_MUTANTS = ["record_before", "input_lag"]
 
 
@@ -83,8 +84,18 @@ def field_variant(mut):
 
 
 def step_variant(mut):
+    def project(v):
+        nrm = np.sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2])
+        if mut == "renorm_squared":
+            nrm = nrm * nrm
+        if mut == "renorm_xy_only":
+            return (v[0] / nrm, v[1] / nrm, v[2])
+        return tuple(v[j] / nrm for j in range(3))
+
     def step(m, w, h_in, prm, dot="exact", rhs=sto.field):
         dt = prm.dt
+        if prm.renormalize and mut == "renorm_input":
+            m = project(m)
         k1 = rhs(m, w, h_in, prm, dot)
         if mut == "euler":
             return sto.axpy(m, dt, k1)
@@ -95,8 +106,49 @@ def step_variant(mut):
                  w, h_in, prm, dot)
         c2 = 1.0 if mut == "rk4_weight" else 2.0
         h6 = dt / 3.0 if mut == "rk4_dt3" else dt / 6.0
-        return tuple(m[j] + h6 * (k1[j] + c2 * k2[j] + 2.0 * k3[j] + k4[j]) for j in range(3))
+        out = tuple(m[j] + h6 * (k1[j] + c2 * k2[j] + 2.0 * k3[j] + k4[j]) for j in range(3))
+        if prm.renormalize and mut not in ("renorm_input", "renorm_skipped"):
+            out = project(out)
+        return out
     return step
+
+
+def lyapunov_variant(mut):
+    """Copies of Benettin's twin-trajectory estimate with one mistake."""
+    import math
+
+    def lyap(w, w_in, m0, u, prm, d0=1e-10, seed=1, dot="blas", rhs=sto.field, step=None):
+        rng = np.random.default_rng(seed)
+        n = w.shape[0]
+        u = np.asarray(u, dtype=np.float64).reshape(len(u), -1)
+        a = sto.to_soa(m0)
+        d = rng.standard_normal((n, 3))
+        d *= d0 / np.linalg.norm(d)
+        b = sto.to_soa(np.asarray(m0) + d)
+        total = 0.0
+        for s in range(len(u)):
+            h_in = sto.input_field(w_in, u[s], prm, dot)
+            for _ in range(prm.substeps):
+                a = sto.rk4_step(a, w, h_in, prm, dot)
+                b = sto.rk4_step(b, w, h_in, prm, dot)
+            diff = np.stack([b[j] - a[j] for j in range(3)], axis=1)
+            if mut == "x_only":
+                dist = float(np.linalg.norm(diff[:, 0]))
+            else:
+                dist = float(np.linalg.norm(diff))
+            growth = math.log10(dist / d0) if mut == "log10" else math.log(dist / d0)
+            total += -growth if mut == "log_sign" else growth
+            if mut != "no_rescale":
+                b = sto.to_soa(sto.to_aos(a) + diff * (d0 / dist))
+        if mut == "per_sample":
+            return total / len(u)
+        if mut == "per_step":
+            return total / (len(u) * prm.substeps)
+        return total / (len(u) * prm.substeps * prm.dt)
+    return lyap
+
+
+LYAP_MUTANTS = ["no_rescale", "per_sample", "per_step", "log10", "log_sign", "x_only"]
 
 
 def runner_variant(mut):
@@ -120,7 +172,8 @@ _ORDER = sorted(pins.ALL_PINS, key=lambda f: [
     "pin_field_at_ez", "pin_coupling_brute_force", "pin_gilbert_form",
     "pin_precession_tilted_field", "pin_damping_closed_form", "pin_global_order",
     "pin_units", "pin_structure", "pin_continuation", "pin_energy",
-    "pin_precession_map", "pin_relaxation"].index(f.__name__))
+    "pin_precession_map", "pin_relaxation", "pin_renormalize",
+    "pin_lyapunov"].index(f.__name__))
 
 
 def _caught(**kw):
@@ -156,3 +209,20 @@ def test_step_mutant_is_caught(mut):
 @pytest.mark.parametrize("mut", RUN_MUTANTS)
 def test_runner_mutant_is_caught(mut):
     assert _caught(runner=runner_variant(mut)) is not None, mut
+
+
+def test_step_variant_without_mutation_is_the_oracle():
+    """The RK4 template with no mistake planted passes every pin, with and
+    without renormalisation."""
+    assert _caught(step=step_variant("none")) is None
+
+
+@pytest.mark.parametrize("mut", LYAP_MUTANTS)
+def test_lyapunov_mutant_is_caught(mut):
+    # only the Lyapunov pin calls the estimate, so it is the one to run
+    with np.errstate(all="ignore"), pytest.raises((AssertionError, FloatingPointError, ValueError)):
+        pins.pin_lyapunov(lyap=lyapunov_variant(mut))
+
+
+def test_lyapunov_variant_without_mutation_is_the_oracle():
+    pins.pin_lyapunov(lyap=lyapunov_variant("none"))
