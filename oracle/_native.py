@@ -44,6 +44,10 @@ def lib():
             L.exact_dot.argtypes = [dp, ctypes.c_long, dp, ctypes.c_long, ctypes.c_long]
             L.exact_matvec.restype = None
             L.exact_matvec.argtypes = [dp, ctypes.c_long, ctypes.c_long, ctypes.c_long, dp, dp]
+            L.exact_matvec_reference.restype = None
+            L.exact_matvec_reference.argtypes = L.exact_matvec.argtypes
+            L.exact_fallbacks.restype = ctypes.c_long
+            L.exact_fallbacks.argtypes = []
             L.exact_sum.restype = ctypes.c_double
             L.exact_sum.argtypes = [dp, ctypes.c_long]
             L.exact_threads.restype = ctypes.c_int
@@ -66,7 +70,12 @@ def exact_dot(x, y) -> float:
 
 
 def exact_matvec(a, x) -> np.ndarray:
-    """Row-wise correctly rounded product A @ x (A two-dimensional)."""
+    """Row-wise correctly rounded product A @ x (A two-dimensional).
+
+    Each row is decided by a certified error-free-transformation enclosure
+    where that settles the rounding, and by the exact superaccumulator
+    otherwise; either way the entry is the nearest double to the exact sum.
+    """
     a = np.ascontiguousarray(a, dtype=np.float64)
     x = np.ascontiguousarray(x, dtype=np.float64).ravel()
     rows, cols = a.shape
@@ -75,6 +84,23 @@ def exact_matvec(a, x) -> np.ndarray:
     out = np.empty(rows)
     lib().exact_matvec(_ptr(a), rows, cols, cols, _ptr(x), _ptr(out))
     return out
+
+
+def exact_matvec_reference(a, x) -> np.ndarray:
+    """The same product by the superaccumulator alone, row by row."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    rows, cols = a.shape
+    if cols != x.size:
+        raise ValueError("shape mismatch")
+    out = np.empty(rows)
+    lib().exact_matvec_reference(_ptr(a), rows, cols, cols, _ptr(x), _ptr(out))
+    return out
+
+
+def exact_fallbacks() -> int:
+    """Rows exact_matvec has handed to the superaccumulator so far."""
+    return int(lib().exact_fallbacks())
 
 
 def exact_sum(x) -> float:

@@ -171,16 +171,158 @@ double exact_dot(const double *x, long incx, const double *y, long incy, long n)
     return acc_round(&acc);
 }
 
-/* out[k] = nearest double to sum_i A[k*lda + i] * x[i], for k < rows.
- * Rows are independent, so they may be evaluated by several threads without
- * changing any result. */
-void exact_matvec(const double *A, long rows, long cols, long lda,
-                  const double *x, double *out)
+/* ------------------------------------------------------------------------
+ * Certified fast path for the matrix-vector product.
+ *
+ * The superaccumulator above is the definition; it is also slow (tens of ns
+ * per product).  For a row of the coupling product the nearest double to
+ * the exact sum can usually be certified from a cheaper enclosure:
+ *
+ *  1. Error-free transformations (Ogita, Rump and Oishi, "Accurate sum and
+ *     dot product", SIAM J. Sci. Comput. 26, 2005): TwoProduct gives
+ *     x*y = h + r exactly (r = fma(x, y, -h)) when no underflow occurs, and
+ *     Knuth's TwoSum gives p + h = p' + q exactly.  With LANES independent
+ *     running sums and a final TwoSum of the lanes, the exact dot product
+ *     is P + T, where P is a double and T the exact sum of every error term
+ *     q and r.
+ *  2. T is summed in floating point as S.  For m terms summed in any order
+ *     |S - T| <= gamma_m sum|terms|, gamma_m = m u/(1 - m u), u = 2^-53
+ *     (Higham, "Accuracy and Stability of Numerical Algorithms", Sec. 4.2).
+ *     The sum of |terms| is itself summed in floating point as A; a bound
+ *     E = 2 m u A covers both roundings while m u < 1e-3.
+ *  3. TwoSum(P, S) = (hi, lo) exactly, so the exact result X lies in
+ *     [hi + lo - E, hi + lo + E].  hi is the nearest double to X if that
+ *     interval lies strictly inside (hi - g/2, hi + g/2), where g is the
+ *     smaller of the two gaps from hi to its neighbouring doubles.
+ *
+ * Any row that fails the test (a result too close to a rounding boundary,
+ * a zero or subnormal result, a product outside [2^-960, 2^960] in
+ * magnitude where TwoProduct might not be exact, non-finite data) is
+ * recomputed with the superaccumulator.  The result is therefore the
+ * nearest double to the exact sum for every row, whichever path produced it.
+ * ---------------------------------------------------------------------- */
+#include <omp.h>
+
+#define LANES 8
+
+static long g_fallbacks = 0;    /* rows sent to the superaccumulator */
+
+/* One row: returns 1 and sets *res when certified, 0 otherwise. */
+#define FAST_ROW_BODY                                                          \
+    double P[LANES], Eacc[LANES], Aacc[LANES];                                 \
+    int bad[LANES];                                                            \
+    for (int j = 0; j < LANES; ++j) {                                          \
+        P[j] = 0.0; Eacc[j] = 0.0; Aacc[j] = 0.0; bad[j] = 0;                  \
+    }                                                                          \
+    long i = 0;                                                                \
+    for (; i + LANES <= n; i += LANES) {                                       \
+        _Pragma("omp simd")                                                    \
+        for (int j = 0; j < LANES; ++j) {                                      \
+            double a = x[i + j], b = y[i + j];                                 \
+            double h = a * b;                                                  \
+            double r = fma(a, b, -h);                                          \
+            double p = P[j];                                                   \
+            double s = p + h;                                                  \
+            double bb = s - p;                                                 \
+            double q = (p - (s - bb)) + (h - bb);                              \
+            P[j] = s;                                                          \
+            Eacc[j] += q + r;                                                  \
+            Aacc[j] += fabs(q) + fabs(r);                                      \
+            double ah = fabs(h);                                               \
+            bad[j] |= ((ah < 0x1p-960) & (a != 0.0) & (b != 0.0))              \
+                      | !(ah <= 0x1p960);                                      \
+        }                                                                      \
+    }                                                                          \
+    for (; i < n; ++i) {                                                       \
+        double a = x[i], b = y[i];                                             \
+        double h = a * b;                                                      \
+        double r = fma(a, b, -h);                                              \
+        double p = P[0];                                                       \
+        double s = p + h;                                                      \
+        double bb = s - p;                                                     \
+        double q = (p - (s - bb)) + (h - bb);                                  \
+        P[0] = s;                                                              \
+        Eacc[0] += q + r;                                                      \
+        Aacc[0] += fabs(q) + fabs(r);                                          \
+        double ah = fabs(h);                                                   \
+        bad[0] |= ((ah < 0x1p-960) & (a != 0.0) & (b != 0.0))                  \
+                  | !(ah <= 0x1p960);                                          \
+    }                                                                          \
+    double Pt = P[0], St = Eacc[0], At = Aacc[0];                              \
+    int anybad = bad[0];                                                       \
+    for (int j = 1; j < LANES; ++j) {                                          \
+        double s = Pt + P[j];                                                  \
+        double bb = s - Pt;                                                    \
+        double q = (Pt - (s - bb)) + (P[j] - bb);                              \
+        Pt = s;                                                                \
+        St += q + Eacc[j];                                                     \
+        At += fabs(q) + Aacc[j];                                               \
+        anybad |= bad[j];                                                      \
+    }                                                                          \
+    double hi = Pt + St;                                                       \
+    double bb = hi - Pt;                                                       \
+    double lo = (Pt - (hi - bb)) + (St - bb);                                  \
+    double m_terms = 2.0 * (double)n + 4.0 * LANES;                            \
+    double E = 2.0 * m_terms * 0x1p-53 * At;                                   \
+    if (anybad || !(hi != 0.0) || !isfinite(hi) || !isfinite(E)                \
+        || fabs(hi) < 0x1p-1000 || m_terms * 0x1p-53 >= 1e-3)                  \
+        return 0;                                                              \
+    double gu = nextafter(hi, INFINITY) - hi;                                  \
+    double gd = hi - nextafter(hi, -INFINITY);                                 \
+    double g = gu < gd ? gu : gd;                                              \
+    if (!((fabs(lo) + E) * (1.0 + 0x1p-40) < 0.5 * g))                         \
+        return 0;                                                              \
+    *res = hi;                                                                 \
+    return 1;
+
+__attribute__((target("avx2,fma")))
+static int fast_dot_avx2(const double *x, const double *y, long n, double *res)
+{
+    FAST_ROW_BODY
+}
+
+static int fast_dot_generic(const double *x, const double *y, long n, double *res)
+{
+    FAST_ROW_BODY
+}
+
+/* out[k] = nearest double to sum_i A[k*lda + i] * x[i], for k < rows, by the
+ * superaccumulator alone.  Rows are independent, so they may be evaluated
+ * by several threads without changing any result. */
+void exact_matvec_reference(const double *A, long rows, long cols, long lda,
+                            const double *x, double *out)
 {
 #pragma omp parallel for schedule(static)
     for (long k = 0; k < rows; ++k)
         out[k] = exact_dot(A + k * lda, 1, x, 1, cols);
 }
+
+/* out[k] = nearest double to sum_i A[k*lda + i] * x[i], for k < rows: the
+ * certified fast path where it decides, the superaccumulator elsewhere.
+ * The result equals exact_matvec_reference bit for bit. */
+void exact_matvec(const double *A, long rows, long cols, long lda,
+                  const double *x, double *out)
+{
+    int (*fast)(const double *, const double *, long, double *) =
+        (__builtin_cpu_supports("avx2") && __builtin_cpu_supports("fma"))
+            ? fast_dot_avx2 : fast_dot_generic;
+    long fb = 0;
+#pragma omp parallel for schedule(static) reduction(+:fb)
+    for (long k = 0; k < rows; ++k) {
+        double v;
+        if (!fast(A + k * lda, x, cols, &v)) {
+            v = exact_dot(A + k * lda, 1, x, 1, cols);
+            ++fb;
+        }
+        out[k] = v;
+    }
+#pragma omp atomic
+    g_fallbacks += fb;
+}
+
+/* Rows exact_matvec has sent to the superaccumulator since the library was
+ * loaded (a test hook: shows which path decided). */
+long exact_fallbacks(void) { return g_fallbacks; }
 
 /* Exact sum of n doubles, rounded once (the sum of x[i] * 1.0). */
 double exact_sum(const double *x, long n)
@@ -193,5 +335,4 @@ double exact_sum(const double *x, long n)
 }
 
 /* Number of threads exact_matvec uses (OpenMP's current maximum). */
-#include <omp.h>
 int exact_threads(void) { return omp_get_max_threads(); }

@@ -68,6 +68,68 @@ def test_exact_matvec_rows():
     np.testing.assert_allclose(out, a @ x, rtol=1e-13)
 
 
+def test_exact_matvec_fast_path_against_rational_arithmetic():
+    """Rows decided by the certified enclosure and rows sent to the
+    superaccumulator both equal the rational-arithmetic result: ordinary
+    rows, heavy cancellation, wide exponent ranges, products below 2^-960
+    and above 2^960, zero rows, exact ties and results one sticky bit away
+    from a tie."""
+    from oracle._native import exact_fallbacks, exact_matvec_reference
+    rng = np.random.default_rng(31)
+    rows = []
+    for trial in range(400):
+        n = int(rng.integers(1, 70))
+        kind = trial % 8
+        x = rng.standard_normal(n)
+        if kind == 1:
+            x *= np.exp2(rng.integers(-300, 300, n))
+        if kind == 2 and n > 1:
+            x[-1] = -x[0]                                   # cancellation
+        if kind == 3:
+            x *= np.exp2(-700.0)                            # tiny products
+        if kind == 4:
+            x *= np.exp2(600.0)                             # huge products
+        if kind == 5:
+            x[:] = 0.0
+        rows.append(x)
+    width = max(len(r) for r in rows)
+    a = np.zeros((len(rows) + 3, width + 2))
+    for k, r in enumerate(rows):
+        a[k, :len(r)] = r
+    v = rng.standard_normal(width + 2) * np.exp2(rng.integers(-40, 40, width + 2))
+    v[:3] = 1.0
+    # a tie (1 + 2^-53 lies halfway between two doubles), a tie broken by a
+    # sticky bit far below, and a result just below a power of two
+    a[-3, :2] = [1.0, 2.0 ** -53]
+    a[-2, :3] = [1.0, 2.0 ** -53, 2.0 ** -300]
+    a[-1, :2] = [2.0, -(2.0 ** -60)]
+    ref = [float(sum((Fraction(a[k, i]) * Fraction(v[i]) for i in range(a.shape[1])),
+                     Fraction(0))) for k in range(a.shape[0])]
+    f0 = exact_fallbacks()
+    got = exact_matvec(a, v)
+    sent = exact_fallbacks() - f0
+    assert [float(g) for g in got] == ref
+    assert np.array_equal(exact_matvec_reference(a, v), got)
+    # the ties, the tiny, huge and zero rows went to the superaccumulator;
+    # most ordinary rows were certified
+    assert 3 <= sent < a.shape[0] // 2, sent
+
+
+def test_exact_matvec_fast_path_on_workload_shapes():
+    """On the coupling matrices of the sized workloads the fast product equals
+    the superaccumulator bit for bit, and certifies (nearly) every row."""
+    from oracle._native import exact_fallbacks, exact_matvec_reference
+    rng = np.random.default_rng(32)
+    for n in (16, 257, 1000, 3000):
+        a = rng.standard_normal((n, n)) / math.sqrt(n)
+        np.fill_diagonal(a, 0.0)
+        x = np.cos(rng.uniform(0, math.pi, n))
+        f0 = exact_fallbacks()
+        got = exact_matvec(a, x)
+        assert np.array_equal(got, exact_matvec_reference(a, x))
+        assert exact_fallbacks() - f0 <= 1
+
+
 def test_matvec_rules_agree_on_exact_data():
     """Small integers times dyadic values: every rounding rule is exact."""
     rng = np.random.default_rng(4)
