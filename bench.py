@@ -8,13 +8,15 @@ stage combination, one record per sample) followed by the FP64 ridge
 readout of the records.  The metric is node-steps/s = N x RK4 steps per
 second of wall time over the timed steps.
 
-Default workload: 10,000 coupled oscillators in FP32 (1,000 input samples x
-20 RK4 steps, dt = 0.01), the largest configuration, where the coupling
-matrix (400 MB) is streamed from HBM once per RK4 stage.  The JSON line
-also carries the same workload in FP64, 1,000 oscillators in FP32 and FP64
-(10,000 samples x 20 steps) and 16 oscillators in FP64 (2,000 x 20) under
-"also", the roofline of the dominant kernel, and the CPU oracle timed on a
-bounded sample of the default workload.
+Default workload: 10,000 coupled oscillators in FP64, the paper's precision
+(1,000 input samples x 20 RK4 steps, dt = 0.01), the largest configuration,
+where the coupling matrix (800 MB) is streamed from HBM once per RK4 stage.
+The JSON line also carries the same workload in FP32, 1,000 oscillators in
+FP32 and FP64 (10,000 samples x 20 steps), 16 oscillators in FP64 (2,000 x
+20), the parameter sweep, the multi-stream workload and the adjoints under
+"also", the roofline of the dominant kernel, and the CPU oracle timed on
+the host cores: a bounded prefix of the default workload, the whole
+16-oscillator series and a stated prefix of the 1,000-oscillator series.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -222,8 +224,8 @@ def run_streams_workload(stx, torch, name: str, steps: int, warmup: int, couplin
     """S input streams share one reservoir (FP32 MFMA coupling: the MULTI
     path for x coupling, the per-stage BATCH path for all three components);
     one step is the run of every stream plus one readout per stream.  The
-    same work through the plain single-reservoir path is timed on one stream
-    and scaled by S."""
+    same runs through the plain single-reservoir path, one stream after
+    another over the whole series, are timed beside it."""
     from workloads import STREAMS, WORKLOADS, make_stream_arrays
     from paper_2312_01121_amd import params
 
@@ -264,19 +266,22 @@ def run_streams_workload(stx, torch, name: str, steps: int, warmup: int, couplin
     nmse = evs[-1][2]
     path = r.path
     r.close()
-    # plain path: one stream through the single-reservoir kernels, x S
+    # plain path: every stream through the single-reservoir kernels, one
+    # after another, each over the whole series (measured, not scaled)
     r1 = stx.Reservoir(a["W"], a["w_in"], a["m0"], prm)
     plain_path = r1.path
-    u1 = torch.from_numpy(np.ascontiguousarray(a["u"][:, 0])).cuda()
     st1 = torch.empty((wl.samples, wl.n, 3), dtype=torch.float32, device="cuda")
-    r1.run_device(u1, st1, stream)
+    u_all = [torch.from_numpy(np.ascontiguousarray(a["u"][:, st])).cuda() for st in range(S)]
+    r1.run_device(u_all[0], st1, stream)                # warm-up
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    r1.run_device(u1, st1, stream)
+    for st in range(S):
+        r1.set_state(a["m0"])
+        r1.run_device(u_all[st], st1, stream)
     e1.record(stream)
     torch.cuda.synchronize()
-    plain_ms = e0.elapsed_time(e1) * S
+    plain_ms = e0.elapsed_time(e1)
     r1.close()
     wall_s = (t1 - t0) / steps
     C = 3 if coupling == "xyz" else 1
@@ -387,12 +392,14 @@ def run_streams_adjoint_workload(stx, torch, name: str, coupling: str, steps: in
     }
 
 
-def run_sweep_workload(stx, torch, name: str, steps: int, warmup: int, plain_samples: int = 20,
+def run_sweep_workload(stx, torch, name: str, steps: int, warmup: int, plain_samples: int = 200,
                        samples=None, plain: bool = True):
     """Parameter sweep (SWEEP path): every reservoir's run plus one readout
     per reservoir is one step.  The plain single-reservoir path (each
-    reservoir alone, its own auto-selected kernel) is timed on the first
-    ``plain_samples`` samples and scaled to the full series."""
+    reservoir alone, its own auto-selected kernel, one after another) is
+    timed on the first ``plain_samples`` samples (all of them with
+    --plain-full) and scaled to the full series; the per-sample cost of
+    every path is constant, so the scaling is linear."""
     import numpy as np
     from workloads import SWEEPS, make_sweep_arrays
     from paper_2312_01121_amd import params
@@ -465,6 +472,7 @@ def run_sweep_workload(stx, torch, name: str, steps: int, warmup: int, plain_sam
         "algo_bytes_per_launch": algo, "achieved_gbs": achieved, "hbm_frac": achieved / HBM_PEAK_GBS,
         "readout_nmse_median": float(np.median(nmse)), "readout_nmse_min": float(np.min(nmse)),
         "plain_paths": paths, "plain_run_ms_estimate": plain_ms if plain else None,
+        "plain_samples_timed": plain_samples if plain else 0,
         "speedup_vs_plain": plain_ms / run_ms if plain else None,
     }
 
@@ -478,72 +486,120 @@ PAPER_TABLE2_S = {
 }
 
 
-def paper_table(stx, torch, steps: int):
+def paper_table(stx, torch, steps: int, repeats: int = 3, chunk_steps: int = 50000):
     """The paper's benchmark on this GPU: u = 0, FP64, dt = 1e-11 s (0.01 in
     units of 1 ns), the paper's coupling generator (U[-1,1], zero diagonal,
     spectral radius 1), its identical initial tilt and A_cp = A_in = 1 Oe,
-    for N = 1 ... 10^4, ``steps`` RK4 steps each."""
+    for N = 1 ... 10^4, ``steps`` RK4 steps each, ``repeats`` times from the
+    same initial state (the paper reports the mean of repeated runs, Sec. 4).
+    A long run is issued in chunks of ``chunk_steps`` steps that continue
+    the state (bitwise the same as one call), each writing its records into
+    one reused buffer, so that progress can be printed."""
     import numpy as np
-    from workloads import draw_coupling, draw_initial, draw_input_weights, seed_streams
+    from workloads import make_paper_arrays
     from paper_2312_01121_amd import params
 
     g = params.field_unit()
     substeps = 20
     samples = max(1, steps // substeps)
+    chunk = max(1, min(samples, chunk_steps // substeps))
     rows = []
     for i, n in enumerate(PAPER_N):
-        g_w, g_in, g_m0, _ = seed_streams(0, 5000 + n)
-        w = draw_coupling(g_w, n, "paper")
-        w_in = draw_input_weights(g_in, n, 1)
-        m0 = draw_initial(g_m0, n, "paper")
+        a = make_paper_arrays(n, 1)
         prm = stx.make_params(**params.table1(a_cp=g * 1.0, a_in=g * 1.0, substeps=substeps), dtype="f64")
-        r = stx.Reservoir(w, w_in, m0, prm)
-        u_d = torch.zeros((samples, 1), dtype=torch.float64, device="cuda")
-        states = torch.empty((samples, n, 3), dtype=torch.float64, device="cuda")
+        r = stx.Reservoir(a["W"], a["w_in"], a["m0"], prm)
+        u_d = torch.zeros((chunk, 1), dtype=torch.float64, device="cuda")
+        states = torch.empty((chunk, n, 3), dtype=torch.float64, device="cuda")
         r.run_device(u_d[:1].contiguous(), states[:1].contiguous())   # warm-up
-        r.set_state(m0)
         stream = torch.cuda.current_stream()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        r.run_device(u_d, states, stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        sec = e0.elapsed_time(e1) * 1e-3
-        rec = states.cpu().numpy()
-        drift = float(np.max(np.abs(np.linalg.norm(rec, axis=2) - 1.0)))
+        secs, drift = [], 0.0
+        for rep in range(repeats):
+            r.set_state(a["m0"])
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            done = 0
+            while done < samples:
+                k = min(chunk, samples - done)
+                r.run_device(u_d[:k], states[:k], stream)
+                done += k
+                if done < samples:
+                    # progress of a long run (the wait does not enter the event time)
+                    torch.cuda.synchronize()
+                    log(f"paper N={n} repeat {rep + 1}: {done * substeps} of {samples * substeps} steps")
+                    drift = max(drift, float(torch.max(torch.abs(torch.linalg.norm(states[:k], dim=2) - 1.0))))
+            e1.record(stream)
+            torch.cuda.synchronize()
+            secs.append(e0.elapsed_time(e1) * 1e-3)
+            k = samples - (samples - 1) // chunk * chunk
+            drift = max(drift, float(torch.max(torch.abs(torch.linalg.norm(states[:k], dim=2) - 1.0))))
+        med = float(np.median(secs))
         base = PAPER_TABLE2_S["numpy_base"][i]
-        rows.append({"n": n, "path": r.path, "rk4_steps": samples * substeps, "seconds": sec,
-                     "us_per_rk4_step": sec * 1e6 / (samples * substeps),
-                     "node_steps_per_s": n * samples * substeps / sec, "max_norm_drift": drift,
+        rows.append({"n": n, "path": r.path, "rk4_steps": samples * substeps, "repeats": repeats,
+                     "seconds": secs, "seconds_median": med, "seconds_min": min(secs), "seconds_max": max(secs),
+                     "us_per_rk4_step": med * 1e6 / (samples * substeps),
+                     "node_steps_per_s": n * samples * substeps / med, "max_norm_drift": drift,
                      "paper_numpy_base_s": base, "paper_torch_gpu_s": PAPER_TABLE2_S["torch_gpu"][i]})
         r.close()
         log(json.dumps(rows[-1]))
     return rows
 
 
-def cpu_baseline(name: str, arrays, budget_s: float = 25.0):
+def oracle_rate(name: str, arrays, budget_s: float, whole: bool = False):
     """The FP64 oracle (correctly rounded coupling sums) on the first input
-    samples of the workload, on this host's cores."""
+    samples of a workload, sample by sample until the time budget would be
+    exceeded (or over every sample with ``whole``).  Returns node-steps/s,
+    the samples run, the seconds and the threads the coupling product used."""
     from oracle import _native, constants, sto
     from workloads import WORKLOADS
 
     wl = WORKLOADS[name]
     prm = constants.dimensionless(a_cp=wl.a_cp, a_in=wl.a_in, dt=wl.dt, substeps=wl.substeps)
     samples = 0
+    total = len(arrays["u"])
     t0 = time.perf_counter()
     m = arrays["m0"]
     while True:
         _, m = sto.run(arrays["W"], arrays["w_in"], m, arrays["u"][samples:samples + 1], prm)
         samples += 1
         el = time.perf_counter() - t0
-        if el >= budget_s * 0.5 or samples >= wl.samples or el / samples * (samples + 1) > budget_s:
+        if samples >= total:
             break
+        if not whole and (el >= budget_s * 0.5 or el / samples * (samples + 1) > budget_s):
+            break
+    # the product runs on one thread below 2^16 matrix entries, else on all
+    threads = _native.exact_threads() if wl.n * wl.n >= (1 << 16) else 1
+    return wl.n * samples * wl.substeps / el, samples, el, threads
+
+
+def cpu_baseline(name: str, arrays, budget_s: float = 12.0):
+    """The oracle on this host's cores: a bounded prefix of the benchmark's
+    own workload (the reported value), the whole 16-oscillator series and a
+    prefix of the 1,000-oscillator series, and the oracle's NumPy-BLAS form."""
+    from oracle import constants
+    from workloads import WORKLOADS, make_workload_arrays
+
+    wl = WORKLOADS[name]
+    value, samples, el, threads = oracle_rate(name, arrays, budget_s)
+    others = []
+    for other, whole, budget in (("sto16", True, 0.0), ("sto1k", False, 12.0)):
+        if other == name:
+            continue
+        ow = WORKLOADS[other]
+        a = make_workload_arrays(ow)
+        v, smp, sec, thr = oracle_rate(other, a, budget, whole=whole)
+        others.append({
+            "workload": other, "n": ow.n, "value": v, "unit": "node-steps/s", "cores": thr,
+            "samples": smp, "rk4_steps": smp * ow.substeps, "seconds": sec,
+            "horizon": "whole series" if smp == ow.samples else f"first {smp} of {ow.samples} samples",
+        })
+        log(json.dumps(others[-1]))
+    prm = constants.dimensionless(a_cp=wl.a_cp, a_in=wl.a_in, dt=wl.dt, substeps=wl.substeps)
     return {
-        "value": wl.n * samples * wl.substeps / el, "unit": "node-steps/s", "cores": _native.exact_threads(),
-        "kind": "oracle",
+        "value": value, "unit": "node-steps/s", "cores": threads, "kind": "oracle",
         "sample": f"first {samples} input sample(s) = {samples * wl.substeps} RK4 steps of the {name} "
                   f"workload (N={wl.n}), FP64 oracle with correctly rounded coupling sums, {el:.1f} s",
+        "other_workloads": others,
         "blas_form": cpu_blas_form(name, arrays, prm),
     }
 
@@ -589,13 +645,23 @@ def cpu_blas_form(name: str, arrays, prm, budget_s: float = 4.0):
     }
 
 
+def finish(torch):
+    """Drain the device and drop torch's cached blocks before the line is
+    printed: every library handle is already closed, so nothing is left for
+    interpreter exit to free on the device."""
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sto10k")
-    ap.add_argument("--dtype", default="f32", choices=("f32", "f64"))
+    ap.add_argument("--dtype", default="f64", choices=("f32", "f64"))
     ap.add_argument("--no-also", action="store_true", help="skip the secondary workloads")
     ap.add_argument("--adjoint", default=None, metavar="WORKLOAD:DTYPE:SAMPLES",
                     help="time only the adjoint line for this workload (e.g. sto10k:f32:50; for the "
@@ -607,8 +673,11 @@ def main():
                     help="run only the first SAMPLES input samples of the main workload (short profiled runs)")
     ap.add_argument("--paper-table", type=int, default=0, metavar="STEPS",
                     help="only run the paper's benchmark (u = 0, FP64, N = 1..1e4) for STEPS RK4 steps each")
+    ap.add_argument("--repeats", type=int, default=3, help="paper benchmark: runs per size (median and spread)")
     ap.add_argument("--no-plain", action="store_true",
                     help="sweep workload: skip timing the plain single-reservoir path")
+    ap.add_argument("--plain-full", action="store_true",
+                    help="sweep workload: time the plain path over the whole input series, not a prefix")
     ap.add_argument("--coupling", default="x", choices=("x", "xyz"),
                     help="multi-stream workload: the paper's m^x coupling or all three components")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -627,7 +696,8 @@ def main():
     from workloads import WORKLOADS, make_workload_arrays
 
     if args.paper_table:
-        rows = paper_table(stx, torch, args.paper_table)
+        rows = paper_table(stx, torch, args.paper_table, args.repeats)
+        finish(torch)
         print(json.dumps({"paper_table": rows, "steps": args.paper_table}), flush=True)
         return
     if args.calibrate_copy:
@@ -647,12 +717,14 @@ def main():
                                                own_checkpoints=args.own_checkpoints)
         else:
             res = run_adjoint_workload(stx, torch, name, dt, int(samples), args.steps, args.warmup)
+        finish(torch)
         print(json.dumps({"adjoint": res}), flush=True)
         return
     if args.workload in SWEEPS or args.workload in STREAMS:
         if args.workload in SWEEPS:
             res = run_sweep_workload(stx, torch, args.workload, args.steps, args.warmup, samples=args.samples,
-                                     plain=not args.no_plain)
+                                     plain=not args.no_plain,
+                                     plain_samples=10 ** 9 if args.plain_full else 200)
             roof = {"bound": "hbm", "kernel": res["kernel"], "achieved": res["achieved_gbs"], "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": res["hbm_frac"], "traffic": stored_traffic("k_sweep_stage", args.workload, "f32")}
             unit_nodes = res["nodes"]
@@ -661,6 +733,7 @@ def main():
             roof = {"bound": "mfma", "kernel": res["kernel"], "achieved": res["mfma_tflops"], "peak": 157.3,
                     "unit": "TFLOP/s", "frac": res["mfma_frac"], "traffic": None}
             unit_nodes = res["n"] * res["streams"]
+        finish(torch)
         print(json.dumps({
             "metric": METRIC, "value": res["value"], "unit": "node-steps/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak",
@@ -735,6 +808,7 @@ def main():
         "detail": main_res,
         "also": also,
     }
+    finish(torch)
     print(json.dumps(out), flush=True)
 
 

@@ -204,6 +204,7 @@ double exact_dot(const double *x, long incx, const double *y, long incy, long n)
 #include <omp.h>
 
 #define LANES 8
+#define EXACT_PARALLEL_MIN (1L << 16)
 
 static long g_fallbacks = 0;    /* rows sent to the superaccumulator */
 
@@ -292,7 +293,7 @@ static int fast_dot_generic(const double *x, const double *y, long n, double *re
 void exact_matvec_reference(const double *A, long rows, long cols, long lda,
                             const double *x, double *out)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (rows * cols >= EXACT_PARALLEL_MIN)
     for (long k = 0; k < rows; ++k)
         out[k] = exact_dot(A + k * lda, 1, x, 1, cols);
 }
@@ -307,7 +308,9 @@ void exact_matvec(const double *A, long rows, long cols, long lda,
         (__builtin_cpu_supports("avx2") && __builtin_cpu_supports("fma"))
             ? fast_dot_avx2 : fast_dot_generic;
     long fb = 0;
-#pragma omp parallel for schedule(static) reduction(+:fb)
+    /* small products stay on one thread: a parallel region costs more than
+     * they do (the rows are independent either way) */
+#pragma omp parallel for schedule(static) reduction(+:fb) if (rows * cols >= EXACT_PARALLEL_MIN)
     for (long k = 0; k < rows; ++k) {
         double v;
         if (!fast(A + k * lda, x, cols, &v)) {

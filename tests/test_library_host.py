@@ -165,3 +165,124 @@ def test_readout_batch_rejects_bad_arguments(stx):
     assert lib.readout_fit_batch_device(1, one, short, 0, 10, n, y, 2, 1e-6, 0, w, nm, None) == stx.STO_E_INVALID
     assert lib.readout_fit_batch_device(1, one, None, 0, 10, n, y, 10, 1e-6, 0, w, nm, None) == stx.STO_E_INVALID
     assert lib.readout_fit_batch_device(65536, one, None, 0, 10, n, y, 2, 1e-6, 0, w, nm, None) == stx.STO_E_INVALID
+
+
+# ----------------------------------------------------------------------------
+# Host buffers the binding hands to the library are as large as the header says
+# ----------------------------------------------------------------------------
+class _FakeLib:
+    """Stands in for the shared library: every entry point checks that each
+    host buffer it receives holds at least the number of doubles the header
+    (include/sto_reservoir.h) says the library reads or writes there, and
+    then writes its full extent, as the real library does.  The sizes come
+    from a registry of the arrays the binding converted to pointers."""
+
+    def __init__(self, registry, n, n_in, streams):
+        self.reg, self.n, self.n_in, self.S = registry, n, n_in, streams
+        self.substeps = None
+        self.calls = []
+
+    def _need(self, p, count, name, write=False):
+        if p is None:
+            return
+        addr = ctypes.cast(p, ctypes.c_void_p).value
+        have = self.reg.get(addr)
+        assert have is not None, f"{name}: pointer not from a registered array"
+        assert have >= 8 * count, f"{name}: {have} bytes, the library uses {8 * count}"
+        if write:
+            np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(ctypes.c_double)), shape=(count,))[:] = 0.5
+
+    def reservoir_create(self, n, n_in, prm, W, w_in, m0, hp):
+        self.substeps = prm._obj.substeps
+        self._need(W, n * n, "W"), self._need(w_in, n * n_in, "w_in"), self._need(m0, n * 3, "m0")
+        hp._obj.value = 1
+        return 0
+
+    def reservoir_create_streams(self, n, n_in, S, prm, W, w_in, m0, hp):
+        self.substeps = prm._obj.substeps
+        self._need(W, n * n, "W"), self._need(w_in, n * n_in, "w_in"), self._need(m0, S * n * 3, "m0")
+        hp._obj.value = 1
+        return 0
+
+    def reservoir_streams(self, h):
+        return self.S
+
+    def reservoir_path(self, h):
+        return 2
+
+    def reservoir_run(self, h, u, steps, states):
+        samples = steps // self.substeps
+        self._need(u, samples * self.S * self.n_in, "u")
+        self._need(states, samples * self.S * self.n * 3, "states", write=True)
+        self.calls.append("run")
+        return 0
+
+    def reservoir_get_state(self, h, m):
+        self._need(m, self.S * self.n * 3, "m", write=True)
+        self.calls.append("get_state")
+        return 0
+
+    def reservoir_set_state(self, h, m):
+        self._need(m, self.S * self.n * 3, "m")
+        return 0
+
+    def reservoir_adjoint(self, h, m_start, u, steps, gs, gf, gW, gwin, gm0, gsc, ce):
+        samples = steps // self.substeps
+        per = self.S * self.n
+        self._need(m_start, per * 3, "m_start"), self._need(u, samples * self.S * self.n_in, "u")
+        self._need(gs, samples * per * 3, "grad_states"), self._need(gf, per * 3, "grad_final")
+        self._need(gW, self.n * self.n, "grad_W", True), self._need(gwin, self.n * self.n_in, "grad_w_in", True)
+        self._need(gm0, per * 3, "grad_m0", True), self._need(gsc, 4, "grad_scalars", True)
+        self.calls.append("adjoint")
+        return 0
+
+    def reservoir_destroy(self, h):
+        pass
+
+    def sto_last_error(self):
+        return b""
+
+
+@pytest.mark.parametrize("streams", [1, 3])
+def test_binding_host_buffers_have_the_header_sizes(stx, monkeypatch, streams):
+    """Guards the host arrays of reservoir_run, reservoir_get_state and
+    reservoir_adjoint for one stream and several: a binding that sized an
+    output for one stream while the library writes S of them overran the
+    heap (glibc reported the corruption later, in an unrelated free)."""
+    registry = {}
+    real_dptr = stx._dptr
+
+    def dptr(a):
+        registry[a.ctypes.data] = a.nbytes
+        return real_dptr(a)
+
+    n, n_in, samples = 6, 2, 4
+    fake = _FakeLib(registry, n, n_in, streams)
+    monkeypatch.setattr(stx, "_dptr", dptr)
+    monkeypatch.setattr(stx, "_lib", fake)
+    rng = np.random.default_rng(0)
+    m0 = rng.standard_normal((n, 3)) if streams == 1 else rng.standard_normal((streams, n, 3))
+    r = stx.Reservoir(rng.standard_normal((n, n)), rng.standard_normal((n, n_in)), m0,
+                      _ok_params(stx, substeps=5), streams=streams)
+    u = rng.standard_normal((samples, streams, n_in))
+    rec = r.run(u)
+    assert rec.size == samples * streams * n * 3 and np.all(rec == 0.5)
+    st = r.get_state()
+    assert st.size == streams * n * 3 and np.all(st == 0.5)
+    r.set_state(st)
+    g = rng.standard_normal(rec.shape)
+    out = r.adjoint(m0, u, grad_states=g, grad_final=st)
+    assert out["m0"].size == streams * n * 3 and np.all(out["m0"] == 0.5)
+    assert out["W"].shape == (n, n) and out["w_in"].shape == (n, n_in)
+    assert fake.calls == ["run", "get_state", "adjoint"]
+    r.close()
+
+
+def test_fake_library_catches_an_undersized_output(stx, monkeypatch):
+    """The check above fails for a buffer one stream short (the mistake it guards)."""
+    registry = {}
+    fake = _FakeLib(registry, 4, 1, 2)
+    buf = np.empty((4, 3))                       # room for one stream only
+    registry[buf.ctypes.data] = buf.nbytes
+    with pytest.raises(AssertionError, match="grad_m0"):
+        fake._need(stx._dptr(buf), 2 * 4 * 3, "grad_m0", write=True)

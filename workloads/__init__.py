@@ -19,6 +19,7 @@ from .inputs import (  # noqa: F401
     draw_input_weights,
     draw_inputs,
     draw_target,
+    make_paper_arrays,
     make_stream_arrays,
     make_sweep_arrays,
     make_workload_arrays,

@@ -194,6 +194,16 @@ def make_stream_arrays(wl: Workload, streams: int, samples: Optional[int] = None
     return {"W": base["W"], "w_in": base["w_in"], "m0": base["m0"], "u": u, "y": y}
 
 
+def make_paper_arrays(n: int, samples: int) -> Dict[str, np.ndarray]:
+    """The paper's benchmark setup at size n (Sec. 3.2): u = 0, the paper's
+    coupling generator (U[-1,1], zero diagonal, spectral radius 1), U[-1,1]
+    input weights and the identical initial tilt of Eq. (initial).  The
+    arrays of size n come from SeedSequence([0, 5000 + n])."""
+    g_w, g_in, g_m0, _ = seed_streams(0, 5000 + n)
+    return {"W": draw_coupling(g_w, n, "paper"), "w_in": draw_input_weights(g_in, n, 1),
+            "m0": draw_initial(g_m0, n, "paper"), "u": np.zeros((samples, 1))}
+
+
 @dataclasses.dataclass(frozen=True)
 class Sweep:
     """A parameter sweep: ``count`` reservoirs of log-uniform size in
