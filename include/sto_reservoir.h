@@ -251,6 +251,40 @@ int64_t reservoir_streams(const sto_reservoir *r);
 /* reservoir_path -- the sto_path the handle runs (never STO_PATH_AUTO). */
 int32_t reservoir_path(const sto_reservoir *r);
 
+/*
+ * reservoir_trace_phases -- diagnostic of the persistent paths
+ * (STO_PATH_RESIDENT, STO_PATH_MULTI), which exchange the stage inputs of
+ * every RK4 stage (paper, Sec. 3.3: the coupling W^cp x needs all of x)
+ * through global memory.  stages > 0 arms a trace: every later run of the
+ * handle has wave 0 of each workgroup stamp the device's constant-rate
+ * clock at four points of each of its first `stages` RK4 stages, counted
+ * from the start of that run: 0 stage start, 1 stage input gathered, 2 own
+ * rows computed, 3 own rows published.  stages == 0 frees the trace.  The
+ * handle owns the trace buffer (groups * stages * 4 * 8 bytes).
+ * Errors: STO_E_INVALID, STO_E_UNSUPPORTED (any other path), STO_E_NOMEM.
+ *
+ * reservoir_phase_times -- copies the stamps of the last run into out
+ * (host, groups * stages * 4 values, [group][stage][point]; capacity is its
+ * length; NULL only queries the sizes) after the handle's stream has
+ * finished.  Fills *groups and
+ * *stages (0 when no trace is armed) and *clock_khz, the clock's rate.
+ * A stamp of 0 was not reached (a stage beyond the run's last).
+ */
+sto_status reservoir_trace_phases(sto_reservoir *r, int64_t stages);
+
+/*
+ * reservoir_adjoint_kernels -- which kernel families the handle's last
+ * adjoint call (reservoir_adjoint*) ran, as a bit mask: 1 forward passes
+ * with one launch per RK4 stage, 2 forward passes in one persistent launch
+ * per segment, 4 reversed stages with one launch per stage, 8 reversed
+ * stages in one persistent launch per segment.  0 before the first adjoint
+ * call, -1 for a NULL handle.  Lets a caller (and the tests) see whether the
+ * persistent kernels ran or the call fell back to the per-stage ones.
+ */
+int32_t reservoir_adjoint_kernels(const sto_reservoir *r);
+sto_status reservoir_phase_times(const sto_reservoir *r, uint64_t *out, int64_t capacity, int64_t *groups,
+                                 int64_t *stages, int64_t *clock_khz);
+
 /* reservoir_destroy -- free the handle and its device memory; NULL is a no-op. */
 void reservoir_destroy(sto_reservoir *r);
 

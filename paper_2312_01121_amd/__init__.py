@@ -130,6 +130,13 @@ def _load():
     lib.readout_grad_device.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, vp, ctypes.c_int64,
                                         ctypes.c_double, ctypes.c_int32, vp, vp, dp, vp]
     lib.readout_grad_device.restype = ctypes.c_int
+    lib.reservoir_adjoint_kernels.argtypes = [H]
+    lib.reservoir_adjoint_kernels.restype = ctypes.c_int32
+    lib.reservoir_trace_phases.argtypes = [H, ctypes.c_int64]
+    lib.reservoir_trace_phases.restype = ctypes.c_int
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    lib.reservoir_phase_times.argtypes = [H, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int64, i64p, i64p, i64p]
+    lib.reservoir_phase_times.restype = ctypes.c_int
     lib.sto_last_error.restype = ctypes.c_char_p
     for name in ("reservoir_create", "reservoir_create_streams", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
                  "reservoir_set_state", "readout_fit"):
@@ -143,6 +150,7 @@ EXPORTED = ("reservoir_create", "reservoir_create_streams", "reservoir_streams",
             "reservoir_set_state", "reservoir_path", "reservoir_destroy", "readout_fit", "readout_fit_device",
             "readout_fit_batch_device", "sweep_create", "sweep_nodes", "sweep_run", "sweep_run_device", "sweep_get_state", "sweep_destroy",
             "reservoir_adjoint", "reservoir_adjoint_device", "reservoir_adjoint_records_device", "readout_grad_device",
+            "reservoir_trace_phases", "reservoir_phase_times", "reservoir_adjoint_kernels",
             "sto_read_bandwidth", "sto_set_stream_variant", "sto_last_error")
 
 SCALAR_NAMES = ("a_cp", "a_in", "h_s", "h_appl")
@@ -223,6 +231,28 @@ def reservoir_set_state(h, m):
 
 def reservoir_path(h) -> int:
     return int(_lib.reservoir_path(h))
+
+
+ADJ_FWD_STAGE, ADJ_FWD_PERSISTENT, ADJ_REV_STAGE, ADJ_REV_PERSISTENT = 1, 2, 4, 8
+
+
+def reservoir_adjoint_kernels(h) -> int:
+    return int(_lib.reservoir_adjoint_kernels(h))
+
+
+def reservoir_trace_phases(h, stages: int):
+    _check(_lib.reservoir_trace_phases(h, stages))
+
+
+def reservoir_phase_times(h):
+    """(stamps [group][stage][point] as uint64, clock rate in kHz)."""
+    g, st, khz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.reservoir_phase_times(h, None, 0, ctypes.byref(g), ctypes.byref(st), ctypes.byref(khz)))
+    out = np.zeros((g.value, st.value, 4), dtype=np.uint64)
+    if out.size:
+        _check(_lib.reservoir_phase_times(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), out.size,
+                                          ctypes.byref(g), ctypes.byref(st), ctypes.byref(khz)))
+    return out, int(khz.value)
 
 
 def reservoir_destroy(h):
@@ -479,6 +509,21 @@ class Reservoir:
                                  grad_final_dev, out.get("W"), out.get("w_in"), out.get("m0"), out.get("scalars"),
                                  checkpoint_every, stream, records_dev)
         return out
+
+    @property
+    def adjoint_kernels(self) -> dict:
+        """Kernel families of the last adjoint call on this handle."""
+        m = reservoir_adjoint_kernels(self.h)
+        return {"forward": ("persistent" if m & ADJ_FWD_PERSISTENT else "stage" if m & ADJ_FWD_STAGE else None),
+                "reverse": ("persistent" if m & ADJ_REV_PERSISTENT else "stage" if m & ADJ_REV_STAGE else None)}
+
+    def trace_phases(self, stages: int):
+        """Arm (stages > 0) or free (0) the phase trace of the persistent paths."""
+        reservoir_trace_phases(self.h, stages)
+
+    def phase_times(self):
+        """Stamps of the last run: (uint64 [group][stage][point], clock kHz)."""
+        return reservoir_phase_times(self.h)
 
     def get_state(self) -> np.ndarray:
         m = reservoir_get_state(self.h, self.n * self.streams)

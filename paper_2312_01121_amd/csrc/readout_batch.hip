@@ -327,15 +327,31 @@ __global__ void __launch_bounds__(1024) k_bnmse(const RItem* __restrict__ items,
 
 }  // namespace
 
-int readout_solve_batch(int count, const void* const* rec, const int64_t* stride, int rec_f32, int rows,
-                        const int64_t* n, int features, const double* const* y, double lam, double* const* w_dev,
-                        double* nmse_host, hipStream_t stream, const char** err, int* bad_item) {
-    *bad_item = -1;
-    std::vector<RItem> items(count);
+namespace {
+
+__global__ void k_zero_ints(int* p, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Items, tile lists and the workspace layout of one batched readout.
+struct Plan {
+    std::vector<RItem> items;
+    std::vector<int64_t> gstart, ustart;
+    int panels = 0, max_m = 0, max_cols = 0;
+    // byte offsets of the device buffers in one workspace, and its size
+    size_t o_items = 0, o_gstart = 0, o_ustart = 0, o_phi = 0, o_c = 0, o_rhs = 0, o_res = 0, o_sums = 0,
+           o_bad = 0, bytes = 0;
+};
+
+Plan make_plan(int count, const void* const* rec, const int64_t* stride, int rows, const int64_t* n, int features,
+               const double* const* y, double* const* w_dev) {
+    Plan pl;
+    pl.items.resize(count);
     int64_t phi_total = 0, c_total = 0, rhs_total = 0;
-    int max_m = 0, max_cols = 0;
     for (int q = 0; q < count; ++q) {
-        RItem& it = items[q];
+        RItem& it = pl.items[q];
         it.rec = rec[q];
         it.stride = stride[q];
         it.y = y[q];
@@ -350,30 +366,58 @@ int readout_solve_batch(int count, const void* const* rec, const int64_t* stride
         phi_total += (int64_t)rows * it.cols;
         c_total += (int64_t)it.m * it.m;
         rhs_total += std::max(it.m, it.cols);
-        max_m = std::max(max_m, it.m);
-        max_cols = std::max(max_cols, it.cols);
+        pl.max_m = std::max(pl.max_m, it.m);
+        pl.max_cols = std::max(pl.max_cols, it.cols);
     }
     // tile lists: the Gram matrices, and the trailing update after each panel
-    const int panels = (max_m + kNB - 1) / kNB;
-    std::vector<int64_t> gstart(count + 1, 0), ustart((size_t)panels * (count + 1), 0);
+    pl.panels = (pl.max_m + kNB - 1) / kNB;
+    pl.gstart.assign(count + 1, 0);
+    pl.ustart.assign((size_t)pl.panels * (count + 1), 0);
     auto tri = [](int64_t edge) {
         const int64_t nt = (edge + kT - 1) / kT;
         return nt * (nt + 1) / 2;
     };
-    for (int q = 0; q < count; ++q) gstart[q + 1] = gstart[q] + tri(items[q].m);
-    for (int p = 0; p < panels; ++p) {
-        int64_t* us = &ustart[(size_t)p * (count + 1)];
+    for (int q = 0; q < count; ++q) pl.gstart[q + 1] = pl.gstart[q] + tri(pl.items[q].m);
+    for (int p = 0; p < pl.panels; ++p) {
+        int64_t* us = &pl.ustart[(size_t)p * (count + 1)];
         for (int q = 0; q < count; ++q) {
-            const int j0 = p * kNB, m = items[q].m;
+            const int j0 = p * kNB, m = pl.items[q].m;
             const int rem = j0 < m ? m - std::min(m, j0 + kNB) : 0;
             us[q + 1] = us[q] + tri(rem);
         }
     }
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t at = off;
+        off += align256(std::max<size_t>(b, 1));
+        return at;
+    };
+    pl.o_items = take(sizeof(RItem) * count);
+    pl.o_gstart = take(8 * pl.gstart.size());
+    pl.o_ustart = take(8 * pl.ustart.size());
+    pl.o_phi = take((size_t)phi_total * 8);
+    pl.o_c = take((size_t)c_total * 8);
+    pl.o_rhs = take((size_t)rhs_total * 8);
+    pl.o_res = take((size_t)count * rows * 8);
+    pl.o_sums = take((size_t)count * 16);
+    pl.o_bad = take((size_t)count * 2 * sizeof(int));
+    pl.bytes = off;
+    return pl;
+}
 
-    RItem* items_d = nullptr;
-    int64_t *gstart_d = nullptr, *ustart_d = nullptr;
-    double *phi = nullptr, *C = nullptr, *rhs = nullptr, *res = nullptr, *sums = nullptr;
-    int* bad = nullptr;
+// The fit itself, every device buffer carved out of the workspace ws.
+int solve_in(const Plan& pl, void* ws, int count, int rec_f32, int rows, int features, double lam,
+             double* nmse_host, hipStream_t stream, const char** err, int* bad_item) {
+    char* base = static_cast<char*>(ws);
+    RItem* items_d = reinterpret_cast<RItem*>(base + pl.o_items);
+    int64_t* gstart_d = reinterpret_cast<int64_t*>(base + pl.o_gstart);
+    int64_t* ustart_d = reinterpret_cast<int64_t*>(base + pl.o_ustart);
+    double* phi = reinterpret_cast<double*>(base + pl.o_phi);
+    double* C = reinterpret_cast<double*>(base + pl.o_c);
+    double* rhs = reinterpret_cast<double*>(base + pl.o_rhs);
+    double* res = reinterpret_cast<double*>(base + pl.o_res);
+    double* sums = reinterpret_cast<double*>(base + pl.o_sums);
+    int* bad = reinterpret_cast<int*>(base + pl.o_bad);
     int rc = 0;
     auto check = [&](hipError_t e) {
         if (e != hipSuccess && rc == 0) {
@@ -384,24 +428,21 @@ int readout_solve_batch(int count, const void* const* rec, const int64_t* stride
     };
     std::vector<int> hbad(2 * count, 0);
     std::vector<double> hsums(2 * count, 0.0);
-    if (check(hipMalloc(&items_d, sizeof(RItem) * count)) && check(hipMalloc(&gstart_d, 8 * gstart.size())) &&
-        check(hipMalloc(&ustart_d, 8 * std::max<size_t>(1, ustart.size()))) &&
-        check(hipMalloc(&phi, (size_t)phi_total * 8)) && check(hipMalloc(&C, (size_t)c_total * 8)) &&
-        check(hipMalloc(&rhs, (size_t)rhs_total * 8)) && check(hipMalloc(&res, (size_t)count * rows * 8)) &&
-        check(hipMalloc(&sums, (size_t)count * 16)) &&
-        check(hipMalloc(&bad, (size_t)count * 2 * sizeof(int))) &&
-        check(hipMemcpyAsync(items_d, items.data(), sizeof(RItem) * count, hipMemcpyHostToDevice, stream)) &&
-        check(hipMemcpyAsync(gstart_d, gstart.data(), 8 * gstart.size(), hipMemcpyHostToDevice, stream)) &&
+    const int max_m = pl.max_m, max_cols = pl.max_cols, panels = pl.panels;
+    const std::vector<int64_t>& ustart = pl.ustart;
+    hipLaunchKernelGGL(k_zero_ints, dim3((2 * count + 255) / 256), dim3(256), 0, stream, bad, 2 * count);
+    if (check(hipGetLastError()) &&
+        check(hipMemcpyAsync(items_d, pl.items.data(), sizeof(RItem) * count, hipMemcpyHostToDevice, stream)) &&
+        check(hipMemcpyAsync(gstart_d, pl.gstart.data(), 8 * pl.gstart.size(), hipMemcpyHostToDevice, stream)) &&
         (ustart.empty() ||
-         check(hipMemcpyAsync(ustart_d, ustart.data(), 8 * ustart.size(), hipMemcpyHostToDevice, stream))) &&
-        check(hipMemsetAsync(bad, 0, (size_t)count * 2 * sizeof(int), stream))) {
+         check(hipMemcpyAsync(ustart_d, ustart.data(), 8 * ustart.size(), hipMemcpyHostToDevice, stream)))) {
         const dim3 per_item(256, count);
         if (rec_f32)
             hipLaunchKernelGGL(k_bgather<float>, per_item, dim3(256), 0, stream, items_d, rows, features, phi, bad);
         else
             hipLaunchKernelGGL(k_bgather<double>, per_item, dim3(256), 0, stream, items_d, rows, features, phi, bad);
-        hipLaunchKernelGGL(k_bgram, dim3((unsigned)gstart[count]), dim3(kT, kT), 0, stream, items_d, gstart_d, count,
-                           rows, lam, phi, C);
+        hipLaunchKernelGGL(k_bgram, dim3((unsigned)pl.gstart[count]), dim3(kT, kT), 0, stream, items_d, gstart_d,
+                           count, rows, lam, phi, C);
         hipLaunchKernelGGL(k_bvec, dim3((max_m + 255) / 256, count), dim3(256), 0, stream, items_d, rows, phi, rhs, 0,
                            bad);
         for (int p = 0; p < panels; ++p) {
@@ -436,9 +477,24 @@ int readout_solve_batch(int count, const void* const* rec, const int64_t* stride
         if (rc == 0)
             for (int q = 0; q < count; ++q) nmse_host[q] = hsums[2 * q] / hsums[2 * q + 1];
     }
-    for (void* p : {(void*)items_d, (void*)gstart_d, (void*)ustart_d, (void*)phi, (void*)C, (void*)rhs, (void*)res,
-                    (void*)sums, (void*)bad})
-        if (p) (void)hipFree(p);
+    return rc;
+}
+
+}  // namespace
+
+int readout_solve_batch(int count, const void* const* rec, const int64_t* stride, int rec_f32, int rows,
+                        const int64_t* n, int features, const double* const* y, double lam, double* const* w_dev,
+                        double* nmse_host, hipStream_t stream, const char** err, int* bad_item) {
+    *bad_item = -1;
+    const Plan pl = make_plan(count, rec, stride, rows, n, features, y, w_dev);
+    void* ws = nullptr;
+    hipError_t e = hipMalloc(&ws, pl.bytes);
+    if (e != hipSuccess) {
+        if (err) *err = hipGetErrorString(e);
+        return 2;
+    }
+    const int rc = solve_in(pl, ws, count, rec_f32, rows, features, lam, nmse_host, stream, err, bad_item);
+    (void)hipFree(ws);
     return rc;
 }
 

@@ -126,6 +126,11 @@ struct sto_reservoir {
     int* sync = nullptr;
     int cur = 0;
     hipStream_t stream = nullptr;
+    int adjoint_kernels = 0;   // kernel families of the last adjoint call
+    // phase trace of the persistent paths (reservoir_trace_phases)
+    unsigned long long* trace = nullptr;
+    int64_t trace_stages = 0;
+    int64_t trace_groups = 0;
     // scratch for the host-buffer entry point
     double* u_dev = nullptr;
     size_t u_cap = 0;
@@ -176,7 +181,7 @@ sto::DevState<T> dev_state(const sto_reservoir* r) {
 
 void free_all(sto_reservoir* r) {
     void* ptrs[] = {r->W, r->Wt, r->w_in, r->m, r->ms[0], r->ms[1], r->acc, r->xchg, r->bad, r->sync, r->u_dev,
-                    r->states_dev};
+                    r->states_dev, r->trace};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (r->stream) (void)hipStreamDestroy(r->stream);
@@ -263,6 +268,9 @@ hipError_t dispatch(sto_reservoir* r, const double* u_dev, int samples, void* st
     spec.renorm = r->prm.renormalize;
     spec.xyz = r->prm.coupling == STO_COUPLE_XYZ;
     spec.stream = s;
+    spec.trace = r->trace;
+    spec.trace_stages = (int)r->trace_stages;
+    spec.trace_groups = (int)r->trace_groups;
     switch (r->path) {
         case STO_PATH_SMALL: return sto::run_small<T>(d, k, spec);
         case STO_PATH_RESIDENT: return sto::run_resident<T>(d, k, spec);
@@ -383,6 +391,7 @@ sto_status adjoint_dispatch(sto_reservoir* r, const void* m_start, const double*
     a.seg_steps = seg;
     a.bad = r->bad;
     a.stream = stream;
+    a.kernels = &r->adjoint_kernels;
     hipError_t e = sto::adjoint_run<T>(a);
     if (e == hipErrorLaunchTimeOut)
         return fail(STO_E_DEVICE,
@@ -712,6 +721,58 @@ sto_status reservoir_create_streams(int64_t n, int64_t n_in, int64_t streams, co
         if (st != STO_OK) return cleanup(st);
     }
     *out = r;
+    return STO_OK;
+}
+
+int32_t reservoir_adjoint_kernels(const sto_reservoir* r) { return r ? r->adjoint_kernels : -1; }
+
+sto_status reservoir_trace_phases(sto_reservoir* r, int64_t stages) {
+    if (!r) return fail(STO_E_INVALID, "handle is NULL");
+    if (stages < 0 || stages > (1 << 20)) return fail(STO_E_INVALID, "stages out of range: %lld", (long long)stages);
+    if (r->trace) {
+        HIP_TRY(hipStreamSynchronize(r->stream), "trace");
+        HIP_TRY(hipFree(r->trace), "hipFree trace");
+        r->trace = nullptr;
+    }
+    r->trace_stages = r->trace_groups = 0;
+    if (stages == 0) return STO_OK;
+    const int xyz = r->prm.coupling == STO_COUPLE_XYZ;
+    int groups = 0;
+    if (r->path == STO_PATH_RESIDENT) {
+        if (!sto::resident_shape((int)r->n, (int)r->elem, xyz, &groups, nullptr, nullptr))
+            return fail(STO_E_UNSUPPORTED, "resident shape does not fit");
+    } else if (r->path == STO_PATH_MULTI) {
+        int gx = 0, gy = 0;
+        if (!sto::multi_fits((int)r->n, (int)r->streams, xyz, &gx, &gy))
+            return fail(STO_E_UNSUPPORTED, "multi-stream shape does not fit");
+        groups = gx * gy;
+    } else {
+        return fail(STO_E_UNSUPPORTED, "phase traces exist for the resident and multi-stream paths only");
+    }
+    const size_t bytes = (size_t)groups * stages * 4 * sizeof(unsigned long long);
+    HIP_TRY(hipMalloc(&r->trace, bytes), "hipMalloc trace");
+    HIP_TRY(hipMemset(r->trace, 0, bytes), "hipMemset trace");
+    r->trace_stages = stages;
+    r->trace_groups = groups;
+    return STO_OK;
+}
+
+sto_status reservoir_phase_times(const sto_reservoir* r, uint64_t* out, int64_t capacity, int64_t* groups,
+                                 int64_t* stages, int64_t* clock_khz) {
+    if (!r) return fail(STO_E_INVALID, "handle is NULL");
+    if (!groups || !stages || !clock_khz) return fail(STO_E_INVALID, "groups, stages and clock_khz are required");
+    *groups = r->trace_groups;
+    *stages = r->trace_stages;
+    int dev = 0, khz = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "wall clock rate");
+    *clock_khz = khz;
+    const int64_t count = r->trace_groups * r->trace_stages * 4;
+    if (count == 0 || !out) return STO_OK;   // out NULL: a query of the sizes
+    if (capacity < count) return fail(STO_E_INVALID, "out must hold %lld values", (long long)count);
+    HIP_TRY(hipStreamSynchronize(r->stream), "trace");
+    HIP_TRY(hipDeviceSynchronize(), "trace");
+    HIP_TRY(hipMemcpy(out, r->trace, (size_t)count * sizeof(uint64_t), hipMemcpyDeviceToHost), "trace copy");
     return STO_OK;
 }
 

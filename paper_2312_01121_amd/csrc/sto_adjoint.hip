@@ -623,8 +623,10 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
     };
     // forward over local steps [0, kn) of the segment starting at j0; the
     // state is in m and ms[0] (cur = 0 between steps)
+    int used = 0;   // ADJ_* kernel families run
     auto forward = [&](int64_t j0, int64_t kn, int trace) -> hipError_t {
         d.j0 = j0;
+        used |= use_multi ? ADJ_FWD_PERSISTENT : ADJ_FWD_STAGE;
         if constexpr (sizeof(T) == 4) {
             if (use_multi) {
                 DevState<float> ds{};
@@ -698,6 +700,7 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
         if (!reversed)
             for (int64_t kk = kn - 1; kk >= 0; --kk)
                 for (int stage = 3; stage >= 0; --stage) rev_stage((int)kk, stage);
+        used |= reversed ? ADJ_REV_PERSISTENT : ADJ_REV_STAGE;
         ADJ_TRY(hipGetLastError());
         if (a.g_W) {
             // rows of the panels: (step, stage, stream, component), pitch ld
@@ -742,6 +745,7 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
         hipLaunchKernelGGL(k_adj_scalars, dim3(1), dim3(256), 0, st, d.gacc, n, NS, ld, a.g_scal);
         ADJ_TRY(hipGetLastError());
     }
+    if (a.kernels) *a.kernels = used;
     // the workspace is freed on return: wait for the work that uses it
     int aborted = 0;
     if (msync) ADJ_TRY(hipMemcpyAsync(&aborted, msync + 64, sizeof(int), hipMemcpyDeviceToHost, st));

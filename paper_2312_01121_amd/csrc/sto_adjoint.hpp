@@ -33,6 +33,15 @@ struct AdjArgs {
     int64_t seg_steps;   // RK4 steps per recomputed segment (>= 1)
     int* bad;            // device flag: first non-finite sample (INT_MAX: none)
     hipStream_t stream;
+    int* kernels;        // host, or nullptr: receives the ADJ_* kernel families the call ran
+};
+
+// Kernel families an adjoint call ran (bit mask; reservoir_adjoint_kernels).
+enum : int {
+    ADJ_FWD_STAGE = 1,        // forward passes with one launch per RK4 stage
+    ADJ_FWD_PERSISTENT = 2,   // forward passes in one persistent launch per segment
+    ADJ_REV_STAGE = 4,        // reversed stages with one launch per stage
+    ADJ_REV_PERSISTENT = 8,   // reversed stages in one persistent launch per segment
 };
 
 // Bytes of the per-step stage trace (the workspace per step of a segment).

@@ -79,6 +79,11 @@ struct RunSpec {
     int renorm;
     int xyz;
     hipStream_t stream;
+    // persistent paths: device-clock stamps of the exchange phases of the
+    // first trace_stages stages, 4 per stage and workgroup (nullptr: none)
+    unsigned long long* trace = nullptr;
+    int trace_stages = 0;
+    int trace_groups = 0;    // workgroups the trace buffer holds
 };
 
 // Launch-shape choices, fixed defaults overridable through the environment
@@ -114,6 +119,9 @@ int small_max_n(int elem_bytes, int xyz);
 // Whether the resident kernel can hold n on this device (W split across
 // co-resident workgroups' LDS); fills the chosen grid size.
 bool resident_fits(int n, int elem_bytes, int xyz, int* grid_out);
+// The resident kernel's launch shape for n (grid, rows per workgroup,
+// threads per workgroup); false if it does not fit.
+bool resident_shape(int n, int elem_bytes, int xyz, int* grid_out, int* rpb_out, int* block_out);
 
 // Offset (in ints) of the abort flag in DevState::sync; non-zero after a
 // resident run means a grid barrier timed out.

@@ -34,6 +34,13 @@
 // abort flag, and every workgroup that sees it leaves the kernel, so a grid
 // that is not co-resident ends with an error instead of a hang.  The
 // cooperative launch itself refuses grids that cannot be co-resident.
+//
+// Launch shape: BLOCK threads (4, 8 or 16 waves) and rows_per_block rows of
+// W per workgroup, at most 4 rows per wave (1 with 16 waves).  The default is 4 waves and
+// ceil(n / CUs) rows.  With a trace buffer, wave 0 of every workgroup
+// stamps the device's constant-rate clock at four points of each of the
+// first trace_stages stages (stage start, gather done, own rows computed,
+// own rows published), for the phase breakdown of the exchange.
 
 #include <climits>
 
@@ -43,9 +50,9 @@ namespace sto {
 
 namespace {
 
-constexpr int kBlock = 256;              // 4 waves
-constexpr int kWaves = kBlock / 64;
-constexpr int kMaxRowsPerWave = 4;       // rows per workgroup <= 16
+// rows per wave: up to 4 with 4 or 8 waves; one with 16 waves, whose
+// register budget (128 per lane) holds one row's state without spilling
+constexpr int max_rows_per_wave(int block) { return block >= 1024 ? 1 : 4; }
 constexpr int kSpinLimit = 1 << 20;      // poll rounds (one memory round trip each)
 constexpr size_t kLdsMax = 160 * 1024;
 
@@ -71,12 +78,12 @@ __device__ __forceinline__ void rearm(T* p) {
 
 // Wait until the n entries of src are published and copy them to LDS.
 // Returns false if the wait was abandoned (spin limit or abort flag).
-template <typename T>
+template <typename T, int BLOCK>
 __device__ bool gather_stage_input(const T* src, T* dst, int n, int* abort_flag) {
     using B = typename Bits<T>::type;
     const B* s = reinterpret_cast<const B*>(src);
     bool ok = true;
-    for (int i0 = 0; i0 < n; i0 += 4 * kBlock) {
+    for (int i0 = 0; i0 < n; i0 += 4 * BLOCK) {
         B v[4];
         bool pending = true;
         int rounds = 0;
@@ -84,12 +91,12 @@ __device__ bool gather_stage_input(const T* src, T* dst, int n, int* abort_flag)
             pending = false;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int i = i0 + q * kBlock + threadIdx.x;
+                const int i = i0 + q * BLOCK + threadIdx.x;
                 v[q] = i < n ? __hip_atomic_load(s + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : B(0);
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int i = i0 + q * kBlock + threadIdx.x;
+                const int i = i0 + q * BLOCK + threadIdx.x;
                 if (i < n) {
                     if (v[q] == sentinel<T>()) pending = true;
                     else dst[i] = __builtin_bit_cast(T, v[q]);
@@ -112,10 +119,19 @@ __device__ bool gather_stage_input(const T* src, T* dst, int n, int* abort_flag)
     return ok;
 }
 
-template <typename T, bool XYZ>
-__global__ void __launch_bounds__(kBlock) k_resident(DevState<T> d, Coef<T> k, const double* __restrict__ u,
-                                                     T* __restrict__ states, int samples, int substeps,
-                                                     int cur, int renorm, int rows_per_block, int wld) {
+__device__ __forceinline__ void stamp(unsigned long long* trace, int trace_stages, int sigma, int point) {
+    if (trace && sigma < trace_stages && threadIdx.x == 0)
+        trace[((size_t)blockIdx.x * trace_stages + sigma) * 4 + point] = wall_clock64();
+}
+
+template <typename T, bool XYZ, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_resident(DevState<T> d, Coef<T> k, const double* __restrict__ u,
+                                                    T* __restrict__ states, int samples, int substeps,
+                                                    int cur, int renorm, int rows_per_block, int wld,
+                                                    unsigned long long* trace, int trace_stages) {
+    constexpr int kBlock = BLOCK;
+    constexpr int kWaves = BLOCK / 64;
+    constexpr int kMaxRowsPerWave = max_rows_per_wave(BLOCK);
     using A = Acc<T>;
     using AT = typename A::type;
     constexpr int C = XYZ ? 3 : 1;                           // exchanged components
@@ -170,12 +186,15 @@ __global__ void __launch_bounds__(kBlock) k_resident(DevState<T> d, Coef<T> k, c
                 T* xout = xbuf + (int64_t)((sigma + 1) % 3) * C * ld;
                 T* xold = xbuf + (int64_t)((sigma + 2) % 3) * C * ld;
                 __syncthreads();   // every wave is done with xs of the previous stage
+                stamp(trace, trace_stages, sigma, 0);
                 bool ok = true;
 #pragma unroll
-                for (int c = 0; c < C; ++c) ok = ok && gather_stage_input<T>(xin + c * ld, xs + c * n, n, abort_flag);
+                for (int c = 0; c < C; ++c)
+                    ok = ok && gather_stage_input<T, BLOCK>(xin + c * ld, xs + c * n, n, abort_flag);
                 if (!ok) ok_lds = 0;
                 __syncthreads();
                 if (ok_lds == 0) return;
+                stamp(trace, trace_stages, sigma, 1);
                 // step 3 early: re-arm this wave's rows of the buffer two
                 // stages ahead as soon as the gather is done (every workgroup
                 // finished reading it: the gather saw all outputs of the
@@ -251,6 +270,7 @@ __global__ void __launch_bounds__(kBlock) k_resident(DevState<T> d, Coef<T> k, c
                     sy[q] = ny;
                     sz[q] = nz;
                 }
+                stamp(trace, trace_stages, sigma, 2);
                 // step 4: publish this wave's rows once the re-arm stores have
                 // completed (one wait for all rows; the clobber keeps the
                 // compiler from moving the stores across it)
@@ -268,6 +288,7 @@ __global__ void __launch_bounds__(kBlock) k_resident(DevState<T> d, Coef<T> k, c
                         }
                     }
                 }
+                stamp(trace, trace_stages, sigma, 3);
             }
         }
         if (lane == 0) {
@@ -329,23 +350,66 @@ size_t resident_lds(int n, int rows_per_block, int elem, int xyz) {
     return ((size_t)rows_per_block * wld_of(n) + (xyz ? 3 : 1) * (size_t)n) * elem;
 }
 
+template <typename T, bool XYZ>
+const void* resident_fn(int block) {
+    switch (block) {
+        case 256: return reinterpret_cast<const void*>(&k_resident<T, XYZ, 256>);
+        case 512: return reinterpret_cast<const void*>(&k_resident<T, XYZ, 512>);
+        case 1024: return reinterpret_cast<const void*>(&k_resident<T, XYZ, 1024>);
+        default: return nullptr;
+    }
+}
+
+const void* resident_kernel(int elem, int xyz, int block) {
+    if (elem == 8) return xyz ? resident_fn<double, true>(block) : resident_fn<double, false>(block);
+    return xyz ? resident_fn<float, true>(block) : resident_fn<float, false>(block);
+}
+
+int env_int(const char* name) {
+    const char* v = getenv(name);
+    return v && *v ? atoi(v) : 0;
+}
+
 }  // namespace
 
-bool resident_fits(int n, int elem_bytes, int xyz, int* grid_out) {
+// Launch shape of the resident kernel for n: rows per workgroup, threads per
+// workgroup and grid.  Default: 4 waves and ceil(n / CUs) rows, so that the
+// grid covers at most one workgroup per CU.  STO_RESIDENT_RPB (rows per
+// workgroup) and STO_RESIDENT_WAVES (4, 8 or 16) override it for
+// measurements.  False if the shape does not fit (LDS, rows per wave) or its
+// workgroups cannot all be co-resident.
+bool resident_shape(int n, int elem_bytes, int xyz, int* grid_out, int* rpb_out, int* block_out) {
     const int cus = device_cus();
     if (cus <= 0 || n < 2) return false;
-    const int rpb = (n + cus - 1) / cus;
-    if (rpb > kWaves * kMaxRowsPerWave) return false;
-    if (resident_lds(n, rpb, elem_bytes, xyz) + 64 > kLdsMax) return false;
-    if (grid_out) *grid_out = (n + rpb - 1) / rpb;
+    int waves = env_int("STO_RESIDENT_WAVES");
+    if (waves != 4 && waves != 8 && waves != 16) waves = 4;
+    int rpb = env_int("STO_RESIDENT_RPB");
+    if (rpb <= 0) rpb = (n + cus - 1) / cus;
+    const int block = 64 * waves;
+    if (rpb > waves * max_rows_per_wave(block)) return false;
+    const size_t lds = resident_lds(n, rpb, elem_bytes, xyz);
+    if (lds + 64 > kLdsMax) return false;
+    const int grid = (n + rpb - 1) / rpb;
+    const void* fn = resident_kernel(elem_bytes, xyz, block);
+    if (!fn) return false;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return false;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess) return false;
+    if ((int64_t)per_cu * cus < grid) return false;
+    if (grid_out) *grid_out = grid;
+    if (rpb_out) *rpb_out = rpb;
+    if (block_out) *block_out = block;
     return true;
+}
+
+bool resident_fits(int n, int elem_bytes, int xyz, int* grid_out) {
+    return resident_shape(n, elem_bytes, xyz, grid_out, nullptr, nullptr);
 }
 
 template <typename T>
 hipError_t run_resident(const DevState<T>& d, const Coef<T>& k, const RunSpec& r) {
-    int grid = 0;
-    if (!resident_fits(d.n, sizeof(T), r.xyz, &grid)) return hipErrorInvalidValue;
-    int rpb = (d.n + grid - 1) / grid;
+    int grid = 0, rpb = 0, block = 0;
+    if (!resident_shape(d.n, sizeof(T), r.xyz, &grid, &rpb, &block)) return hipErrorInvalidValue;
     int wld = (int)wld_of(d.n);
     const size_t lds = resident_lds(d.n, rpb, sizeof(T), r.xyz);
     const int C = r.xyz ? 3 : 1;
@@ -363,12 +427,12 @@ hipError_t run_resident(const DevState<T>& d, const Coef<T>& k, const RunSpec& r
     const double* u = r.u;
     T* states = static_cast<T*>(r.states);
     int samples = r.samples, substeps = r.substeps, cur = r.cur, renorm = r.renorm;
-    void* args[] = {&dd, &kk, &u, &states, &samples, &substeps, &cur, &renorm, &rpb, &wld};
-    const void* fn = r.xyz ? reinterpret_cast<const void*>(&k_resident<T, true>)
-                           : reinterpret_cast<const void*>(&k_resident<T, false>);
-    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kBlock), args, (unsigned)lds, r.stream);
+    // a trace armed for fewer workgroups than this launch has is not written
+    unsigned long long* trace = r.trace && r.trace_groups >= grid ? r.trace : nullptr;
+    int trace_stages = trace ? r.trace_stages : 0;
+    void* args[] = {&dd, &kk, &u, &states, &samples, &substeps, &cur, &renorm, &rpb, &wld, &trace, &trace_stages};
+    const void* fn = resident_kernel(sizeof(T), r.xyz, block);
+    e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, (unsigned)lds, r.stream);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }

@@ -54,3 +54,37 @@ def random_case(n, n_in=1, seed=0, samples=10, spread=0.05):
     m0 = v / np.linalg.norm(v, axis=1, keepdims=True)
     u = rng.uniform(-1, 1, (samples, n_in))
     return w, w_in, m0, u
+
+
+def _one_stream_adjoint(args):
+    """Worker: the oracle's adjoint of one input stream (BLAS on one thread)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import adjoint
+    w, w_in, m0, u, prm, g_rec, g_fin, dot = args
+    with threadpool_limits(limits=1):
+        r = adjoint.run_adjoint(w, w_in, m0, u, prm, g_rec, g_fin, dot=dot)
+    return {k: r[k] for k in ("W", "w_in", "m0", "a_cp", "a_in", "h_s", "h_appl")}
+
+
+def oracle_streams_adjoint(w, w_in, m0s, u, prm, g_rec, g_fin, dot="blas", workers=1):
+    """The oracle's adjoint run once per stream: dL/dW, dL/dw_in and the
+    scalars of the shared reservoir sum over the streams (in stream order).
+    workers > 1 runs the streams in that many spawned CPU processes (they
+    never touch the GPU)."""
+    S = m0s.shape[0]
+    jobs = [(w, w_in, m0s[s], u[:, s], prm, g_rec[:, s], None if g_fin is None else g_fin[s], dot)
+            for s in range(S)]
+    if workers > 1:
+        import multiprocessing
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=min(workers, S),
+                                 mp_context=multiprocessing.get_context("spawn")) as ex:
+            parts = list(ex.map(_one_stream_adjoint, jobs))
+    else:
+        parts = [_one_stream_adjoint(j) for j in jobs]
+    tot = {}
+    for r in parts:
+        for k in ("W", "w_in", "a_cp", "a_in", "h_s", "h_appl"):
+            tot[k] = tot.get(k, 0.0) + r[k]
+    tot["m0"] = np.stack([r["m0"] for r in parts])
+    return tot

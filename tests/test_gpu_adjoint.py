@@ -20,7 +20,7 @@ import sys
 import numpy as np
 import pytest
 
-from common import lib_params, oracle_params, random_case
+from common import lib_params, oracle_params, oracle_streams_adjoint, random_case
 from oracle import adjoint, readout, sto
 
 pytestmark = pytest.mark.gpu
@@ -47,10 +47,11 @@ def rel_err(got, ref):
 
 
 def compare(got, ref, tol, label):
+    """Each array against its largest entry, each scalar gradient against
+    its own magnitude."""
     errs = {k: rel_err(got[k], ref[k]) for k in ("W", "w_in", "m0")}
-    scal = np.array([got[k] for k in SCALARS])
-    scal_ref = np.array([ref[k] for k in SCALARS])
-    errs["scalars"] = rel_err(scal, scal_ref)
+    for k in SCALARS:
+        errs[k] = abs(float(got[k]) - float(ref[k])) / max(abs(float(ref[k])), 1e-300)
     say(label, {k: f"{v:.2e}" for k, v in errs.items()})
     for k, v in errs.items():
         assert v <= tol, (label, k, v)
@@ -285,21 +286,6 @@ def test_autograd_end_to_end(stx):
 # ---------------------------------------------------------------------------
 # S input streams sharing W (the batched FP32 adjoint)
 # ---------------------------------------------------------------------------
-def oracle_streams_adjoint(w, w_in, m0s, u, prm, g_rec, g_fin, dot="blas"):
-    """The oracle's adjoint run once per stream: dL/dW, dL/dw_in and the
-    scalars of the shared reservoir sum over the streams."""
-    tot = {}
-    m0 = []
-    for s in range(m0s.shape[0]):
-        r = adjoint.run_adjoint(w, w_in, m0s[s], u[:, s], prm, g_rec[:, s],
-                                None if g_fin is None else g_fin[s], dot=dot)
-        m0.append(r["m0"])
-        for k in ("W", "w_in") + SCALARS:
-            tot[k] = tot.get(k, 0.0) + (np.asarray(r[k]) if k in ("W", "w_in") else r[k])
-    tot["m0"] = np.stack(m0)
-    return tot
-
-
 def unit_states(rng, streams, n, spread=0.3):
     v = rng.standard_normal((streams, n, 3)) * spread
     v[..., 2] += 1.0
@@ -324,6 +310,11 @@ def test_adjoint_streams_matches_oracle(stx, coupling, seg, renorm):
     ref = oracle_streams_adjoint(w, w_in, np.float32(m0s).astype(np.float64), u, prm, g_rec, g_fin)
     with stx.Reservoir(w, w_in, m0s, lib_params(prm, "f32"), streams=S) as r:
         got = r.adjoint(m0s, u, g_rec, g_fin, checkpoint_every=seg)
+        # segments of whole samples run on the persistent kernels
+        kern = r.adjoint_kernels
+        whole = seg == 0 or seg % sub == 0
+        assert kern == ({"forward": "persistent", "reverse": "persistent"} if whole
+                        else {"forward": "stage", "reverse": "stage"}), kern
     compare(got, ref, F32_TOL, f"streams {coupling}")
 
 
@@ -359,6 +350,7 @@ def test_adjoint_streams_reverse_kernels_agree(stx, coupling, n, S, seg, renorm,
         with stx.Reservoir(w, w_in, m0s, lib_params(prm, "f32"), streams=S) as r:
             assert r.path == "multi"
             got[key] = r.adjoint(m0s, u, g_rec, g_fin, checkpoint_every=seg)
+            assert r.adjoint_kernels["reverse"] == ("persistent" if rev == "1" else "stage"), key
         compare(got[key], ref, F32_TOL, f"streams {key} {coupling}")
     compare(got["auto"], got["stage"], F32_TOL, "persistent vs per-stage reverse")
     compare(got["two"], got["stage"], F32_TOL, "two row tiles vs per-stage reverse")
@@ -387,6 +379,8 @@ def test_adjoint_streams_several_inputs(stx, n_in, coupling, monkeypatch):
         with stx.Reservoir(w, w_in, m0s, lib_params(prm, "f32"), streams=S) as r:
             assert r.path == "multi"
             got[rev] = r.adjoint(m0s, u, g_rec, g_fin, checkpoint_every=sub)
+            persistent = rev == "1" and n_in <= 4
+            assert r.adjoint_kernels["reverse"] == ("persistent" if persistent else "stage"), (rev, n_in)
         compare(got[rev], ref, F32_TOL, f"streams n_in={n_in} reverse={rev}")
     compare(got["1"], got["0"], F32_TOL, "persistent vs per-stage reverse")
 
@@ -408,10 +402,12 @@ def test_adjoint_streams64_xyz_oracle_and_central_fd(stx):
     w, w_in = (np.float32(x).astype(np.float64) for x in (a["W"], a["w_in"]))
     m0_ref = np.float32(m0s).astype(np.float64)
     say("adjoint streams64 xyz")
-    ref = oracle_streams_adjoint(w, w_in, m0_ref, a["u"], prm, g_rec, None)
+    ref = oracle_streams_adjoint(w, w_in, m0_ref, a["u"], prm, g_rec, None, workers=16)
     with stx.Reservoir(w, w_in, m0s, lib_params(prm, "f32"), streams=S) as r:
         assert r.path == "multi"
-        got = r.adjoint(m0s, a["u"], g_rec, checkpoint_every=2)
+        # a segment of the whole sample: the persistent forward and reverse
+        got = r.adjoint(m0s, a["u"], g_rec, checkpoint_every=5)
+        assert r.adjoint_kernels == {"forward": "persistent", "reverse": "persistent"}, r.adjoint_kernels
     compare(got, ref, F32_TOL, "streams64 xyz")
 
     def loss(p, ww):
@@ -433,6 +429,52 @@ def test_adjoint_streams64_xyz_oracle_and_central_fd(stx):
     errs["W"] = abs(fd - mine) / abs(mine)
     say("  oracle adjoint vs central differences", {k: f"{v:.1e}" for k, v in errs.items()})
     assert max(errs.values()) <= 1e-6
+
+
+@pytest.mark.parametrize("coupling", ["xyz", "x"])
+def test_adjoint_streams64_paper_amplitudes_records(stx, coupling, monkeypatch):
+    """The differentiation workload in the configuration the benchmark times:
+    N = 512, 64 streams, the paper's amplitudes (A_cp = A_in = 1 Oe), 10
+    input samples of 20 RK4 steps, a checkpoint every 100 steps taken from
+    the run's records (reservoir_adjoint_records_device), the library's
+    choice of row tiles and stream groups (13 groups with a ragged last one
+    for isotropic coupling).  The persistent reverse and the per-stage
+    reverse against the oracle's adjoint (FP64, every stream)."""
+    import torch
+    from workloads import STREAMS, WORKLOADS, make_stream_arrays
+    wl = WORKLOADS["streams64"]
+    S = STREAMS["streams64"]
+    samples = 10
+    a = make_stream_arrays(wl, S, samples=samples)
+    amp = 1.764e7 * 1e-9                      # 1 Oe in the dimensionless field unit
+    prm = oracle_params(a_cp=amp, a_in=amp, coupling=coupling, substeps=wl.substeps)
+    rng = np.random.default_rng(65)
+    m0s = np.ascontiguousarray(np.broadcast_to(a["m0"], (S, wl.n, 3)))
+    g_rec = np.float32(rng.standard_normal((samples, S, wl.n, 3))).astype(np.float64)
+    w, w_in = (np.float32(x).astype(np.float64) for x in (a["W"], a["w_in"]))
+    say(f"adjoint streams64 paper amplitudes {coupling}: oracle over {S} streams")
+    ref = oracle_streams_adjoint(w, w_in, np.float32(m0s).astype(np.float64), a["u"], prm, g_rec, None,
+                                 workers=16)
+    dev = torch.device("cuda")
+    got = {}
+    for rev in ("1", "0"):
+        monkeypatch.setenv("STO_MULTI_REVERSE", rev)
+        say(f"  reverse={rev}")
+        with stx.Reservoir(w, w_in, m0s, lib_params(prm, "f32"), streams=S) as r:
+            assert r.path == "multi"
+            u_d = torch.from_numpy(a["u"]).to(dev)
+            records = torch.empty((samples, S, wl.n, 3), dtype=torch.float32, device=dev)
+            r.run_device(u_d, records)
+            out = r.adjoint_device(torch.from_numpy(m0s).to(dev, torch.float32), u_d,
+                                   grad_states_dev=torch.from_numpy(g_rec).to(dev, torch.float32),
+                                   checkpoint_every=100, records_dev=records)
+            torch.cuda.synchronize()
+            assert r.adjoint_kernels == {"forward": "persistent",
+                                         "reverse": "persistent" if rev == "1" else "stage"}, r.adjoint_kernels
+        got[rev] = {**{k: out[k].double().cpu().numpy() for k in ("W", "w_in", "m0")},
+                    **{k: float(v) for k, v in zip(SCALARS, out["scalars"].cpu().numpy())}}
+        compare(got[rev], ref, F32_TOL, f"streams64 paper amplitudes {coupling} reverse={rev}")
+    compare(got["1"], got["0"], F32_TOL, "persistent vs per-stage reverse")
 
 
 def test_adjoint_matches_central_fd_f64(stx):
