@@ -372,6 +372,26 @@ sto_status readout_fit_device(const void *states_dev, int32_t dtype, int64_t T, 
                               void *w_out_dev, double *nmse_out, void *hip_stream);
 
 /*
+ * readout_fit_device_noalloc -- readout_fit_device for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same kernels and results,
+ * with the fit's whole workspace (design matrix, Gram matrix, tile lists,
+ * residuals, flags) in the library's static device array of 96 MiB, of
+ * which each GPU the library runs on holds one copy until the process
+ * ends.  The call makes no hipMalloc or hipFree.  Arguments, results and
+ * errors as readout_fit_device, plus STO_E_UNSUPPORTED when the workspace,
+ * about 8 ((T - washout) (F + 1) + m^2) bytes with m = min(T - washout,
+ * F + 1), would exceed the array (the message states both sizes; N = 1,000
+ * over 9,000 fitted rows and N = 10,000 over 900 fit).  Every call on one
+ * GPU shares that GPU's array and overwrites it: calls that overlap on one
+ * GPU (several host threads or streams) race and must be serialised by the
+ * caller.
+ */
+sto_status readout_fit_device_noalloc(const void *states_dev, int32_t dtype, int64_t T, int64_t n,
+                                      const void *y_dev, int64_t washout, double lambda, int32_t features,
+                                      void *w_out_dev, double *nmse_out, void *hip_stream);
+
+/*
  * readout_fit_batch_device -- readout_fit_device for `count` record sets,
  * each with its own target series (which may be one shared buffer), fitted
  * together: the readouts of a sweep's reservoirs, or of the S streams of a

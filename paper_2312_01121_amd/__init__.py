@@ -97,6 +97,8 @@ def _load():
     lib.readout_fit_device.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, vp, ctypes.c_int64,
                                        ctypes.c_double, ctypes.c_int32, vp, dp, vp]
     lib.readout_fit_device.restype = ctypes.c_int
+    lib.readout_fit_device_noalloc.argtypes = lib.readout_fit_device.argtypes
+    lib.readout_fit_device_noalloc.restype = ctypes.c_int
     lib.readout_fit_batch_device.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64),
                                              ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
                                              ctypes.POINTER(vp), ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
@@ -148,6 +150,7 @@ _lib = _load()
 
 EXPORTED = ("reservoir_create", "reservoir_create_streams", "reservoir_streams", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
             "reservoir_set_state", "reservoir_path", "reservoir_destroy", "readout_fit", "readout_fit_device",
+            "readout_fit_device_noalloc",
             "readout_fit_batch_device", "sweep_create", "sweep_nodes", "sweep_run", "sweep_run_device", "sweep_get_state", "sweep_destroy",
             "reservoir_adjoint", "reservoir_adjoint_device", "reservoir_adjoint_records_device", "readout_grad_device",
             "reservoir_trace_phases", "reservoir_phase_times", "reservoir_adjoint_kernels",
@@ -291,6 +294,25 @@ def readout_fit_device(states_dev, y_dev, washout: int, lam: float, features: in
                                    ctypes.c_void_p(y_dev.data_ptr()), washout, lam, features,
                                    ctypes.c_void_p(w_out_dev.data_ptr()), _dptr(nmse), ctypes.c_void_p(s)))
     return w_out_dev, float(nmse[0])
+
+
+def readout_fit_device_noalloc(states_dev, y_dev, washout: int, lam: float, w_out_dev, features: int = 0,
+                               stream=None) -> float:
+    """readout_fit_device with its workspace in the library's static device
+    array (no device allocation; w_out_dev must be given).  Returns nmse."""
+    import torch
+    assert states_dev.is_cuda and states_dev.is_contiguous() and states_dev.dim() == 3
+    assert y_dev.is_cuda and y_dev.dtype == torch.float64 and y_dev.is_contiguous()
+    T, n, _ = states_dev.shape
+    cols = (3 * n if features else n) + 1
+    assert w_out_dev.is_cuda and w_out_dev.dtype == torch.float64 and w_out_dev.numel() == cols
+    dtype = {torch.float64: STO_F64, torch.float32: STO_F32}[states_dev.dtype]
+    nmse = np.empty(1)
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    _check(_lib.readout_fit_device_noalloc(ctypes.c_void_p(states_dev.data_ptr()), dtype, T, n,
+                                           ctypes.c_void_p(y_dev.data_ptr()), washout, lam, features,
+                                           ctypes.c_void_p(w_out_dev.data_ptr()), _dptr(nmse), ctypes.c_void_p(s)))
+    return float(nmse[0])
 
 
 def readout_fit_batch_device(states_list, y_dev, washout: int, lam: float, features: int = 0, w_list=None,

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "readout_batch.hpp"
@@ -480,6 +481,18 @@ int solve_in(const Plan& pl, void* ws, int count, int rec_f32, int rows, int fea
     return rc;
 }
 
+// Workspace of the allocation-free readout: one array per device, resolved
+// to a device address once per device (the name itself is a host-side
+// stand-in and is never passed to a kernel).
+__device__ __align__(256) unsigned char scratch[kReadoutScratchBytes];
+
+struct ScratchAddr {
+    void* ptr = nullptr;
+    bool resolved = false;
+};
+std::mutex g_scratch_mu;
+ScratchAddr g_scratch[64];
+
 }  // namespace
 
 int readout_solve_batch(int count, const void* const* rec, const int64_t* stride, int rec_f32, int rows,
@@ -496,6 +509,49 @@ int readout_solve_batch(int count, const void* const* rec, const int64_t* stride
     const int rc = solve_in(pl, ws, count, rec_f32, rows, features, lam, nmse_host, stream, err, bad_item);
     (void)hipFree(ws);
     return rc;
+}
+
+size_t readout_workspace_bytes(int count, const int64_t* n, int rows, int features) {
+    std::vector<const void*> rec(count, nullptr);
+    std::vector<int64_t> stride(count, 0);
+    std::vector<const double*> y(count, nullptr);
+    std::vector<double*> w(count, nullptr);
+    return make_plan(count, rec.data(), stride.data(), rows, n, features, y.data(), w.data()).bytes;
+}
+
+hipError_t readout_scratch_address(void** ptr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev].resolved) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch[dev].ptr = p;
+        g_scratch[dev].resolved = true;
+    }
+    *ptr = g_scratch[dev].ptr;
+    return hipSuccess;
+}
+
+int readout_solve_scratch(const void* rec, int rec_f32, int rows, int64_t n, int features, const double* y,
+                          double lam, double* w_dev, double* nmse_host, hipStream_t stream, const char** err) {
+    const int64_t stride = 3 * n;
+    int bad_item = -1;
+    const Plan pl = make_plan(1, &rec, &stride, rows, &n, features, &y, &w_dev);
+    if (pl.bytes > kReadoutScratchBytes) {
+        if (err) *err = "workspace exceeds the static scratch";
+        return 4;
+    }
+    void* ws = nullptr;
+    hipError_t e = readout_scratch_address(&ws);
+    if (e != hipSuccess) {
+        if (err) *err = hipGetErrorString(e);
+        return 2;
+    }
+    return solve_in(pl, ws, 1, rec_f32, rows, features, lam, nmse_host, stream, err, &bad_item);
 }
 
 }  // namespace sto

@@ -996,6 +996,31 @@ sto_status readout_fit_device(const void* states_dev, int32_t dtype, int64_t T, 
 }
 
 
+sto_status readout_fit_device_noalloc(const void* states_dev, int32_t dtype, int64_t T, int64_t n, const void* y_dev,
+                                      int64_t washout, double lambda, int32_t features, void* w_out_dev,
+                                      double* nmse_out, void* hip_stream) {
+    if (!states_dev || !y_dev || !w_out_dev || !nmse_out) return fail(STO_E_INVALID, "NULL argument");
+    if (dtype != STO_F64 && dtype != STO_F32) return fail(STO_E_INVALID, "unknown dtype %d", dtype);
+    sto_status st = readout_check(T, n, washout, lambda, features);
+    if (st != STO_OK) return st;
+    const int64_t rows = T - washout;
+    const size_t need = sto::readout_workspace_bytes(1, &n, (int)rows, features);
+    if (need > sto::kReadoutScratchBytes)
+        return fail(STO_E_UNSUPPORTED,
+                    "readout of %lld rows x %lld nodes needs %zu bytes of workspace; the allocation-free fit "
+                    "holds at most %zu (use readout_fit_device)",
+                    (long long)rows, (long long)n, need, sto::kReadoutScratchBytes);
+    const size_t elem = dtype == STO_F64 ? 8 : 4;
+    const void* rec = static_cast<const char*>(states_dev) + (size_t)washout * n * 3 * elem;
+    const double* y = static_cast<const double*>(y_dev) + washout;
+    const char* err = nullptr;
+    int rc = sto::readout_solve_scratch(rec, dtype == STO_F32, (int)rows, n, features, y, lambda,
+                                        static_cast<double*>(w_out_dev), nmse_out,
+                                        static_cast<hipStream_t>(hip_stream), &err);
+    if (rc == 4) return fail(STO_E_UNSUPPORTED, "readout: %s", err ? err : "workspace exceeds the scratch");
+    return rc == 0 ? STO_OK : readout_status(rc, err);
+}
+
 sto_status readout_fit_batch_device(int32_t count, const void* const* states_dev, const int64_t* row_stride,
                                     int32_t dtype, int64_t T, const int64_t* n, const void* const* y_dev, int64_t washout,
                                     double lambda, int32_t features, double* const* w_out_dev, double* nmse_out,
