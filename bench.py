@@ -52,12 +52,27 @@ KERNEL_SOURCES = {
 }
 
 
+# Of the shared internal header only the structures the kernels take as
+# arguments enter the hash: the rest of it is host-side.
+KERNEL_STRUCTS = ("DevState", "SweepRes", "SweepTask", "SweepDev")
+
+
+def _kernel_structs(text: str) -> bytes:
+    import re
+    parts = []
+    for name in KERNEL_STRUCTS:
+        m = re.search(r"struct " + name + r" \{.*?\n\};", text, flags=re.S)
+        parts.append(m.group(0) if m else "")
+    return "\n".join(parts).encode()
+
+
 def kernel_source_hash(kernel: str) -> str:
     """Hash of the sources a kernel is compiled from (stale counters are dropped)."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2312_01121_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+            data = fh.read()
+        h.update(_kernel_structs(data.decode()) if f == "sto_internal.hpp" else data)
     return h.hexdigest()[:16]
 
 

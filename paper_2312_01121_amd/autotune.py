@@ -1,12 +1,21 @@
-"""Autotuner for the streaming kernels (STO_PATH_STREAM).
+"""Autotuners of the single-stream paths.
 
-Times every compiled launch shape (rows of W per wave x unroll of the column
-loop) of the stage kernel on this GPU, for each element type and a ladder of
-sizes, and writes the fastest shape per size bucket into
-``csrc/stream_tune.hpp`` (the table the library consults).  Rebuild the
-library afterwards (``python paper_2312_01121_amd/_build.py``).
+Default mode (the streaming kernels, STO_PATH_STREAM): times every compiled
+launch shape (rows of W per wave x unroll of the column loop) of the stage
+kernel on this GPU, for each element type and a ladder of sizes, and writes
+the fastest shape per size bucket into ``csrc/stream_tune.hpp``.
 
-Usage (on the GPU): python -m paper_2312_01121_amd.autotune [--write [PATH]] [--samples S]
+``--paths``: times the three single-stream paths at a ladder of sizes for
+each element type and coupling -- the one-workgroup kernel (small), the
+cooperative kernel with W in the LDS of many workgroups (resident) in every
+candidate launch shape (waves and rows per workgroup) that fits, and the
+per-stage streaming kernel -- and writes the fastest path and shape per size
+bucket into ``csrc/path_tune.hpp``, which sets the automatic path choice and
+the resident launch shape.
+
+Rebuild the library afterwards (``python paper_2312_01121_amd/_build.py``).
+
+Usage (on the GPU): python -m paper_2312_01121_amd.autotune [--paths] [--write [PATH]] [--samples S]
 """
 
 from __future__ import annotations
@@ -21,6 +30,13 @@ import numpy as np
 VARIANTS = [(1, 4), (2, 2), (2, 4), (4, 1), (4, 2), (4, 4), (8, 1), (8, 2)]
 SIZES = {"f32": [3200, 4096, 6144, 8192, 10000, 14000], "f64": [2200, 3072, 4096, 6144, 8192, 10000]}
 HEADER = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "stream_tune.hpp")
+PATH_HEADER = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "path_tune.hpp")
+# sizes of the path ladder and the resident launch shapes tried (waves, rows
+# per workgroup; 0 rows: ceil(n / CUs))
+PATH_SIZES = {"f64": [16, 32, 48, 64, 80, 96, 128, 140, 192, 256, 384, 512, 768, 1000, 1280, 1536, 2048],
+              "f32": [16, 32, 64, 96, 128, 160, 199, 256, 384, 512, 768, 1000, 1280, 1536, 2048, 2560, 3072]}
+RESIDENT_SHAPES = [(4, 0), (8, 0), (16, 0), (4, 4), (8, 8), (16, 16), (8, 16)]
+PATH_CODE = {"small": 1, "resident": 2, "stream": 3}
 
 
 def measure(stx, torch, n: int, dtype: str, variants, samples: int):
@@ -94,15 +110,141 @@ constexpr StreamTuneEntry kStreamTune[] = {{
         fh.write(text)
 
 
+def time_path(stx, torch, n, dtype, coupling, path, shape, samples, reps=3):
+    """Best of ``reps`` runs, microseconds per RK4 step; None if the path or
+    shape cannot hold n."""
+    for k in ("STO_RESIDENT_WAVES", "STO_RESIDENT_RPB"):
+        os.environ.pop(k, None)
+    if shape is not None:
+        os.environ["STO_RESIDENT_WAVES"] = str(shape[0])
+        if shape[1]:
+            os.environ["STO_RESIDENT_RPB"] = str(shape[1])
+    rng = np.random.default_rng(n)
+    w = rng.standard_normal((n, n)) / np.sqrt(n)
+    np.fill_diagonal(w, 0.0)
+    w_in = rng.uniform(-1, 1, (n, 1))
+    v = rng.standard_normal((n, 3)) * 0.05
+    v[:, 2] += 1.0
+    m0 = v / np.linalg.norm(v, axis=1, keepdims=True)
+    prm = stx.make_params(**stx.params.table1(), dtype=dtype, coupling=coupling, path=path)
+    try:
+        r = stx.Reservoir(w, w_in, m0, prm)
+    except stx.StoError:
+        return None
+    try:
+        u = torch.from_numpy(rng.uniform(-1, 1, (samples, 1))).cuda()
+        r.run_device(u[:2].contiguous())
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            r.run_device(u)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) * 1e3 / (samples * prm.substeps))
+        return best
+    except stx.StoError:
+        return None
+    finally:
+        r.close()
+        for k in ("STO_RESIDENT_WAVES", "STO_RESIDENT_RPB"):
+            os.environ.pop(k, None)
+
+
+def path_table(best):
+    lines = []
+    for (dtype, coupling), per in sorted(best.items()):
+        elem = 4 if dtype == "f32" else 8
+        xyz = 1 if coupling == "xyz" else 0
+        sizes = sorted(per)
+        for i, n in enumerate(sizes):
+            n_max = (n + sizes[i + 1]) // 2 if i + 1 < len(sizes) else (1 << 30)
+            path, waves, rpb = per[n]
+            lines.append(f"    {{{elem}, {xyz}, {n_max}, {PATH_CODE[path]}, {waves}, {rpb}}},   // {path}")
+    return "\n".join(lines)
+
+
+def write_path_header(best, measured, path=PATH_HEADER):
+    text = f"""// Path and launch shape of a single-stream reservoir by element type,
+// coupling and size, chosen by measurement.  Written by
+// paper_2312_01121_amd/autotune.py --paths; entries are scanned in order and
+// the first with matching element size and coupling and n <= n_max applies.
+// Each measured size covers n up to the midpoint to the next; above the last
+// one the entry's path holds while it can (the resident path falls back to
+// the stream path where W no longer fits the CUs' LDS).
+#pragma once
+
+namespace sto {{
+
+struct PathTuneEntry {{
+    int elem_bytes;
+    int xyz;        // 0: m^x coupling, 1: all three components
+    int n_max;
+    int path;       // 1 small, 2 resident, 3 stream (sto_path values)
+    int waves;      // resident: waves per workgroup (4, 8 or 16)
+    int rpb;        // resident: rows per workgroup (0: ceil(n / CUs))
+}};
+
+// Fastest path and shape per size bucket (microseconds per RK4 step measured
+// for every path and resident shape that holds the size; listed below).
+constexpr PathTuneEntry kPathTune[] = {{
+{path_table(best)}
+}};
+
+// Measured (dtype/coupling/n): {{path or resident_wavesxrows: us per RK4 step}}
+// {json.dumps(measured, sort_keys=True)}
+
+}}  // namespace sto
+"""
+    with open(path, "w") as fh:
+        fh.write(text)
+
+
+def tune_paths(stx, torch, samples, write):
+    best, measured = {}, {}
+    for dtype, sizes in PATH_SIZES.items():
+        for coupling in ("x", "xyz"):
+            best[(dtype, coupling)] = {}
+            for n in sizes:
+                s = samples if n <= 1000 else max(10, samples // 3)
+                times = {"small": time_path(stx, torch, n, dtype, coupling, "small", None, s),
+                         "stream": time_path(stx, torch, n, dtype, coupling, "stream", None, s)}
+                for shape in RESIDENT_SHAPES:
+                    times[f"resident_{shape[0]}x{shape[1]}"] = time_path(stx, torch, n, dtype, coupling,
+                                                                          "resident", shape, s)
+                ok = {k: v for k, v in times.items() if v is not None}
+                key = min(ok, key=ok.get)
+                if key.startswith("resident_"):
+                    waves, rpb = (int(x) for x in key[len("resident_"):].split("x"))
+                    best[(dtype, coupling)][n] = ("resident", waves, rpb)
+                else:
+                    best[(dtype, coupling)][n] = (key, 0, 0)
+                measured[f"{dtype}/{coupling}/{n}"] = {k: round(v, 2) for k, v in ok.items()}
+                print(json.dumps({"dtype": dtype, "coupling": coupling, "n": n, "best": key,
+                                  "us": round(ok[key], 2), "all": measured[f"{dtype}/{coupling}/{n}"]}), flush=True)
+    if write:
+        write_path_header(best, measured, write)
+        print(f"wrote {write}", file=sys.stderr)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--samples", type=int, default=3)
-    ap.add_argument("--write", nargs="?", const=HEADER, default=None, metavar="PATH",
-                    help="write the table header (default path: csrc/stream_tune.hpp)")
+    ap.add_argument("--paths", action="store_true", help="tune the path choice and resident shapes instead")
+    ap.add_argument("--write", nargs="?", const="default", default=None, metavar="PATH",
+                    help="write the table header (default: csrc/stream_tune.hpp, or csrc/path_tune.hpp)")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available(), "the autotuner runs on the GPU"
     import paper_2312_01121_amd as stx
+
+    if args.paths:
+        write = PATH_HEADER if args.write == "default" else args.write
+        tune_paths(stx, torch, max(args.samples, 60), write)
+        return
+    if args.write == "default":
+        args.write = HEADER
 
     best, measured = {}, {}
     for dtype, sizes in SIZES.items():

@@ -666,8 +666,15 @@ sto_status reservoir_create_streams(int64_t n, int64_t n_in, int64_t streams, co
         }
         if (path == STO_PATH_AUTO) path = multi_ok ? STO_PATH_MULTI : STO_PATH_BATCH;
     } else if (path == STO_PATH_AUTO) {
-        if (n <= small_n) path = STO_PATH_SMALL;
-        else if (sto::resident_fits((int)n, (int)r->elem, xyz, &grid)) path = STO_PATH_RESIDENT;
+        // the measured path table where it has an entry for n (each path
+        // only where it can hold n), else by capacity
+        const int tuned = sto::tuned_path((int)r->elem, xyz, (int)n, nullptr, nullptr);
+        const bool resident_ok = sto::resident_fits((int)n, (int)r->elem, xyz, &grid);
+        if (tuned == STO_PATH_SMALL && n <= small_n) path = STO_PATH_SMALL;
+        else if (tuned == STO_PATH_RESIDENT && resident_ok) path = STO_PATH_RESIDENT;
+        else if (tuned == STO_PATH_STREAM) path = STO_PATH_STREAM;
+        else if (n <= small_n) path = STO_PATH_SMALL;
+        else if (resident_ok) path = STO_PATH_RESIDENT;
         else path = STO_PATH_STREAM;
     } else if (path == STO_PATH_SMALL && n > small_n) {
         delete r;

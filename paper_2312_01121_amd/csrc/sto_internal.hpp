@@ -116,6 +116,11 @@ int sweep_rows_per_task(int elem_bytes);
 
 // Largest n the single-workgroup kernel holds (W in LDS).
 int small_max_n(int elem_bytes, int xyz);
+// Measured path for a single-stream reservoir of n nodes (sto_path value:
+// 1 small, 2 resident, 3 stream; 0 if no table entry) and, for the resident
+// path, its measured waves per workgroup and rows per workgroup (0: ceil(n /
+// CUs)).
+int tuned_path(int elem_bytes, int xyz, int n, int* waves, int* rpb);
 // Whether the resident kernel can hold n on this device (W split across
 // co-resident workgroups' LDS); fills the chosen grid size.
 bool resident_fits(int n, int elem_bytes, int xyz, int* grid_out);

@@ -44,6 +44,7 @@
 
 #include <climits>
 
+#include "path_tune.hpp"
 #include "sto_internal.hpp"
 
 namespace sto {
@@ -370,23 +371,10 @@ int env_int(const char* name) {
     return v && *v ? atoi(v) : 0;
 }
 
-}  // namespace
-
-// Launch shape of the resident kernel for n: rows per workgroup, threads per
-// workgroup and grid.  Default: 4 waves and ceil(n / CUs) rows, so that the
-// grid covers at most one workgroup per CU.  STO_RESIDENT_RPB (rows per
-// workgroup) and STO_RESIDENT_WAVES (4, 8 or 16) override it for
-// measurements.  False if the shape does not fit (LDS, rows per wave) or its
-// workgroups cannot all be co-resident.
-bool resident_shape(int n, int elem_bytes, int xyz, int* grid_out, int* rpb_out, int* block_out) {
-    const int cus = device_cus();
-    if (cus <= 0 || n < 2) return false;
-    int waves = env_int("STO_RESIDENT_WAVES");
-    if (waves != 4 && waves != 8 && waves != 16) waves = 4;
-    int rpb = env_int("STO_RESIDENT_RPB");
-    if (rpb <= 0) rpb = (n + cus - 1) / cus;
+// Whether (waves, rpb) runs n nodes: rows per wave, LDS, co-residency.
+bool shape_fits(int n, int elem_bytes, int xyz, int waves, int rpb, int cus, int* grid_out) {
     const int block = 64 * waves;
-    if (rpb > waves * max_rows_per_wave(block)) return false;
+    if (rpb < 1 || rpb > waves * max_rows_per_wave(block)) return false;
     const size_t lds = resident_lds(n, rpb, elem_bytes, xyz);
     if (lds + 64 > kLdsMax) return false;
     const int grid = (n + rpb - 1) / rpb;
@@ -396,10 +384,58 @@ bool resident_shape(int n, int elem_bytes, int xyz, int* grid_out, int* rpb_out,
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess) return false;
     if ((int64_t)per_cu * cus < grid) return false;
-    if (grid_out) *grid_out = grid;
-    if (rpb_out) *rpb_out = rpb;
-    if (block_out) *block_out = block;
+    *grid_out = grid;
     return true;
+}
+
+}  // namespace
+
+int tuned_path(int elem_bytes, int xyz, int n, int* waves, int* rpb) {
+    for (const PathTuneEntry& e : kPathTune)
+        if (e.elem_bytes == elem_bytes && e.xyz == (xyz ? 1 : 0) && n <= e.n_max) {
+            if (waves) *waves = e.waves;
+            if (rpb) *rpb = e.rpb;
+            return e.path;
+        }
+    return 0;
+}
+
+// Launch shape of the resident kernel for n: rows per workgroup, threads per
+// workgroup and grid.  The measured shape of the path table for n when it
+// fits, else 4 waves and ceil(n / CUs) rows (at most one workgroup per CU).
+// STO_RESIDENT_RPB (rows per workgroup) and STO_RESIDENT_WAVES (4, 8 or 16)
+// override both for measurements.  False if no shape fits (LDS, rows per
+// wave) or its workgroups cannot all be co-resident.
+bool resident_shape(int n, int elem_bytes, int xyz, int* grid_out, int* rpb_out, int* block_out) {
+    const int cus = device_cus();
+    if (cus <= 0 || n < 2) return false;
+    const int env_waves = env_int("STO_RESIDENT_WAVES"), env_rpb = env_int("STO_RESIDENT_RPB");
+    const int def_rpb = (n + cus - 1) / cus;
+    int cand[2][2];
+    int nc = 0;
+    if (env_waves > 0 || env_rpb > 0) {
+        const int w = (env_waves == 8 || env_waves == 16) ? env_waves : 4;
+        cand[nc][0] = w;
+        cand[nc++][1] = env_rpb > 0 ? env_rpb : def_rpb;
+    } else {
+        int tw = 0, tr = 0;
+        if (tuned_path(elem_bytes, xyz, n, &tw, &tr) == 2 && (tw == 4 || tw == 8 || tw == 16)) {
+            cand[nc][0] = tw;
+            cand[nc++][1] = tr > 0 ? tr : def_rpb;
+        }
+        cand[nc][0] = 4;
+        cand[nc++][1] = def_rpb;
+    }
+    for (int c = 0; c < nc; ++c) {
+        int grid = 0;
+        if (shape_fits(n, elem_bytes, xyz, cand[c][0], cand[c][1], cus, &grid)) {
+            if (grid_out) *grid_out = grid;
+            if (rpb_out) *rpb_out = cand[c][1];
+            if (block_out) *block_out = 64 * cand[c][0];
+            return true;
+        }
+    }
+    return false;
 }
 
 bool resident_fits(int n, int elem_bytes, int xyz, int* grid_out) {
