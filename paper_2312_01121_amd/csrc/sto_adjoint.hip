@@ -40,6 +40,7 @@
 #include "sto_adjoint.hpp"
 #include "sto_adjoint_dev.hpp"
 #include "sto_multi.hpp"
+#include "sto_resident.hpp"
 
 namespace sto {
 
@@ -617,6 +618,19 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
             ADJ_TRY(hipMemsetAsync(msync, 0, 512, st));
         }
     }
+    // One stream whose W fits the CUs' LDS, with segments of whole samples:
+    // the recompute and the reversed stages of every segment each run in one
+    // cooperative launch of the resident kernels (STO_RES_ADJOINT=0 keeps
+    // them on the per-stage kernels, for measurements).
+    bool use_res = false;
+    T* rxchg = nullptr;
+    if (NS == 1 && K % a.substeps == 0 && env_int("STO_RES_ADJOINT", 1) != 0 &&
+        resident_adjoint_fits(n, (int)sizeof(T), XYZ, a.n_in)) {
+        use_res = true;
+        ADJ_TRY(mem.get(&rxchg, (size_t)3 * C * ld * sizeof(T)));
+        ADJ_TRY(mem.get(&msync, 512));
+        ADJ_TRY(hipMemsetAsync(msync, 0, 512, st));
+    }
     auto keep_abort = [&]() -> hipError_t {
         hipLaunchKernelGGL(k_keep_abort, dim3(1), dim3(64), 0, st, msync + kSyncAbortWord, msync + 64);
         return hipGetLastError();
@@ -626,7 +640,38 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
     int used = 0;   // ADJ_* kernel families run
     auto forward = [&](int64_t j0, int64_t kn, int trace) -> hipError_t {
         d.j0 = j0;
-        used |= use_multi ? ADJ_FWD_PERSISTENT : ADJ_FWD_STAGE;
+        used |= (use_multi || use_res) ? ADJ_FWD_PERSISTENT : ADJ_FWD_STAGE;
+        if (use_res) {
+            DevState<T> ds{};
+            ds.W = a.W;
+            ds.w_in = a.w_in;
+            ds.m = d.m;
+            ds.ms[0] = d.ms[0];
+            ds.ms[1] = d.ms[1];
+            ds.acc = d.acc;
+            ds.xchg = rxchg;
+            ds.bad = a.bad;
+            ds.sync = msync;
+            ds.n = n;
+            ds.n_in = a.n_in;
+            ds.ld = ld;
+            RunSpec rs{};
+            rs.u = a.u + (j0 / a.substeps) * a.n_in;
+            rs.states = nullptr;
+            rs.samples = (int)(kn / a.substeps);
+            rs.substeps = a.substeps;
+            rs.cur = 0;
+            rs.renorm = a.renorm;
+            rs.xyz = XYZ;
+            rs.stream = st;
+            if (trace) {
+                const ResTrace<T> tr{d.xt, d.wx, d.pn};
+                ADJ_TRY(run_resident_traced<T>(ds, k, rs, tr, (int)(j0 / a.substeps)));
+            } else {
+                ADJ_TRY(run_resident<T>(ds, k, rs));
+            }
+            return keep_abort();
+        }
         if constexpr (sizeof(T) == 4) {
             if (use_multi) {
                 DevState<float> ds{};
@@ -689,6 +734,12 @@ hipError_t adjoint_impl(const AdjArgs<T>& a) {
         d.j0 = j0;
         hipLaunchKernelGGL((k_adj_prep<T, XYZ>), pgrid, pblock, 0, st, d, k, (int)(kn - 1));
         bool reversed = false;
+        if (use_res) {
+            ADJ_TRY(hipGetLastError());
+            ADJ_TRY(run_resident_reverse<T>(d, k, (int)kn, XYZ, rxchg, msync, st));
+            ADJ_TRY(keep_abort());
+            reversed = true;
+        }
         if constexpr (sizeof(T) == 4) {
             if (use_multi_rev) {
                 ADJ_TRY(hipGetLastError());

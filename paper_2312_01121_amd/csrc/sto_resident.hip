@@ -45,7 +45,9 @@
 #include <climits>
 
 #include "path_tune.hpp"
+#include "sto_adjoint_dev.hpp"
 #include "sto_internal.hpp"
+#include "sto_resident.hpp"
 
 namespace sto {
 
@@ -125,11 +127,16 @@ __device__ __forceinline__ void stamp(unsigned long long* trace, int trace_stage
         trace[((size_t)blockIdx.x * trace_stages + sigma) * 4 + point] = wall_clock64();
 }
 
-template <typename T, bool XYZ, int BLOCK>
+// TRACE: the adjoint's recompute of one segment; every stage also writes
+// its input (xt), its raw coupling sums before a_cp (wx) and, at the last
+// stage of a step, the norm before the projection (pn), in the layout of
+// the adjoint's workspace ([step][stage][component][ld]; pn [step][ld]).
+template <typename T, bool XYZ, int BLOCK, bool TRACE>
 __global__ void __launch_bounds__(BLOCK) k_resident(DevState<T> d, Coef<T> k, const double* __restrict__ u,
                                                     T* __restrict__ states, int samples, int substeps,
                                                     int cur, int renorm, int rows_per_block, int wld,
-                                                    unsigned long long* trace, int trace_stages) {
+                                                    unsigned long long* trace, int trace_stages,
+                                                    ResTrace<T> tr, int sample0) {
     constexpr int kBlock = BLOCK;
     constexpr int kWaves = BLOCK / 64;
     constexpr int kMaxRowsPerWave = max_rows_per_wave(BLOCK);
@@ -218,6 +225,13 @@ __global__ void __launch_bounds__(BLOCK) k_resident(DevState<T> d, Coef<T> k, co
                     const int r = wave + q * kWaves;
                     if (r >= nrows) break;   // wave-uniform
                     const T* wr = wsh + (int64_t)r * wld;
+                    const int64_t kk = (int64_t)s * substeps + sub;   // step of this launch
+                    if (TRACE && lane == 0) {
+                        T* x = tr.xt + (kk * 4 + stage) * 3 * ld;
+                        x[row_begin + r] = sx[q];
+                        x[ld + row_begin + r] = sy[q];
+                        x[2 * ld + row_begin + r] = sz[q];
+                    }
                     // two independent accumulation chains per lane (columns
                     // j and j + 64 of each 128), joined before the butterfly
                     // (measured: four chains are slower)
@@ -256,12 +270,24 @@ __global__ void __launch_bounds__(BLOCK) k_resident(DevState<T> d, Coef<T> k, co
                         cy = k.a_cp * A::round(vy);
                         cz = k.a_cp * A::round(vz);
                     }
+                    if (TRACE && lane == 0) {
+                        T* w = tr.wx + (kk * 4 + stage) * C * ld;
+                        w[row_begin + r] = A::round(vx);
+                        if (XYZ) {
+                            w[ld + row_begin + r] = A::round(vy);
+                            w[2 * ld + row_begin + r] = A::round(vz);
+                        }
+                    }
                     T fx, fy, fz;
                     llg_rhs<T, XYZ>(k, sx[q], sy[q], sz[q], cx, cy, cz, hin[q], fx, fy, fz);
                     T nx = rk4_update(k, stage, mx[q], ax[q], fx);
                     T ny = rk4_update(k, stage, my[q], ay[q], fy);
                     T nz = rk4_update(k, stage, mz[q], az[q], fz);
                     if (stage == 3) {
+                        if (TRACE && renorm && lane == 0) {
+                            const double ex = nx, ey = ny, ez = nz;
+                            tr.pn[kk * ld + row_begin + r] = (T)__builtin_sqrt((ex * ex + ey * ey) + ez * ez);
+                        }
                         if (renorm) renormalize(nx, ny, nz);
                         mx[q] = nx;
                         my[q] = ny;
@@ -304,7 +330,7 @@ __global__ void __launch_bounds__(BLOCK) k_resident(DevState<T> d, Coef<T> k, co
                     rec[1] = my[q];
                     rec[2] = mz[q];
                 }
-                if (!finite3(mx[q], my[q], mz[q])) atomicMin(d.bad, s);
+                if (!finite3(mx[q], my[q], mz[q])) atomicMin(d.bad, sample0 + s);
             }
         }
     }
@@ -320,6 +346,11 @@ __global__ void __launch_bounds__(BLOCK) k_resident(DevState<T> d, Coef<T> k, co
             d.m[2 * ld + row] = xc[2 * ld + row] = mz[q];
         }
     }
+}
+
+// Clears count words (a fill kernel rather than a memset node).
+__global__ void k_zero_words(int* p, int count) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0;
 }
 
 __global__ void k_resident_prologue(const void* ms_cur, void* xchg, int64_t elems_per_buffer, int elem,
@@ -338,6 +369,157 @@ __global__ void k_resident_prologue(const void* ms_cur, void* xchg, int64_t elem
     }
 }
 
+// Parameter partials of one node over a reversed segment, in registers
+// (FP64), added to the per-node sums once at the end; captures the next
+// stage's coupling adjoint for the exchange.
+constexpr int kRevIn = 4;   // input channels summed in registers
+
+template <typename T>
+struct ResSink {
+    double g[4] = {0.0, 0.0, 0.0, 0.0};
+    double w[kRevIn] = {0.0, 0.0, 0.0, 0.0};
+    T b[3] = {T(0), T(0), T(0)};
+    __device__ __forceinline__ void add(const AdjDev<T>& d, int64_t, double pcp, double pin, double phs, double pap,
+                                        double ab, const double* u_s, T bx, T by, T bz) {
+        g[0] += pcp;
+        g[1] += pin;
+        g[2] += phs;
+        g[3] += pap;
+#pragma unroll
+        for (int q = 0; q < kRevIn; ++q)
+            if (q < d.n_in) w[q] += ab * u_s[q];
+        b[0] = bx;
+        b[1] = by;
+        b[2] = bz;
+    }
+    __device__ __forceinline__ void flush(const AdjDev<T>& d, int64_t gi) {
+        const int64_t gs = d.ld;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) d.gacc[c * gs + gi] += g[c];
+#pragma unroll
+        for (int q = 0; q < kRevIn; ++q)
+            if (q < d.n_in) d.gwin[q * gs + gi] += w[q];
+    }
+};
+
+// The reversed stages of one adjoint segment of a single stream in one
+// cooperative launch.  Workgroup g keeps its rows of W^T in LDS; per stage
+// every workgroup gathers the stage's coupling adjoint bbar of all nodes
+// through the rotating sentinel buffers (the exchange of k_resident), each
+// wave forms t = W^T bbar for its rows (plain fma, two chains per lane, a
+// butterfly sum), and lane q of the wave runs the adjoint epilogue of its
+// row q (rev_load / rev_finish, as the per-stage kernel k_adj_stage runs
+// it).  The epilogue's inputs are loaded before the gather; its parameter
+// partials stay in registers until the end of the segment; the next stage's
+// bbar it computes is published.  Buffer 0 starts with the bbar of
+// (kn - 1, 3).
+template <typename T, bool XYZ, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_resident_rev(AdjDev<T> d, Coef<T> k, T* __restrict__ xbuf, int* sync,
+                                                        int kn, int rows_per_block, int wld) {
+    constexpr int kWaves = BLOCK / 64;
+    constexpr int kMaxRowsPerWave = max_rows_per_wave(BLOCK);
+    constexpr int C = XYZ ? 3 : 1;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int ok_lds;
+    const int n = d.n;
+    const int64_t ld = d.ld;
+    T* wsh = reinterpret_cast<T*>(smem_raw);                    // rows_per_block x wld: rows of W^T
+    T* xs = wsh + (int64_t)rows_per_block * wld;                // [C][n] coupling adjoint
+    const int row_begin = blockIdx.x * rows_per_block;
+    const int nrows = max(0, min(rows_per_block, n - row_begin));
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    int* abort_flag = sync + kSyncAbortWord;
+    if (threadIdx.x == 0) ok_lds = 1;
+    for (int i = threadIdx.x; i < nrows * n; i += BLOCK) {
+        const int r = i / n;
+        const int c = i - r * n;
+        wsh[(int64_t)r * wld + c] = d.Wt[(int64_t)(row_begin + r) * ld + c];
+    }
+    // lane q < kMaxRowsPerWave owns the epilogue of the wave's row q
+    const int myr = wave + lane * kWaves;
+    const bool mine = lane < kMaxRowsPerWave && myr < nrows;
+    const int node = row_begin + myr;
+    ResSink<T> sink;
+
+    int sigma = 0;
+    for (int kk = kn - 1; kk >= 0; --kk) {
+        for (int stage = 3; stage >= 0; --stage, ++sigma) {
+            const T* xin = xbuf + (int64_t)(sigma % 3) * C * ld;
+            T* xout = xbuf + (int64_t)((sigma + 1) % 3) * C * ld;
+            T* xold = xbuf + (int64_t)((sigma + 2) % 3) * C * ld;
+            RevIn<T> in{};
+            if (mine) in = rev_load<T, XYZ>(d, node, 0, kk, stage);
+            __syncthreads();
+            bool ok = true;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                ok = ok && gather_stage_input<T, BLOCK>(xin + c * ld, xs + c * n, n, abort_flag);
+            if (!ok) ok_lds = 0;
+            __syncthreads();
+            if (ok_lds == 0) return;
+            if (mine) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) rearm(xold + c * ld + node);
+            }
+            T t[3] = {T(0), T(0), T(0)};
+#pragma unroll
+            for (int q = 0; q < kMaxRowsPerWave; ++q) {
+                const int r = wave + q * kWaves;
+                if (r >= nrows) break;   // wave-uniform
+                const T* wr = wsh + (int64_t)r * wld;
+                T vx = T(0), vy = T(0), vz = T(0), ux = T(0), uy = T(0), uz = T(0);
+                int j = lane;
+                for (; j + 64 < n; j += 128) {
+                    const T w0 = wr[j], w1 = wr[j + 64];
+                    vx = __builtin_fma(w0, xs[j], vx);
+                    ux = __builtin_fma(w1, xs[j + 64], ux);
+                    if (XYZ) {
+                        vy = __builtin_fma(w0, xs[n + j], vy);
+                        uy = __builtin_fma(w1, xs[n + j + 64], uy);
+                        vz = __builtin_fma(w0, xs[2 * n + j], vz);
+                        uz = __builtin_fma(w1, xs[2 * n + j + 64], uz);
+                    }
+                }
+                if (j < n) {
+                    const T w0 = wr[j];
+                    vx = __builtin_fma(w0, xs[j], vx);
+                    if (XYZ) {
+                        vy = __builtin_fma(w0, xs[n + j], vy);
+                        vz = __builtin_fma(w0, xs[2 * n + j], vz);
+                    }
+                }
+                vx += ux;
+                for (int off = 32; off > 0; off >>= 1) vx += __shfl_xor(vx, off, 64);
+                if (XYZ) {
+                    vy += uy;
+                    vz += uz;
+                    for (int off = 32; off > 0; off >>= 1) {
+                        vy += __shfl_xor(vy, off, 64);
+                        vz += __shfl_xor(vz, off, 64);
+                    }
+                }
+                if (lane == q) {
+                    t[0] = vx;
+                    t[1] = vy;
+                    t[2] = vz;
+                }
+            }
+            // the re-arm stores must complete before the publish below; the
+            // epilogue's own stores need not
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            if (mine) {
+                rev_finish<T, XYZ>(d, k, node, 0, kk, stage, in, t[0], t[1], t[2], sink);
+                if (kk > 0 || stage > 0) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) publish(xout + c * ld + node, sink.b[c]);
+                }
+            }
+        }
+    }
+    if (mine) sink.flush(d, node);
+}
+
 int device_cus() {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -351,19 +533,37 @@ size_t resident_lds(int n, int rows_per_block, int elem, int xyz) {
     return ((size_t)rows_per_block * wld_of(n) + (xyz ? 3 : 1) * (size_t)n) * elem;
 }
 
+// variant 0: plain run; 1: the adjoint's traced recompute; 2: its reverse
+template <typename T, bool XYZ, int BLOCK>
+const void* resident_fn_v(int variant) {
+    if (variant == 1) return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, true>);
+    if (variant == 2) return reinterpret_cast<const void*>(&k_resident_rev<T, XYZ, BLOCK>);
+    return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, false>);
+}
+
 template <typename T, bool XYZ>
-const void* resident_fn(int block) {
+const void* resident_fn(int block, int variant) {
     switch (block) {
-        case 256: return reinterpret_cast<const void*>(&k_resident<T, XYZ, 256>);
-        case 512: return reinterpret_cast<const void*>(&k_resident<T, XYZ, 512>);
-        case 1024: return reinterpret_cast<const void*>(&k_resident<T, XYZ, 1024>);
+        case 256: return resident_fn_v<T, XYZ, 256>(variant);
+        case 512: return resident_fn_v<T, XYZ, 512>(variant);
+        case 1024: return resident_fn_v<T, XYZ, 1024>(variant);
         default: return nullptr;
     }
 }
 
-const void* resident_kernel(int elem, int xyz, int block) {
-    if (elem == 8) return xyz ? resident_fn<double, true>(block) : resident_fn<double, false>(block);
-    return xyz ? resident_fn<float, true>(block) : resident_fn<float, false>(block);
+const void* resident_kernel(int elem, int xyz, int block, int variant = 0) {
+    if (elem == 8) return xyz ? resident_fn<double, true>(block, variant) : resident_fn<double, false>(block, variant);
+    return xyz ? resident_fn<float, true>(block, variant) : resident_fn<float, false>(block, variant);
+}
+
+// Whether the kernel variant runs a grid of `grid` workgroups of `block`
+// threads with `lds` bytes co-resident on the CUs.
+bool co_resident(const void* fn, int block, size_t lds, int grid, int cus) {
+    if (!fn) return false;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return false;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess) return false;
+    return (int64_t)per_cu * cus >= grid;
 }
 
 int env_int(const char* name) {
@@ -378,12 +578,7 @@ bool shape_fits(int n, int elem_bytes, int xyz, int waves, int rpb, int cus, int
     const size_t lds = resident_lds(n, rpb, elem_bytes, xyz);
     if (lds + 64 > kLdsMax) return false;
     const int grid = (n + rpb - 1) / rpb;
-    const void* fn = resident_kernel(elem_bytes, xyz, block);
-    if (!fn) return false;
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return false;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess) return false;
-    if ((int64_t)per_cu * cus < grid) return false;
+    if (!co_resident(resident_kernel(elem_bytes, xyz, block), block, lds, grid, cus)) return false;
     *grid_out = grid;
     return true;
 }
@@ -466,7 +661,10 @@ hipError_t run_resident(const DevState<T>& d, const Coef<T>& k, const RunSpec& r
     // a trace armed for fewer workgroups than this launch has is not written
     unsigned long long* trace = r.trace && r.trace_groups >= grid ? r.trace : nullptr;
     int trace_stages = trace ? r.trace_stages : 0;
-    void* args[] = {&dd, &kk, &u, &states, &samples, &substeps, &cur, &renorm, &rpb, &wld, &trace, &trace_stages};
+    ResTrace<T> tr{nullptr, nullptr, nullptr};
+    int sample0 = 0;
+    void* args[] = {&dd, &kk, &u, &states, &samples, &substeps, &cur, &renorm, &rpb, &wld, &trace, &trace_stages,
+                    &tr, &sample0};
     const void* fn = resident_kernel(sizeof(T), r.xyz, block);
     e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, (unsigned)lds, r.stream);
     if (e != hipSuccess) return e;
@@ -475,5 +673,88 @@ hipError_t run_resident(const DevState<T>& d, const Coef<T>& k, const RunSpec& r
 
 template hipError_t run_resident<double>(const DevState<double>&, const Coef<double>&, const RunSpec&);
 template hipError_t run_resident<float>(const DevState<float>&, const Coef<float>&, const RunSpec&);
+
+// The reverse keeps each row's epilogue inputs in registers; with 16 waves
+// (128 registers per lane) they would spill, so it runs the same rows with
+// 8 waves (at most 2 rows per wave).
+int reverse_block(int block) { return block >= 1024 ? 512 : block; }
+
+bool resident_adjoint_fits(int n, int elem_bytes, int xyz, int n_in) {
+    int grid = 0, rpb = 0, block = 0;
+    if (n_in > kRevIn || !resident_shape(n, elem_bytes, xyz, &grid, &rpb, &block)) return false;
+    const size_t lds = resident_lds(n, rpb, elem_bytes, xyz);
+    const int cus = device_cus();
+    return co_resident(resident_kernel(elem_bytes, xyz, block, 1), block, lds, grid, cus) &&
+           co_resident(resident_kernel(elem_bytes, xyz, reverse_block(block), 2), reverse_block(block), lds, grid,
+                       cus);
+}
+
+template <typename T>
+hipError_t run_resident_traced(const DevState<T>& d, const Coef<T>& k, const RunSpec& r, const ResTrace<T>& tr,
+                               int sample0) {
+    int grid = 0, rpb = 0, block = 0;
+    if (!resident_shape(d.n, sizeof(T), r.xyz, &grid, &rpb, &block)) return hipErrorInvalidValue;
+    int wld = (int)wld_of(d.n);
+    const size_t lds = resident_lds(d.n, rpb, sizeof(T), r.xyz);
+    const int C = r.xyz ? 3 : 1;
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, r.stream, d.sync, 64);
+    hipLaunchKernelGGL(k_resident_prologue, dim3(64), dim3(256), 0, r.stream, (const void*)d.ms[r.cur],
+                       (void*)d.xchg, (int64_t)C * d.ld, (int)sizeof(T), (int64_t)C * d.ld);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    DevState<T> dd = d;
+    Coef<T> kk = k;
+    const double* u = r.u;
+    T* states = nullptr;
+    int samples = r.samples, substeps = r.substeps, cur = r.cur, renorm = r.renorm;
+    unsigned long long* trace = nullptr;
+    int trace_stages = 0;
+    ResTrace<T> t = tr;
+    int s0 = sample0;
+    void* args[] = {&dd, &kk, &u, &states, &samples, &substeps, &cur, &renorm, &rpb, &wld, &trace, &trace_stages,
+                    &t, &s0};
+    const void* fn = resident_kernel(sizeof(T), r.xyz, block, 1);
+    if (!co_resident(fn, block, lds, grid, device_cus())) return hipErrorInvalidValue;
+    e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, (unsigned)lds, r.stream);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t run_resident_reverse(const AdjDev<T>& d, const Coef<T>& k, int kn, int xyz, T* xbuf, int* sync,
+                                hipStream_t st) {
+    int grid = 0, rpb = 0, block = 0;
+    if (!resident_shape(d.n, sizeof(T), xyz, &grid, &rpb, &block)) return hipErrorInvalidValue;
+    int wld = (int)wld_of(d.n);
+    const size_t lds = resident_lds(d.n, rpb, sizeof(T), xyz);
+    const int C = xyz ? 3 : 1;
+    const T* first = d.st + (int64_t)(kn - 1) * 4 * C * d.ld + (int64_t)3 * C * d.ld;   // slot (kn - 1, 3)
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, sync, 64);
+    hipLaunchKernelGGL(k_resident_prologue, dim3(64), dim3(256), 0, st, (const void*)first, (void*)xbuf,
+                       (int64_t)C * d.ld, (int)sizeof(T), (int64_t)C * d.ld);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    AdjDev<T> dd = d;
+    Coef<T> kc = k;
+    T* xb = xbuf;
+    int* sy = sync;
+    int kn_ = kn;
+    void* args[] = {&dd, &kc, &xb, &sy, &kn_, &rpb, &wld};
+    const int rb = reverse_block(block);
+    const void* fn = resident_kernel(sizeof(T), xyz, rb, 2);
+    if (!co_resident(fn, rb, lds, grid, device_cus())) return hipErrorInvalidValue;
+    e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(rb), args, (unsigned)lds, st);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+template hipError_t run_resident_traced<double>(const DevState<double>&, const Coef<double>&, const RunSpec&,
+                                                const ResTrace<double>&, int);
+template hipError_t run_resident_traced<float>(const DevState<float>&, const Coef<float>&, const RunSpec&,
+                                               const ResTrace<float>&, int);
+template hipError_t run_resident_reverse<double>(const AdjDev<double>&, const Coef<double>&, int, int, double*, int*,
+                                                 hipStream_t);
+template hipError_t run_resident_reverse<float>(const AdjDev<float>&, const Coef<float>&, int, int, float*, int*,
+                                                hipStream_t);
 
 }  // namespace sto

@@ -122,18 +122,79 @@ def test_adjoint_large_n(stx, n, dtype):
 
 
 def test_adjoint_segments_agree(stx):
-    """Segment length only changes where the forward is recomputed: dL/dm0 and
-    the scalars are bitwise the same, dL/dW equal up to the product's order."""
+    """Segment length only changes where the forward is recomputed.  On the
+    per-stage kernels (segments that are not whole samples) dL/dm0, dL/dw_in
+    and the scalars are bitwise the same for every length, dL/dW equal up to
+    the product's order; segments of whole samples run on the persistent
+    resident kernels, whose sums take another order (1e-13)."""
     w, w_in, m0, u, prm, g_rec, g_fin = case(64, samples=3, substeps=5, seed=2)
     say("adjoint segments 64")
+    outs, kern = {}, {}
     with stx.Reservoir(w, w_in, m0, lib_params(prm, "f64")) as r:
-        outs = [r.adjoint(m0, u, g_rec, g_fin, checkpoint_every=s) for s in (0, 1, 4, 15)]
-    for o in outs[1:]:
-        assert np.array_equal(o["m0"], outs[0]["m0"])
-        assert np.array_equal(o["w_in"], outs[0]["w_in"])
-        for k in SCALARS:
-            assert o[k] == outs[0][k], k
-        assert rel_err(o["W"], outs[0]["W"]) <= 1e-13
+        for seg in (1, 4, 7, 0, 5, 15):
+            outs[seg] = r.adjoint(m0, u, g_rec, g_fin, checkpoint_every=seg)
+            kern[seg] = r.adjoint_kernels
+    for seg in (1, 4, 7):
+        assert kern[seg] == {"forward": "stage", "reverse": "stage"}, (seg, kern[seg])
+    for seg in (0, 5, 15):
+        assert kern[seg] == {"forward": "persistent", "reverse": "persistent"}, (seg, kern[seg])
+    for group in ((1, 4, 7), (0, 5, 15)):
+        ref = outs[group[0]]
+        for seg in group[1:]:
+            o = outs[seg]
+            assert np.array_equal(o["m0"], ref["m0"]), seg
+            if group[0] == 1:
+                assert np.array_equal(o["w_in"], ref["w_in"]), seg
+                for k in SCALARS:
+                    assert o[k] == ref[k], (seg, k)
+            assert rel_err(o["W"], ref["W"]) <= 1e-13
+    compare(outs[0], outs[1], 1e-13, "persistent vs per-stage")
+
+
+# The persistent single-stream adjoint (one cooperative launch for the
+# recompute and one for the reversed stages of every segment): both
+# precisions and couplings, renormalisation, 1 to 5 input channels (5 runs
+# on the per-stage kernels), several segments, the launch shapes of the
+# path table (4 waves, 8 waves x 8 rows; 16 waves x 16 rows in FP32, whose
+# reverse runs with 8 waves), against the oracle and against the per-stage
+# kernels (STO_RES_ADJOINT=0).
+RES_CASES = [
+    # dtype, n, n_in, coupling, renorm, samples, checkpoint samples
+    ("f64", 40, 1, "x", False, 4, 2),
+    ("f64", 300, 2, "xyz", True, 3, 0),
+    ("f64", 1000, 1, "x", False, 2, 1),
+    ("f64", 1500, 4, "x", True, 2, 0),
+    ("f64", 2048, 1, "x", False, 1, 0),
+    ("f64", 1000, 1, "xyz", False, 1, 0),
+    ("f32", 200, 3, "x", False, 4, 2),
+    ("f32", 700, 1, "xyz", True, 3, 1),
+    ("f32", 1000, 1, "x", False, 2, 0),
+    ("f32", 90, 5, "x", False, 3, 0),
+]
+
+
+@pytest.mark.parametrize("dtype,n,n_in,coupling,renorm,samples,cps", RES_CASES,
+                         ids=[f"{c[0]}-n{c[1]}-in{c[2]}-{c[3]}" + ("-renorm" if c[4] else "") for c in RES_CASES])
+def test_adjoint_resident_reverse(stx, dtype, n, n_in, coupling, renorm, samples, cps, monkeypatch):
+    sub = 5
+    w, w_in, m0, u, prm, g_rec, g_fin = case(n, n_in=n_in, samples=samples, substeps=sub, seed=n + n_in,
+                                             coupling=coupling, renormalize=renorm)
+    m0_ref = m0
+    if dtype == "f32":
+        w, w_in, g_rec, g_fin = (np.float32(a).astype(np.float64) for a in (w, w_in, g_rec, g_fin))
+        m0_ref = np.float32(m0).astype(np.float64)
+    say(f"adjoint resident reverse {dtype} n={n} n_in={n_in} {coupling} renorm={renorm}")
+    ref = adjoint.run_adjoint(w, w_in, m0_ref, u, prm, g_rec, g_fin, dot="blas")
+    got = {}
+    for res in ("1", "0"):
+        monkeypatch.setenv("STO_RES_ADJOINT", res)
+        with stx.Reservoir(w, w_in, m0, lib_params(prm, dtype)) as r:
+            got[res] = r.adjoint(m0, u, g_rec, g_fin, checkpoint_every=cps * sub)
+            persistent = res == "1" and n_in <= 4
+            assert r.adjoint_kernels == ({"forward": "persistent", "reverse": "persistent"} if persistent
+                                         else {"forward": "stage", "reverse": "stage"}), (res, r.adjoint_kernels)
+        compare(got[res], ref, F64_TOL if dtype == "f64" else F32_TOL, f"resident={res}")
+    compare(got["1"], got["0"], F64_TOL if dtype == "f64" else F32_TOL, "persistent vs per-stage")
 
 
 def test_adjoint_device_api(stx):
