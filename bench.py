@@ -619,6 +619,61 @@ def cpu_baseline(name: str, arrays, budget_s: float = 12.0):
     }
 
 
+def phase_breakdown(stx, torch, name: str, dtype: str, stages: int = 400, samples: int = 20, coupling: str = "x"):
+    """Exchange phases of the persistent kernel a workload runs on
+    (reservoir_trace_phases): wave 0 of every workgroup stamps the device's
+    constant-rate clock at stage start, stage input gathered, own rows
+    computed and own rows published, for the first `stages` RK4 stages of a
+    run of `samples` samples.  Medians over workgroups and stages, in
+    microseconds; `after_last_publish` is the time from the last workgroup's
+    publish of a stage to a workgroup's completed gather of the next."""
+    import numpy as np
+    from workloads import STREAMS, WORKLOADS, make_stream_arrays, make_workload_arrays
+    from paper_2312_01121_amd import params
+
+    wl = WORKLOADS[name]
+    S = STREAMS.get(name, 1)
+    if S > 1:
+        dtype = "f32"
+        a = make_stream_arrays(wl, S, samples=samples)
+        m0 = np.ascontiguousarray(np.broadcast_to(a["m0"], (S, wl.n, 3)))
+    else:
+        a = make_workload_arrays(wl, samples=samples)
+        m0 = a["m0"]
+    prm = stx.make_params(**params.table1(a_cp=wl.a_cp, a_in=wl.a_in, dt=wl.dt, substeps=wl.substeps),
+                          dtype=dtype, coupling=coupling)
+    r = stx.Reservoir(a["W"], a["w_in"], m0, prm, streams=S)
+    u = torch.from_numpy(a["u"]).cuda()
+    r.run_device(u[:1].contiguous())                   # warm-up
+    r.set_state(m0)
+    r.trace_phases(stages)
+    r.run_device(u)
+    torch.cuda.synchronize()
+    st, khz = r.phase_times()
+    path = r.path
+    r.trace_phases(0)
+    r.close()
+    t = st.astype(np.float64) * (1e3 / khz)           # microseconds
+    ok = np.all(st > 0, axis=2)
+    # the resident kernel's workgroups all wait for each other; those of the
+    # multi-stream kernel only for their own stream group, so no time
+    # relative to the last publish of the whole grid is reported there
+    across = path == "resident"
+    med = lambda x: float(np.median(x)) if np.size(x) else None  # noqa: E731
+    last_pub = np.max(np.where(ok, t[:, :, 3], -np.inf), axis=0)
+    return {
+        "workload": name, "dtype": dtype, "coupling": coupling, "path": path, "workgroups": int(st.shape[0]),
+        "stages": int(st.shape[1]),
+        "clock_khz": khz,
+        "gather_us": med((t[:, :, 1] - t[:, :, 0])[ok]), "compute_us": med((t[:, :, 2] - t[:, :, 1])[ok]),
+        "publish_us": med((t[:, :, 3] - t[:, :, 2])[ok]),
+        "stage_us": med(np.diff(t[:, :, 0], axis=1)[ok[:, 1:] & ok[:, :-1]]),
+        "after_last_publish_us": med((t[:, 1:, 1] - last_pub[None, :-1])[ok[:, 1:]]) if across else None,
+        "publish_spread_us": (med((last_pub - np.min(np.where(ok, t[:, :, 3], np.inf), axis=0))[1:])
+                              if across else None),
+    }
+
+
 def cpu_blas_form(name: str, arrays, prm, budget_s: float = 4.0):
     """The oracle with its coupling as NumPy's matrix product (the analogue of
     the paper's NumPy baseline), timed on one input sample with BLAS pinned to
@@ -695,6 +750,8 @@ def main():
                     help="sweep workload: time the plain path over the whole input series, not a prefix")
     ap.add_argument("--coupling", default="x", choices=("x", "xyz"),
                     help="multi-stream workload: the paper's m^x coupling or all three components")
+    ap.add_argument("--phases", type=int, default=0, metavar="STAGES",
+                    help="only print the exchange-phase breakdown of the workload's persistent kernel over STAGES stages")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device with a plain copy kernel (scales HBM counters)")
     args = ap.parse_args()
@@ -710,6 +767,11 @@ def main():
     import paper_2312_01121_amd as stx
     from workloads import WORKLOADS, make_workload_arrays
 
+    if args.phases:
+        res = phase_breakdown(stx, torch, args.workload, args.dtype, args.phases, coupling=args.coupling)
+        finish(torch)
+        print(json.dumps({"phases": res}), flush=True)
+        return
     if args.paper_table:
         rows = paper_table(stx, torch, args.paper_table, args.repeats)
         finish(torch)

@@ -134,10 +134,19 @@ __device__ bool gather_multi(const float* xb, int64_t ld, int64_t cstride, int n
 // write the stage trace of the adjoint (tr); sample0 offsets the sample
 // index reported on a non-finite state.  RT: 16-node row tiles per
 // workgroup (1 or 2), which share the gathered columns.
+// With a phase buffer, thread 0 of every workgroup stamps the device's
+// constant-rate clock at four points of each of the first phase_stages
+// stages (start, columns gathered, own pairs computed, published).
+__device__ __forceinline__ void multi_stamp(unsigned long long* phase, int phase_stages, int sigma, int point) {
+    if (phase && sigma < phase_stages && threadIdx.x == 0)
+        phase[(((size_t)blockIdx.y * gridDim.x + blockIdx.x) * phase_stages + sigma) * 4 + point] = wall_clock64();
+}
+
 template <int KREG, bool XYZ, bool TRACE, int RT>
 __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float> k, const double* __restrict__ u,
                                                   float* __restrict__ states, int streams, int samples,
-                                                  int substeps, int renorm, int sample0, MultiTrace tr) {
+                                                  int substeps, int renorm, int sample0, MultiTrace tr,
+                                                  unsigned long long* phase, int phase_stages) {
     constexpr int C = XYZ ? 3 : 1;
     constexpr int SPW = streams_per_group<XYZ>();
     constexpr int KI = KREG <= 16 ? 1 : KREG / 16;   // gather entries per row and thread: 512 KI >= 32 KREG >= N
@@ -196,9 +205,11 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
                 float* xout = xbuf + (int64_t)((sigma + 1) % 3) * bstride;
                 float* xold = xbuf + (int64_t)((sigma + 2) % 3) * bstride;
                 __syncthreads();
+                multi_stamp(phase, phase_stages, sigma, 0);
                 if (!gather_multi<C, SPW, KI>(xin, ld, cstride, n, s0, ns, xs, abort_flag)) ok_lds = 0;
                 __syncthreads();
                 if (ok_lds == 0) return;
+                multi_stamp(phase, phase_stages, sigma, 1);
                 // re-arm this pair's entries of the buffer two stages ahead now;
                 // the stores complete while the stage is computed
                 if (mine) {
@@ -280,6 +291,7 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
                 sx = nx;
                 sy = ny;
                 sz = nz;
+                multi_stamp(phase, phase_stages, sigma, 2);
                 if (mine) {
                     const int64_t o = (int64_t)strm * ld + node;
                     __hip_atomic_store(xout + o, nx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -288,6 +300,7 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
                         __hip_atomic_store(xout + 2 * cstride + o, nz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
+                multi_stamp(phase, phase_stages, sigma, 3);
             }
         }
         if (mine) {
@@ -628,7 +641,10 @@ hipError_t launch_multi(const DevState<float>& d, const Coef<float>& k, const Ru
     float* states = static_cast<float*>(r.states);
     int st = streams, samples = r.samples, substeps = r.substeps, renorm = r.renorm, s0 = sample0;
     MultiTrace t = tr;
-    void* args[] = {&dd, &kk, &u, &states, &st, &samples, &substeps, &renorm, &s0, &t};
+    // the phase trace, when it was armed for at least this grid
+    unsigned long long* phase = r.trace && r.trace_groups >= sh.gx * sh.gy ? r.trace : nullptr;
+    int phase_stages = phase ? r.trace_stages : 0;
+    void* args[] = {&dd, &kk, &u, &states, &st, &samples, &substeps, &renorm, &s0, &t, &phase, &phase_stages};
     e = hipLaunchCooperativeKernel(sh.fn, dim3(sh.gx, sh.gy), dim3(kBlock), args, (unsigned)sh.lds, r.stream);
     if (e != hipSuccess) return e;
     return hipGetLastError();

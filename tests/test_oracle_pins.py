@@ -229,3 +229,36 @@ def test_norm_drift_bounded_on_sto16_prefix():
     prm = constants.dimensionless(a_cp=wl.a_cp, a_in=wl.a_in, dt=wl.dt, substeps=wl.substeps)
     rec, _ = sto.run(a["W"], a["w_in"], a["m0"], a["u"], prm)
     assert 0.0 < sto.norm_drift(rec) < 1e-5
+
+
+# ----------------------------------------------------------------------------
+# Stored full-horizon fixtures: made by the current oracle from the current
+# generators (tests/golden/make_horizon.py)
+# ----------------------------------------------------------------------------
+def _fixture(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"horizon_{name}.npz")
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files} | {"meta": json.loads(str(z["meta"]))}
+
+
+@pytest.mark.parametrize("name", ["sto1k", "sto10k", "paper2500", "paper5000", "paper10000"])
+def test_horizon_fixture_is_current(name):
+    """Each fixture records a hash of the oracle and generator sources it was
+    written with: it must be the current one, and its first records must be
+    what the oracle computes now (the first sample, or the first two)."""
+    import sys
+    import os
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_horizon
+    fix = _fixture(name)
+    assert fix["meta"]["oracle_sha256"] == make_horizon.source_hash(), name
+    a, prm, meta = make_horizon.case_inputs(name)
+    assert meta["n"] == fix["meta"]["n"] and meta["samples"] == fix["meta"]["samples"] == len(fix["sums"])
+    k = 2 if meta["n"] <= 1000 else 1
+    rec, _ = sto.run(a["W"], a["w_in"], a["m0"], a["u"][:k], prm)
+    assert np.array_equal(np.array([[math.fsum(rec[s, :, c]) for c in range(3)] for s in range(k)]),
+                          fix["sums"][:k])
+    assert fix["idx"][0] == 0 and np.array_equal(fix["records"][0], rec[0])
+    assert fix["idx"][-1] == meta["samples"] - 1 and np.array_equal(fix["records"][-1], fix["final"])
