@@ -44,7 +44,7 @@ def log(*a):
 
 
 KERNEL_SOURCES = {
-    "k_sweep_stage": ("sto_device.hpp", "sto_internal.hpp", "sto_sweep.hpp", "sto_sweep.hip"),
+    "k_sweep_stage": ("sto_device.hpp", "sto_internal.hpp", "sto_sweep.hpp", "sto_sweep.hip", "sweep_tune.hpp"),
     "k_multi": ("sto_device.hpp", "sto_internal.hpp", "sto_multi.hip"),
     "k_stage": ("sto_device.hpp", "sto_internal.hpp", "sto_kernels.hip"),
     "k_small": ("sto_device.hpp", "sto_internal.hpp", "sto_small.hip"),
@@ -52,15 +52,16 @@ KERNEL_SOURCES = {
 }
 
 
-# Of the shared internal header only the structures the kernels take as
-# arguments enter the hash: the rest of it is host-side.
-KERNEL_STRUCTS = ("DevState", "SweepRes", "SweepTask", "SweepDev")
+# Of the shared internal header only the structures a kernel takes as
+# arguments enter its hash: the rest of it is host-side.
+KERNEL_STRUCTS = {"k_sweep_stage": ("SweepRes", "SweepTask", "SweepDev")}
+DEFAULT_STRUCTS = ("DevState",)
 
 
-def _kernel_structs(text: str) -> bytes:
+def _kernel_structs(text: str, names) -> bytes:
     import re
     parts = []
-    for name in KERNEL_STRUCTS:
+    for name in names:
         m = re.search(r"struct " + name + r" \{.*?\n\};", text, flags=re.S)
         parts.append(m.group(0) if m else "")
     return "\n".join(parts).encode()
@@ -72,7 +73,9 @@ def kernel_source_hash(kernel: str) -> str:
     for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2312_01121_amd", "csrc", f), "rb") as fh:
             data = fh.read()
-        h.update(_kernel_structs(data.decode()) if f == "sto_internal.hpp" else data)
+        if f == "sto_internal.hpp":
+            data = _kernel_structs(data.decode(), KERNEL_STRUCTS.get(kernel, DEFAULT_STRUCTS))
+        h.update(data)
     return h.hexdigest()[:16]
 
 

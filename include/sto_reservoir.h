@@ -129,6 +129,49 @@ sto_status reservoir_create_streams(int64_t n, int64_t n_in, int64_t streams, co
                                     sto_reservoir **out);
 
 /*
+ * reservoir_create_device -- reservoir_create_streams from device buffers of
+ * doubles on the current HIP device (the same model, Sec. 3.1, Eq. (gov),
+ * (coup) and (in)); nothing passes through host memory.
+ *   W_dev       device, n*n doubles, row-major (Eq. (coup))
+ *   w_in_dev    device, n*n_in doubles (Eq. (in))
+ *   m0_dev      device, S*n*3 doubles, [stream][node][xyz], unit vectors
+ *               (within 1e-12, else STO_E_INVALID)
+ *   hip_stream  hipStream_t the copies are enqueued on (NULL: the null
+ *               stream); the call returns after it has finished them
+ * The buffers are read, not kept.  Errors: those of
+ * reservoir_create_streams; STO_E_NONFINITE for a non-finite value.
+ */
+sto_status reservoir_create_device(int64_t n, int64_t n_in, int64_t streams, const sto_params *prm,
+                                   const double *W_dev, const double *w_in_dev, const double *m0_dev,
+                                   void *hip_stream, sto_reservoir **out);
+
+/*
+ * reservoir_load_device -- replace the coupling matrix, the input weights,
+ * the state and the constants of an existing handle, from device buffers of
+ * doubles, without building a new handle (a gradient-based tuning loop of
+ * the model of Sec. 3.1 changes W, w_in and the constants between runs).
+ *   W_dev       device, n*n doubles, row-major; NULL keeps W
+ *   w_in_dev    device, n*n_in doubles; NULL keeps w_in
+ *   m_dev       device, S*n*3 doubles, [stream][node][xyz]: the state the
+ *               next run starts from (checked for finiteness only, as
+ *               reservoir_set_state); NULL keeps the state
+ *   prm         host; NULL keeps the constants.  Only the constants of the
+ *               equation may differ from the handle's (alpha, h_appl, h_k,
+ *               h_s, lambda_stt, p, a_cp, a_in, dt); dtype, coupling,
+ *               substeps, renormalize and path must be those the handle was
+ *               created with (STO_E_INVALID otherwise)
+ *   hip_stream  hipStream_t to enqueue on (NULL: the null stream); the
+ *               call returns after it has finished
+ * Conversion to the handle's dtype and layout runs on the device (one pass
+ * over each array); a transpose of W the handle keeps follows the new W.
+ * Errors: STO_E_INVALID, STO_E_NONFINITE (a non-finite value: the arrays
+ * named are then partly loaded and must be loaded again before a run; the
+ * constants are not changed), STO_E_DEVICE.
+ */
+sto_status reservoir_load_device(sto_reservoir *r, const double *W_dev, const double *w_in_dev,
+                                 const double *m_dev, const sto_params *prm, void *hip_stream);
+
+/*
  * reservoir_run -- integrate steps RK4 steps from the current state.
  *   u       host, (steps/substeps) * n_in doubles, one input vector per
  *           sample, held for substeps steps (all four stages of a step see

@@ -82,6 +82,11 @@ def _load():
                                      ctypes.POINTER(H)]
     lib.reservoir_create_streams.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                              ctypes.POINTER(sto_params), dp, dp, dp, ctypes.POINTER(H)]
+    lib.reservoir_create_device.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                            ctypes.POINTER(sto_params), vp, vp, vp, vp, ctypes.POINTER(H)]
+    lib.reservoir_create_device.restype = ctypes.c_int
+    lib.reservoir_load_device.argtypes = [H, vp, vp, vp, ctypes.POINTER(sto_params), vp]
+    lib.reservoir_load_device.restype = ctypes.c_int
     lib.reservoir_streams.argtypes = [H]
     lib.reservoir_streams.restype = ctypes.c_int64
     lib.reservoir_run.argtypes = [H, dp, ctypes.c_int64, dp]
@@ -148,7 +153,7 @@ def _load():
 
 _lib = _load()
 
-EXPORTED = ("reservoir_create", "reservoir_create_streams", "reservoir_streams", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
+EXPORTED = ("reservoir_create", "reservoir_create_streams", "reservoir_create_device", "reservoir_load_device", "reservoir_streams", "reservoir_run", "reservoir_run_device", "reservoir_get_state",
             "reservoir_set_state", "reservoir_path", "reservoir_destroy", "readout_fit", "readout_fit_device",
             "readout_fit_device_noalloc",
             "readout_fit_batch_device", "sweep_create", "sweep_nodes", "sweep_run", "sweep_run_device", "sweep_get_state", "sweep_destroy",
@@ -200,6 +205,25 @@ def reservoir_create_streams(n: int, n_in: int, streams: int, prm: sto_params, W
     _check(_lib.reservoir_create_streams(n, n_in, streams, ctypes.byref(prm), _dptr(W), _dptr(w_in), _dptr(m0),
                                          ctypes.byref(h)))
     return h
+
+
+def _vp(ptr):
+    return ctypes.c_void_p(ptr) if ptr else None
+
+
+def reservoir_create_device(n: int, n_in: int, streams: int, prm: sto_params, W_ptr: int, w_in_ptr: int,
+                            m0_ptr: int, stream_ptr: Optional[int]) -> ctypes.c_void_p:
+    """Device pointers of doubles: W (n, n), w_in (n, n_in), m0 (streams, n, 3)."""
+    h = ctypes.c_void_p()
+    _check(_lib.reservoir_create_device(n, n_in, streams, ctypes.byref(prm), _vp(W_ptr), _vp(w_in_ptr), _vp(m0_ptr),
+                                        _vp(stream_ptr), ctypes.byref(h)))
+    return h
+
+
+def reservoir_load_device(h, W_ptr: Optional[int], w_in_ptr: Optional[int], m_ptr: Optional[int],
+                          prm: Optional[sto_params], stream_ptr: Optional[int]):
+    _check(_lib.reservoir_load_device(h, _vp(W_ptr), _vp(w_in_ptr), _vp(m_ptr),
+                                      ctypes.byref(prm) if prm is not None else None, _vp(stream_ptr)))
 
 
 def reservoir_streams(h) -> int:
@@ -464,6 +488,47 @@ class Reservoir:
             self.h = reservoir_create(self.n, self.n_in, prm, W, w_in, m0)
         else:
             self.h = reservoir_create_streams(self.n, self.n_in, self.streams, prm, W, w_in, m0)
+
+    @classmethod
+    def from_device(cls, W_dev, w_in_dev, m0_dev, prm: sto_params, streams: int = 1, stream=None) -> "Reservoir":
+        """A handle built from CUDA float64 tensors (reservoir_create_device):
+        W (n, n), w_in (n, n_in), m0 ([streams,] n, 3)."""
+        import torch
+        self = cls.__new__(cls)
+        self.n = int(W_dev.shape[0])
+        self.n_in = int(w_in_dev.numel() // self.n)
+        self.streams = int(streams)
+        self.substeps = prm.substeps
+        self.dtype = "f64" if prm.dtype == STO_F64 else "f32"
+        self._check_device(W_dev, (self.n, self.n))
+        self._check_device(w_in_dev, (self.n * self.n_in,))
+        self._check_device(m0_dev, (self.streams * self.n * 3,))
+        s = (stream or torch.cuda.current_stream()).cuda_stream
+        self.h = reservoir_create_device(self.n, self.n_in, self.streams, prm, W_dev.data_ptr(), w_in_dev.data_ptr(),
+                                         m0_dev.data_ptr(), s)
+        return self
+
+    @staticmethod
+    def _check_device(t, shape):
+        import torch
+        assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), "a contiguous CUDA float64 tensor"
+        assert t.numel() == int(np.prod(shape)), f"{tuple(t.shape)} does not hold {shape}"
+
+    def load_device(self, W_dev=None, w_in_dev=None, m_dev=None, prm: Optional[sto_params] = None, stream=None):
+        """Replace W, w_in, the state and/or the constants from CUDA float64
+        tensors (reservoir_load_device); None keeps the current one."""
+        import torch
+        if W_dev is not None:
+            self._check_device(W_dev, (self.n, self.n))
+        if w_in_dev is not None:
+            self._check_device(w_in_dev, (self.n * self.n_in,))
+        if m_dev is not None:
+            self._check_device(m_dev, (self.streams * self.n * 3,))
+        s = (stream or torch.cuda.current_stream()).cuda_stream
+        ptr = lambda t: t.data_ptr() if t is not None else None
+        reservoir_load_device(self.h, ptr(W_dev), ptr(w_in_dev), ptr(m_dev), prm, s)
+        if prm is not None:
+            self.substeps = prm.substeps
 
     @property
     def path(self) -> str:

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsto_reservoir.so")
-SOURCES = ["runtime.hip", "sto_kernels.hip", "sto_small.hip", "sto_resident.hip", "sto_multi.hip", "sto_sweep.hip", "sto_adjoint.hip", "sto_batch.hip", "readout.hip", "readout_batch.hip"]
+SOURCES = ["runtime.hip", "sto_kernels.hip", "sto_small.hip", "sto_resident.hip", "sto_multi.hip", "sto_sweep.hip", "sto_adjoint.hip", "sto_batch.hip", "sto_load.hip", "readout.hip", "readout_batch.hip"]
 ARCH = os.environ.get("STO_OFFLOAD_ARCH", "gfx950")
 
 

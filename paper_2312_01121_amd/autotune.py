@@ -5,6 +5,10 @@ launch shape (rows of W per wave x unroll of the column loop) of the stage
 kernel on this GPU, for each element type and a ladder of sizes, and writes
 the fastest shape per size bucket into ``csrc/stream_tune.hpp``.
 
+``--sweep``: times candidate tables of the sweep kernel's rows per lane
+group and row pitch (by reservoir size) on the 256-reservoir sweep workload
+and writes the fastest into ``csrc/sweep_tune.hpp``.
+
 ``--paths``: times the three single-stream paths at a ladder of sizes for
 each element type and coupling -- the one-workgroup kernel (small), the
 cooperative kernel with W in the LDS of many workgroups (resident) in every
@@ -228,10 +232,108 @@ def tune_paths(stx, torch, samples, write):
         print(f"wrote {write}", file=sys.stderr)
 
 
+SWEEP_HEADER = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "sweep_tune.hpp")
+# Candidate tables (n_max, rows per lane group, row pitch in elements) for
+# FP32: uniform shapes, a short 64-byte pitch below a size threshold (less
+# padding), 4 rows per group for the largest reservoirs.  They are timed on
+# the 256-reservoir sweep workload itself, where the reservoirs compete for
+# HBM and L2: optima measured per size on sweeps of equal reservoirs did not
+# carry over to it.
+SWEEP_CANDIDATES = [
+    [(1 << 30, 8, 64)],
+    [(1 << 30, 8, 32)],
+    [(1 << 30, 8, 16)],
+    [(1 << 30, 4, 64)],
+    [(48, 8, 16), (1 << 30, 8, 64)],
+    [(192, 8, 16), (1 << 30, 8, 64)],
+    [(192, 8, 16), (1 << 30, 8, 32)],
+    [(1792, 8, 32), (1 << 30, 4, 32)],
+]
+
+
+def table_env(cand):
+    return ",".join(f"{n}:{r}:{p}" for n, r, p in cand)
+
+
+def time_sweep_table(stx, torch, cand, samples=200, reps=3):
+    """Microseconds per RK4 step of the 256-reservoir sweep workload with a
+    candidate table."""
+    from workloads import SWEEPS, make_sweep_arrays
+    os.environ["STO_SWEEP_TABLE"] = table_env(cand)
+    try:
+        import dataclasses
+        from paper_2312_01121_amd import params
+        sw_def = dataclasses.replace(SWEEPS["sweep256"], samples=samples)
+        a = make_sweep_arrays(sw_def)
+        res = a["reservoirs"]
+        for r in res:
+            r["prm"] = stx.make_params(**params.table1(a_cp=r["a_cp"], a_in=r["a_in"], dt=sw_def.dt,
+                                                       substeps=sw_def.substeps, current_scale=r["current_scale"],
+                                                       field_scale=r["field_scale"]), dtype="f32")
+        sw = stx.Sweep(res)
+        u = torch.from_numpy(a["u"]).cuda()
+        sw.run_device(u[:2].contiguous())
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sw.run_device(u)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) * 1e3 / (samples * sw_def.substeps))
+        sw.close()
+        return best
+    finally:
+        os.environ.pop("STO_SWEEP_TABLE", None)
+
+
+def tune_sweep(stx, torch, write):
+    measured = {}
+    for cand in SWEEP_CANDIDATES:
+        us = time_sweep_table(stx, torch, cand)
+        measured[table_env(cand)] = round(us, 2)
+        print(json.dumps({"table": table_env(cand), "us_per_rk4_step": round(us, 2)}), flush=True)
+    best = min(SWEEP_CANDIDATES, key=lambda c: measured[table_env(c)])
+    if write:
+        lines = [f"    {{4, {n}, {r}, {p}}}," for n, r, p in best] + ["    {8, 1073741824, 8, 64},"]
+        table = "\n".join(lines)
+        text = f"""// Rows per lane group and row pitch of the sweep kernel by element type and
+// reservoir size, chosen by measurement.  Written by
+// paper_2312_01121_amd/autotune.py --sweep, which times candidate tables on
+// the 256-reservoir FP32 sweep workload (N log-uniform in [32, 2048]) and
+// keeps the fastest; FP64 sweeps keep 8 rows and a 64-element pitch.
+// Entries are scanned in order and the first with n <= n_max applies.
+#pragma once
+
+namespace sto {{
+
+struct SweepTuneEntry {{
+    int elem_bytes;
+    int n_max;
+    int rows;    // rows of W per lane group (2, 4 or 8)
+    int pitch;   // row pitch of W and the state, in elements (a multiple of 16 bytes)
+}};
+
+constexpr SweepTuneEntry kSweepTune[] = {{
+{table}
+}};
+
+// Measured (candidate table n_max:rows:pitch,...): us per RK4 step of the sweep
+// {json.dumps(measured, sort_keys=True)}
+
+}}  // namespace sto
+"""
+        with open(write, "w") as fh:
+            fh.write(text)
+        print(f"wrote {write}", file=sys.stderr)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--samples", type=int, default=3)
     ap.add_argument("--paths", action="store_true", help="tune the path choice and resident shapes instead")
+    ap.add_argument("--sweep", action="store_true", help="tune the sweep kernel's rows per group and row pitch")
     ap.add_argument("--write", nargs="?", const="default", default=None, metavar="PATH",
                     help="write the table header (default: csrc/stream_tune.hpp, or csrc/path_tune.hpp)")
     args = ap.parse_args()
@@ -242,6 +344,9 @@ def main():
     if args.paths:
         write = PATH_HEADER if args.write == "default" else args.write
         tune_paths(stx, torch, max(args.samples, 60), write)
+        return
+    if args.sweep:
+        tune_sweep(stx, torch, SWEEP_HEADER if args.write == "default" else args.write)
         return
     if args.write == "default":
         args.write = HEADER

@@ -18,6 +18,7 @@
 #include "sto_adjoint.hpp"
 #include "readout_batch.hpp"
 #include "sto_internal.hpp"
+#include "sto_load.hpp"
 #include "sto_sweep.hpp"
 #include "stream_tune.hpp"
 
@@ -494,7 +495,9 @@ struct sto_sweep {
     void* task_dev = nullptr;
     int tasks = 0;
     int* bad = nullptr;
+    int* sample = nullptr;         // device: the input sample being stepped
     hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr; // stream the graph of the stage launches is captured on
     double* u_dev = nullptr;
     size_t u_cap = 0;
     void* states_dev = nullptr;
@@ -505,10 +508,11 @@ namespace {
 
 void sweep_free(sto_sweep* s) {
     void* ptrs[] = {s->W, s->w_in, s->m, s->ms[0], s->ms[1], s->acc, s->res_dev, s->coef_dev, s->task_dev, s->bad,
-                    s->u_dev, s->states_dev};
+                    s->sample, s->u_dev, s->states_dev};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->capture) (void)hipStreamDestroy(s->capture);
 }
 
 // Copy a rows x cols host matrix of doubles into the device at dst (element
@@ -541,6 +545,7 @@ sto::SweepDev<T> sweep_dev(const sto_sweep* s, void* states, int64_t samples) {
     d.tasks = s->tasks;
     d.n_in = (int)s->n_in;
     d.rec_samples = samples;
+    d.sample = s->sample;
     return d;
 }
 
@@ -564,12 +569,34 @@ sto_status sweep_run_impl(sto_sweep* s, const double* u_dev, int64_t steps, void
     spec.renorm = s->renorm;
     spec.xyz = 0;
     spec.stream = stream;
-    hipError_t e = s->dtype == STO_F64 ? sto::run_sweep<double>(sweep_dev<double>(s, states_dev, samples), spec)
-                                       : sto::run_sweep<float>(sweep_dev<float>(s, states_dev, samples), spec);
-    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    // the launches of a few samples are captured once into a graph and
+    // replayed (STO_SWEEP_GRAPH=0: every launch issued directly; the sample
+    // count per graph from STO_SWEEP_GRAPH_SAMPLES, default 8)
+    const int graph_on = env_flag("STO_SWEEP_GRAPH", 1);
+    const int graph_samples = std::max(1, env_int("STO_SWEEP_GRAPH_SAMPLES", 8));
+    if (graph_on && !s->capture)
+        HIP_TRY(hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking), "hipStreamCreate");
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = s->dtype == STO_F64
+                       ? sto::run_sweep<double>(sweep_dev<double>(s, states_dev, samples), spec,
+                                                graph_on ? s->capture : nullptr, graph_samples, &graph, &exec)
+                       : sto::run_sweep<float>(sweep_dev<float>(s, states_dev, samples), spec,
+                                               graph_on ? s->capture : nullptr, graph_samples, &graph, &exec);
+    auto drop_graph = [&]() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    };
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(stream);
+        drop_graph();
+        return hip_fail(e, "kernel launch");
+    }
     int bad = none;
-    HIP_TRY(hipMemcpyAsync(&bad, s->bad, sizeof(int), hipMemcpyDeviceToHost, stream), "flag read");
-    HIP_TRY(hipStreamSynchronize(stream), "run");
+    e = hipMemcpyAsync(&bad, s->bad, sizeof(int), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    drop_graph();
+    if (e != hipSuccess) return hip_fail(e, "run");
     if (bad != none) return fail(STO_E_NONFINITE, "state not finite after sample %d", bad);
     return STO_OK;
 }
@@ -617,8 +644,13 @@ sto_status reservoir_create(int64_t n, int64_t n_in, const sto_params* prm, cons
 
 int64_t reservoir_streams(const sto_reservoir* r) { return r ? r->streams : -1; }
 
-sto_status reservoir_create_streams(int64_t n, int64_t n_in, int64_t streams, const sto_params* prm,
-                                    const double* W, const double* w_in, const double* m0, sto_reservoir** out) {
+}  // extern "C"
+
+namespace {
+
+// Checks the sizes and constants, chooses the path and allocates a handle
+// whose device arrays are all zero (W, w_in and the state still to load).
+sto_status create_empty(int64_t n, int64_t n_in, int64_t streams, const sto_params* prm, sto_reservoir** out) {
     if (!out) return fail(STO_E_INVALID, "out is NULL");
     *out = nullptr;
     if (n < 1 || n > (int64_t)INT_MAX / 4) return fail(STO_E_INVALID, "n out of range: %lld", (long long)n);
@@ -626,14 +658,6 @@ sto_status reservoir_create_streams(int64_t n, int64_t n_in, int64_t streams, co
     if (n_in < 1 || n_in > 65536) return fail(STO_E_INVALID, "n_in out of range: %lld", (long long)n_in);
     sto_status st = validate_params(prm);
     if (st != STO_OK) return st;
-    if (!W || !w_in || !m0) return fail(STO_E_INVALID, "W, w_in and m0 must be non-NULL");
-    if (!finite_all(W, n * n) || !finite_all(w_in, n * n_in) || !finite_all(m0, 3 * n * streams))
-        return fail(STO_E_NONFINITE, "non-finite input array");
-    for (int64_t k = 0; k < n * streams; ++k) {
-        const double* v = m0 + 3 * k;
-        double nn = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-        if (std::fabs(nn - 1.0) > 1e-12) return fail(STO_E_INVALID, "|m0[%lld]| = %.17g is not 1", (long long)k, nn);
-    }
 
     sto_reservoir* r = new (std::nothrow) sto_reservoir();
     if (!r) return fail(STO_E_NOMEM, "handle");
@@ -715,21 +739,132 @@ sto_status reservoir_create_streams(int64_t n, int64_t n_in, int64_t streams, co
 #undef ALLOC
     e = hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking);
     if (e != hipSuccess) return cleanup(hip_fail(e, "hipStreamCreate"));
+    *out = r;
+    return STO_OK;
+}
 
+void destroy_handle(sto_reservoir* r) {
+    if (!r) return;
+    if (r->stream) (void)hipStreamSynchronize(r->stream);
+    free_all(r);
+    delete r;
+}
+
+// The BATCH path reads W^T on every run: made when W is first set.
+sto_status batch_transpose(sto_reservoir* r) {
+    if (r->path != STO_PATH_BATCH) return STO_OK;
+    sto_status st = ensure_transpose(r, r->stream);
+    if (st == STO_OK && hipStreamSynchronize(r->stream) != hipSuccess) st = fail(STO_E_DEVICE, "transpose");
+    return st;
+}
+
+template <typename T>
+hipError_t load_arrays(sto_reservoir* r, const double* W, const double* w_in, const double* m, int check_norm,
+                       hipStream_t stream) {
+    hipError_t e = hipSuccess;
+    if (W) {
+        e = sto::load_matrix<T>(W, r->n, r->n, static_cast<T*>(r->W), r->ld, r->bad, stream);
+        // a transpose made before (adjoint, BATCH path) follows W
+        if (e == hipSuccess && r->Wt)
+            e = sto::transpose_matrix<T>(static_cast<const T*>(r->W), static_cast<T*>(r->Wt), (int)r->n, r->ld,
+                                         stream);
+    }
+    if (e == hipSuccess && w_in)
+        e = sto::load_matrix<T>(w_in, r->n, r->n_in, static_cast<T*>(r->w_in), r->n_in, r->bad, stream);
+    if (e == hipSuccess && m) {
+        T* ms = r->streams == 1 || r->path == STO_PATH_BATCH ? static_cast<T*>(r->ms[r->cur]) : nullptr;
+        e = sto::load_state<T>(m, r->n, r->streams, r->ld, static_cast<T*>(r->m), ms, check_norm, r->bad, stream);
+    }
+    return e;
+}
+
+sto_status load_device_impl(sto_reservoir* r, const double* W, const double* w_in, const double* m,
+                            const sto_params* prm, int check_norm, hipStream_t stream) {
+    if (!r) return fail(STO_E_INVALID, "handle is NULL");
+    if (prm) {
+        sto_status st = validate_params(prm);
+        if (st != STO_OK) return st;
+        const sto_params& o = r->prm;
+        if (prm->dtype != o.dtype || prm->coupling != o.coupling || prm->substeps != o.substeps ||
+            prm->renormalize != o.renormalize || prm->path != o.path)
+            return fail(STO_E_INVALID,
+                        "params may change only the constants of the equation: dtype, coupling, substeps, "
+                        "renormalize and path must stay those of the handle");
+    }
+    HIP_TRY(hipStreamSynchronize(r->stream), "sync");
+    int flags = 0;
+    if (W || w_in || m) {
+        HIP_TRY(hipMemsetAsync(r->bad, 0, sizeof(int), stream), "flag reset");
+        hipError_t e = r->dtype == STO_F64 ? load_arrays<double>(r, W, w_in, m, check_norm, stream)
+                                           : load_arrays<float>(r, W, w_in, m, check_norm, stream);
+        if (e != hipSuccess) return hip_fail(e, "load");
+        HIP_TRY(hipMemcpyAsync(&flags, r->bad, sizeof(int), hipMemcpyDeviceToHost, stream), "flag read");
+        HIP_TRY(hipStreamSynchronize(stream), "load");
+    }
+    if (flags & sto::kLoadNonFinite) return fail(STO_E_NONFINITE, "non-finite input array");
+    if (flags & sto::kLoadOffSphere) return fail(STO_E_INVALID, "an initial magnetisation is not of unit length");
+    if (prm) r->prm = *prm;
+    return STO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sto_status reservoir_create_streams(int64_t n, int64_t n_in, int64_t streams, const sto_params* prm,
+                                    const double* W, const double* w_in, const double* m0, sto_reservoir** out) {
+    if (!out) return fail(STO_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!W || !w_in || !m0) return fail(STO_E_INVALID, "W, w_in and m0 must be non-NULL");
+    if (n >= 1 && n_in >= 1 && streams >= 1 && n <= (int64_t)INT_MAX / 4 && n_in <= 65536 && streams <= 65536) {
+        if (!finite_all(W, n * n) || !finite_all(w_in, n * n_in) || !finite_all(m0, 3 * n * streams))
+            return fail(STO_E_NONFINITE, "non-finite input array");
+        for (int64_t k = 0; k < n * streams; ++k) {
+            const double* v = m0 + 3 * k;
+            double nn = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            if (std::fabs(nn - 1.0) > 1e-12)
+                return fail(STO_E_INVALID, "|m0[%lld]| = %.17g is not 1", (long long)k, nn);
+        }
+    }
+    sto_reservoir* r = nullptr;
+    sto_status st = create_empty(n, n_in, streams, prm, &r);
+    if (st != STO_OK) return st;
     st = upload_matrix(r, r->W, W, n, n, r->ld);
-    if (st != STO_OK) return cleanup(st);
-    st = upload_matrix(r, r->w_in, w_in, n, n_in, n_in);
-    if (st != STO_OK) return cleanup(st);
-    st = upload_state(r, m0);
-    if (st != STO_OK) return cleanup(st);
-    if (path == STO_PATH_BATCH) {
-        st = ensure_transpose(r, r->stream);
-        if (st == STO_OK && hipStreamSynchronize(r->stream) != hipSuccess) st = fail(STO_E_DEVICE, "transpose");
-        if (st != STO_OK) return cleanup(st);
+    if (st == STO_OK) st = upload_matrix(r, r->w_in, w_in, n, n_in, n_in);
+    if (st == STO_OK) st = upload_state(r, m0);
+    if (st == STO_OK) st = batch_transpose(r);
+    if (st != STO_OK) {
+        destroy_handle(r);
+        return st;
     }
     *out = r;
     return STO_OK;
 }
+
+sto_status reservoir_create_device(int64_t n, int64_t n_in, int64_t streams, const sto_params* prm,
+                                   const double* W_dev, const double* w_in_dev, const double* m0_dev,
+                                   void* hip_stream, sto_reservoir** out) {
+    if (!out) return fail(STO_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!W_dev || !w_in_dev || !m0_dev) return fail(STO_E_INVALID, "W, w_in and m0 must be non-NULL");
+    sto_reservoir* r = nullptr;
+    sto_status st = create_empty(n, n_in, streams, prm, &r);
+    if (st != STO_OK) return st;
+    st = load_device_impl(r, W_dev, w_in_dev, m0_dev, nullptr, 1, static_cast<hipStream_t>(hip_stream));
+    if (st == STO_OK) st = batch_transpose(r);
+    if (st != STO_OK) {
+        destroy_handle(r);
+        return st;
+    }
+    *out = r;
+    return STO_OK;
+}
+
+sto_status reservoir_load_device(sto_reservoir* r, const double* W_dev, const double* w_in_dev,
+                                 const double* m_dev, const sto_params* prm, void* hip_stream) {
+    return load_device_impl(r, W_dev, w_in_dev, m_dev, prm, 0, static_cast<hipStream_t>(hip_stream));
+}
+
 
 int32_t reservoir_adjoint_kernels(const sto_reservoir* r) { return r ? r->adjoint_kernels : -1; }
 
@@ -783,12 +918,7 @@ sto_status reservoir_phase_times(const sto_reservoir* r, uint64_t* out, int64_t 
     return STO_OK;
 }
 
-void reservoir_destroy(sto_reservoir* r) {
-    if (!r) return;
-    if (r->stream) (void)hipStreamSynchronize(r->stream);
-    free_all(r);
-    delete r;
-}
+void reservoir_destroy(sto_reservoir* r) { destroy_handle(r); }
 
 int32_t reservoir_path(const sto_reservoir* r) { return r ? r->path : -1; }
 
@@ -1091,28 +1221,11 @@ sto_status sweep_create(int32_t count, const int64_t* n, int64_t n_in, const sto
     s->elem = s->dtype == STO_F64 ? 8 : 4;
     s->substeps = prm[0].substeps;
     s->renorm = prm[0].renormalize;
-    int64_t woff = 0, soff = 0, winoff = 0, noff = 0;
-    std::vector<sto::SweepTask> tasks;
-    for (int r = 0; r < count; ++r) {
-        sto::SweepRes x;
-        x.n = (int)n[r];
-        x.pad = 0;
-        x.ld = round_up(n[r], 64);
-        x.woff = woff;
-        x.soff = soff;
-        x.winoff = winoff;
-        x.noff = noff;
-        s->res.push_back(x);
-        woff += n[r] * x.ld;
-        soff += 3 * x.ld;
-        winoff += n[r] * n_in;
-        noff += n[r];
-        // wave tasks in reservoir order (a largest-first order was measured
-        // slower: the small tasks then form the tail)
-        const int rows = sto::sweep_task_rows(x.ld, (int)s->elem);
-        for (int row = 0; row < n[r]; row += rows) tasks.push_back({x.woff, x.soff, (int)x.ld, x.n, r, row});
-    }
-    s->nodes = noff;
+    sto::SweepLayout lay = sto::sweep_layout((int)s->elem, count, n, n_in);
+    s->res = lay.res;
+    std::vector<sto::SweepTask>& tasks = lay.tasks;
+    const int64_t woff = lay.w_elems, soff = lay.s_elems, winoff = lay.win_elems;
+    s->nodes = lay.nodes;
     s->tasks = (int)tasks.size();
     auto cleanup = [&](sto_status st) {
         sweep_free(s);
@@ -1135,6 +1248,7 @@ sto_status sweep_create(int32_t count, const int64_t* n, int64_t n_in, const sto
     SALLOC(s->coef_dev, (s->dtype == STO_F64 ? sizeof(sto::Coef<double>) : sizeof(sto::Coef<float>)) * count);
     SALLOC(s->task_dev, sizeof(sto::SweepTask) * tasks.size());
     SALLOC(s->bad, sizeof(int));
+    SALLOC(s->sample, sizeof(int));
 #undef SALLOC
     e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     if (e != hipSuccess) return cleanup(hip_fail(e, "hipStreamCreate"));

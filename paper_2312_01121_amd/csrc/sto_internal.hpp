@@ -51,6 +51,8 @@ struct SweepTask {
     int n;             // nodes of the reservoir
     int res;           // reservoir index (constants, w_in, records)
     int row;           // first row of the task
+    int rpg;           // rows per lane group (2, 4 or 8)
+    int pad;
 };
 
 template <typename T>
@@ -68,6 +70,7 @@ struct SweepDev {
     int tasks;
     int n_in;
     int64_t rec_samples;   // samples of the current run (record layout)
+    int* sample;           // device: index of the input sample being stepped
 };
 
 struct RunSpec {
@@ -111,8 +114,13 @@ bool multi_fits(int n, int streams, int xyz, int* grid_x, int* grid_y);
 hipError_t run_multi(const DevState<float>& d, const Coef<float>& k, const RunSpec& r, int streams);
 
 // SWEEP path launcher (one launch per RK4 stage over every reservoir).
-template <typename T> hipError_t run_sweep(const SweepDev<T>& d, const RunSpec& r);
-int sweep_rows_per_task(int elem_bytes);
+// With a capture stream, the launches of `graph_samples` samples are
+// captured once into a HIP graph that is replayed on r.stream (the caller
+// destroys *graph and *exec after the stream has finished); without, every
+// launch is issued directly.
+template <typename T>
+hipError_t run_sweep(const SweepDev<T>& d, const RunSpec& r, hipStream_t capture, int graph_samples,
+                     hipGraph_t* graph, hipGraphExec_t* exec);
 
 // Largest n the single-workgroup kernel holds (W in LDS).
 int small_max_n(int elem_bytes, int xyz);

@@ -6,20 +6,30 @@
 // wave tasks (a table built on the host), each covering consecutive rows of
 // one reservoir: the wave is split into lane groups of G lanes, G the
 // largest power of two that the reservoir's row pitch fills with 16-byte
-// vectors (at most 64), and each group streams R rows of that reservoir's
-// coupling matrix with non-temporal loads against the reservoir's stage
-// input.  Short rows therefore do not leave most of a wave idle.  The row
-// sums are reduced within the group, and R lanes of each group apply the
-// reservoir's own right-hand side of Eq. (gov) and the RK4 bookkeeping
-// (Sec. 3.2), exactly as the single-reservoir stream kernel does.  The sum
-// of N_r^2 matrix elements is read once per stage, so the launch is bound by
-// HBM bandwidth.
+// vectors (at most 64), so that short rows do not leave most of a wave idle,
+// and each group streams R rows (2, 4 or 8) of that reservoir's coupling
+// matrix with non-temporal loads against the reservoir's stage input.  R
+// and the row pitch come per reservoir size from a table measured on a
+// mixed sweep (a shorter pitch streams fewer padding bytes); every
+// reservoir starts on a 256-byte boundary.  The row sums are reduced within
+// the group, and R lanes of each group apply the reservoir's own right-hand
+// side of Eq. (gov) and the RK4 bookkeeping (Sec. 3.2), exactly as the
+// single-reservoir stream kernel does.  The sum of N_r^2 matrix elements is
+// read once per stage, so the launch is bound by HBM bandwidth.
+//
+// The index of the sample being stepped lives in device memory and a
+// one-thread kernel advances it after each sample, so the launches of every
+// sample are identical: the host captures those of a few samples once into
+// a HIP graph and replays it.
 
+#include <algorithm>
 #include <climits>
+#include <cstdio>
 #include <cstdlib>
 
 #include "sto_internal.hpp"
 #include "sto_sweep.hpp"
+#include "sweep_tune.hpp"
 
 namespace sto {
 
@@ -40,17 +50,17 @@ __host__ __device__ inline int group_lanes(int64_t ld, int vn) {
     return g;
 }
 
+// One wave task: R rows per lane group.  The sample being stepped comes
+// from the device counter, so that the launches of one sample are the same
+// for every sample (and can be replayed from a graph).
 template <typename T, int R, int U>
-__global__ void __launch_bounds__(256) k_sweep_stage(SweepDev<T> d, const double* __restrict__ u_s, int sample,
-                                                     int stage, int cur, int record, int renorm) {
+__device__ __forceinline__ void sweep_task(const SweepDev<T>& d, const SweepTask& tk, const double* __restrict__ u,
+                                           int sample, int stage, int cur, int record, int renorm) {
     using A = Acc<T>;
     using AT = typename A::type;
     using V = typename SVec<T>::type;
     constexpr int VN = SVec<T>::n;
     const int lane = threadIdx.x & 63;
-    const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (task >= d.tasks) return;   // wave-uniform
-    const SweepTask tk = d.task[task];
     const int n = tk.n;
     const int64_t ld = tk.ld;
     const int G = group_lanes(ld, VN);   // wave-uniform
@@ -107,7 +117,7 @@ __global__ void __launch_bounds__(256) k_sweep_stage(SweepDev<T> d, const double
         if (gl == r) dot = A::round(s);
     }
     if (!own) return;
-    const T hin = input_field(k, d.w_in + res.winoff + (int64_t)row * d.n_in, u_s, d.n_in);
+    const T hin = input_field(k, d.w_in + res.winoff + (int64_t)row * d.n_in, u + (int64_t)sample * d.n_in, d.n_in);
     T fx, fy, fz;
     llg_rhs<T, false>(k, sx, sy, sz, k.a_cp * dot, T(0), T(0), hin, fx, fy, fz);
     T nx = rk4_update(k, stage, mx, ax, fx);
@@ -135,55 +145,152 @@ __global__ void __launch_bounds__(256) k_sweep_stage(SweepDev<T> d, const double
     xout[2 * ld + row] = nz;
 }
 
-}  // namespace
-
-// Rows per lane group (R): 8, measured fastest on a 256-reservoir sweep
-// (361.9 us per RK4 step against 368.6 with 4 and 415 with 2; visiting the
-// tasks last-to-first on alternate stages measured slower, 369.2).
-// STO_SWEEP_ROWS (2, 4 or 8) overrides it for measurements; it is read once
-// per process, so the task table and the kernel always agree.
-int sweep_rows_per_task(int elem_bytes) {
-    (void)elem_bytes;
-    static const int rows = [] {
-        const char* v = getenv("STO_SWEEP_ROWS");
-        const int r = v ? atoi(v) : 8;
-        return (r == 2 || r == 4) ? r : 8;
-    }();
-    return rows;
+// One RK4 stage of every reservoir; each wave runs one task with the task's
+// rows per lane group (wave-uniform).
+template <typename T, int U>
+__global__ void __launch_bounds__(256) k_sweep_stage(SweepDev<T> d, const double* __restrict__ u, int stage, int cur,
+                                                     int record, int renorm) {
+    const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (task >= d.tasks) return;   // wave-uniform
+    const SweepTask tk = d.task[task];
+    const int sample = *d.sample;
+    switch (tk.rpg) {
+        case 2: sweep_task<T, 2, U>(d, tk, u, sample, stage, cur, record, renorm); break;
+        case 4: sweep_task<T, 4, U>(d, tk, u, sample, stage, cur, record, renorm); break;
+        default: sweep_task<T, 8, U>(d, tk, u, sample, stage, cur, record, renorm); break;
+    }
 }
 
-// Rows of one reservoir covered by one wave task: R rows per lane group
-// times the groups in a wave.
-int sweep_task_rows(int64_t ld, int elem_bytes) {
-    return sweep_rows_per_task(elem_bytes) * (64 / group_lanes(ld, 16 / elem_bytes));
+__global__ void k_sweep_set(int* p, int v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
+__global__ void k_sweep_next(int* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p += 1;
+}
+
+int env_int(const char* name) {
+    const char* v = getenv(name);
+    return v && *v ? atoi(v) : 0;
+}
+
+// The launches of `samples` samples (4 per RK4 step, then the sample counter).
 template <typename T>
-hipError_t run_sweep(const SweepDev<T>& d, const RunSpec& r) {
+void issue(const SweepDev<T>& d, const RunSpec& r, int samples, hipStream_t st) {
     constexpr int U = sizeof(T) == 8 ? 4 : 2;
-    const int R = sweep_rows_per_task((int)sizeof(T));
     const dim3 grid((d.tasks + 3) / 4), block(256);
-    for (int s = 0; s < r.samples; ++s) {
-        const double* u_s = r.u + (int64_t)s * d.n_in;
+    for (int s = 0; s < samples; ++s) {
         for (int sub = 0; sub < r.substeps; ++sub)
             for (int stage = 0; stage < 4; ++stage) {
                 const int rec = stage == 3 && sub == r.substeps - 1;
                 const int c = r.cur ^ (stage & 1);
-                if (R == 4)
-                    hipLaunchKernelGGL((k_sweep_stage<T, 4, U>), grid, block, 0, r.stream, d, u_s, s, stage, c, rec,
-                                       r.renorm);
-                else if (R == 8)
-                    hipLaunchKernelGGL((k_sweep_stage<T, 8, U>), grid, block, 0, r.stream, d, u_s, s, stage, c, rec,
-                                       r.renorm);
-                else
-                    hipLaunchKernelGGL((k_sweep_stage<T, 2, U>), grid, block, 0, r.stream, d, u_s, s, stage, c, rec,
-                                       r.renorm);
+                hipLaunchKernelGGL((k_sweep_stage<T, U>), grid, block, 0, st, d, r.u, stage, c, rec, r.renorm);
             }
+        hipLaunchKernelGGL(k_sweep_next, dim3(1), dim3(64), 0, st, d.sample);
     }
+}
+
+// Rows per lane group and row pitch (elements) of the reservoirs of n nodes.
+void sweep_shape(int elem_bytes, int n, int* rows_per_group, int* pitch) {
+    const int env_rows = env_int("STO_SWEEP_ROWS"), env_pitch = env_int("STO_SWEEP_PITCH");
+    int rpg = 8, p = 64;
+    bool found = false;
+    // STO_SWEEP_TABLE="n_max:rows:pitch,...", scanned like the table, replaces
+    // it for both element types (the autotuner's candidates)
+    if (const char* t = getenv("STO_SWEEP_TABLE")) {
+        while (*t && !found) {
+            int nm = 0, r = 0, pp = 0, used = 0;
+            if (sscanf(t, "%d:%d:%d%n", &nm, &r, &pp, &used) != 3) break;
+            if (n <= nm) {
+                rpg = r;
+                p = pp;
+                found = true;
+            }
+            t += used;
+            if (*t == ',') ++t;
+        }
+        found = true;   // a given table replaces the compiled one even where it has no entry
+    }
+    for (const SweepTuneEntry& e : kSweepTune) {
+        if (found) break;
+        if (e.elem_bytes == elem_bytes && n <= e.n_max) {
+            rpg = e.rows;
+            p = e.pitch;
+            found = true;
+        }
+    }
+    if (rpg != 2 && rpg != 4 && rpg != 8) rpg = 8;
+    if (env_rows == 2 || env_rows == 4 || env_rows == 8) rpg = env_rows;
+    if (env_pitch > 0) p = env_pitch;
+    const int vn = 16 / elem_bytes;   // the pitch keeps every row 16-byte aligned
+    p = std::max(vn, (p + vn - 1) / vn * vn);
+    *rows_per_group = rpg;
+    *pitch = p;
+}
+
+}  // namespace
+
+SweepLayout sweep_layout(int elem_bytes, int count, const int64_t* n, int n_in) {
+    SweepLayout L;
+    const int64_t vn = 16 / elem_bytes, align = 256 / elem_bytes;
+    int64_t woff = 0, soff = 0;
+    for (int r = 0; r < count; ++r) {
+        SweepRes x;
+        int rpg = 8, pitch = 64;
+        sweep_shape(elem_bytes, (int)n[r], &rpg, &pitch);
+        x.n = (int)n[r];
+        x.pad = 0;
+        // a lane group holds at least as many lanes as rows (lane q of a
+        // group finishes row q): the pitch holds at least rpg 16-byte vectors
+        x.ld = (std::max<int64_t>(n[r], rpg * vn) + pitch - 1) / pitch * pitch;
+        x.woff = woff;
+        x.soff = soff;
+        x.winoff = L.win_elems;
+        x.noff = L.nodes;
+        L.res.push_back(x);
+        // every reservoir starts on a 256-byte boundary, so that a short row
+        // pitch of one reservoir does not misalign the cache lines of every
+        // reservoir after it
+        woff = (woff + n[r] * x.ld + align - 1) / align * align;
+        soff = (soff + 3 * x.ld + align - 1) / align * align;
+        L.win_elems += n[r] * n_in;
+        L.nodes += n[r];
+        // wave tasks in reservoir order (a largest-first order was measured
+        // slower: the small tasks then form the tail); a task covers rpg rows
+        // per lane group times the groups in a wave
+        const int rows = rpg * (64 / group_lanes(x.ld, (int)vn));
+        for (int row = 0; row < x.n; row += rows) L.tasks.push_back({x.woff, x.soff, (int)x.ld, x.n, r, row, rpg, 0});
+    }
+    L.w_elems = woff;
+    L.s_elems = soff;
+    return L;
+}
+
+template <typename T>
+hipError_t run_sweep(const SweepDev<T>& d, const RunSpec& r, hipStream_t capture, int graph_samples,
+                     hipGraph_t* graph, hipGraphExec_t* exec) {
+    hipLaunchKernelGGL(k_sweep_set, dim3(1), dim3(64), 0, r.stream, d.sample, 0);
+    int done = 0;
+    if (capture && graph_samples > 0 && r.samples >= graph_samples) {
+        hipError_t e = hipStreamBeginCapture(capture, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) return e;
+        issue<T>(d, r, graph_samples, capture);
+        e = hipStreamEndCapture(capture, graph);
+        if (e != hipSuccess) return e;
+        e = hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return e;
+        for (; done + graph_samples <= r.samples; done += graph_samples) {
+            e = hipGraphLaunch(*exec, r.stream);
+            if (e != hipSuccess) return e;
+        }
+    }
+    issue<T>(d, r, r.samples - done, r.stream);
     return hipGetLastError();
 }
 
-template hipError_t run_sweep<double>(const SweepDev<double>&, const RunSpec&);
-template hipError_t run_sweep<float>(const SweepDev<float>&, const RunSpec&);
+template hipError_t run_sweep<double>(const SweepDev<double>&, const RunSpec&, hipStream_t, int, hipGraph_t*,
+                                      hipGraphExec_t*);
+template hipError_t run_sweep<float>(const SweepDev<float>&, const RunSpec&, hipStream_t, int, hipGraph_t*,
+                                     hipGraphExec_t*);
 
 }  // namespace sto

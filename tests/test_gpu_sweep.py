@@ -131,3 +131,59 @@ def test_sweep256_largest_f64_match_oracle(stx):
         worst = max(worst, float(np.max(np.abs(rec - rec_o))))
     say("  max diff", worst)
     assert worst <= F64_TOL
+
+
+def test_sweep_graph_replay_equals_direct_launches(stx, monkeypatch):
+    """The stage launches of a few samples captured into a HIP graph and
+    replayed (the default) give the bits of the same launches issued one by
+    one: runs of 11 samples with 2-sample graphs (5 replays and one sample
+    issued directly), repeated three times with other sweep work and
+    synchronisations between them, each against the direct run; and the
+    FP64 records against the oracle."""
+    res = small_sweep([33, 70, 129, 300], seed=12)
+    u = np.random.default_rng(13).uniform(-1, 1, (11, 1))
+    for r in res:
+        r["prm"] = lib_params(oracle_prm(r, 4), dtype="f64")
+    monkeypatch.setenv("STO_SWEEP_GRAPH", "0")
+    with stx.Sweep(res) as sw:
+        direct = sw.run(u)
+    monkeypatch.setenv("STO_SWEEP_GRAPH", "1")
+    monkeypatch.setenv("STO_SWEEP_GRAPH_SAMPLES", "2")
+    other = small_sweep([50, 90], seed=14)
+    for r in other:
+        r["prm"] = lib_params(oracle_prm(r, 4), dtype="f64")
+    for rep in range(3):
+        say("sweep graph replay", rep)
+        with stx.Sweep(res) as sw:
+            got = sw.run(u)
+        assert all(np.array_equal(a, b) for a, b in zip(got, direct)), rep
+        with stx.Sweep(other) as sw2:          # other work between the replays
+            sw2.run(u[:3])
+    for r, rec in zip(res, direct):
+        rec_o, _ = sto.run(r["W"], r["w_in"], r["m0"], u, oracle_prm(r, 4))
+        assert float(np.max(np.abs(rec - rec_o))) <= F64_TOL
+
+
+@pytest.mark.parametrize("rows,pitch", [(2, 4), (4, 16), (8, 64), (2, 2), (8, 2), (8, 8), (4, 4)])
+def test_sweep_shapes_match_oracle(stx, rows, pitch, monkeypatch):
+    """Every rows-per-group and row pitch the tuner may choose gives the
+    oracle's trajectory (FP64, bitwise-level bar; FP32 pitch 2 is rounded up
+    to the 16-byte minimum)."""
+    monkeypatch.setenv("STO_SWEEP_ROWS", str(rows))
+    monkeypatch.setenv("STO_SWEEP_PITCH", str(pitch))
+    # sizes of a few nodes: a short pitch then holds fewer vectors than a
+    # group has rows, and the pitch is widened to keep one lane per row
+    res = small_sweep([1, 2, 3, 5, 7, 9, 33, 64, 65, 130, 257], seed=15)
+    u = np.random.default_rng(16).uniform(-1, 1, (3, 1))
+    for dtype in ("f64", "f32"):
+        sub = 20 if dtype == "f64" else 1
+        for r in res:
+            r["prm"] = lib_params(oracle_prm(r, sub), dtype=dtype)
+        say("sweep shape", rows, pitch, dtype)
+        with stx.Sweep(res) as sw:
+            recs = sw.run(u)
+        f32 = (lambda x: np.asarray(x, dtype=np.float32).astype(np.float64)) if dtype == "f32" else (lambda x: x)
+        worst = max(float(np.max(np.abs(rec - sto.run(f32(r["W"]), f32(r["w_in"]), f32(r["m0"]), u,
+                                                      oracle_prm(r, sub))[0])))
+                    for r, rec in zip(res, recs))
+        assert worst <= (F64_TOL if dtype == "f64" else F32_TOL), (dtype, worst)
