@@ -134,15 +134,19 @@ __device__ bool gather_multi(const float* xb, int64_t ld, int64_t cstride, int n
 // write the stage trace of the adjoint (tr); sample0 offsets the sample
 // index reported on a non-finite state.  RT: 16-node row tiles per
 // workgroup (1 or 2), which share the gathered columns.
-// With a phase buffer, thread 0 of every workgroup stamps the device's
-// constant-rate clock at four points of each of the first phase_stages
-// stages (start, columns gathered, own pairs computed, published).
+// PHASE (an instance of its own, so that the others carry no trace code):
+// thread 0 of every workgroup stamps the device's constant-rate clock at
+// four points of each of the first phase_stages stages (start, columns
+// gathered, own pairs computed, published).
+template <bool PHASE>
 __device__ __forceinline__ void multi_stamp(unsigned long long* phase, int phase_stages, int sigma, int point) {
-    if (phase && sigma < phase_stages && threadIdx.x == 0)
-        phase[(((size_t)blockIdx.y * gridDim.x + blockIdx.x) * phase_stages + sigma) * 4 + point] = wall_clock64();
+    if constexpr (PHASE) {
+        if (sigma < phase_stages && threadIdx.x == 0)
+            phase[(((size_t)blockIdx.y * gridDim.x + blockIdx.x) * phase_stages + sigma) * 4 + point] = wall_clock64();
+    }
 }
 
-template <int KREG, bool XYZ, bool TRACE, int RT>
+template <int KREG, bool XYZ, bool TRACE, int RT, bool PHASE>
 __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float> k, const double* __restrict__ u,
                                                   float* __restrict__ states, int streams, int samples,
                                                   int substeps, int renorm, int sample0, MultiTrace tr,
@@ -205,11 +209,11 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
                 float* xout = xbuf + (int64_t)((sigma + 1) % 3) * bstride;
                 float* xold = xbuf + (int64_t)((sigma + 2) % 3) * bstride;
                 __syncthreads();
-                multi_stamp(phase, phase_stages, sigma, 0);
+                multi_stamp<PHASE>(phase, phase_stages, sigma, 0);
                 if (!gather_multi<C, SPW, KI>(xin, ld, cstride, n, s0, ns, xs, abort_flag)) ok_lds = 0;
                 __syncthreads();
                 if (ok_lds == 0) return;
-                multi_stamp(phase, phase_stages, sigma, 1);
+                multi_stamp<PHASE>(phase, phase_stages, sigma, 1);
                 // re-arm this pair's entries of the buffer two stages ahead now;
                 // the stores complete while the stage is computed
                 if (mine) {
@@ -291,7 +295,7 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
                 sx = nx;
                 sy = ny;
                 sz = nz;
-                multi_stamp(phase, phase_stages, sigma, 2);
+                multi_stamp<PHASE>(phase, phase_stages, sigma, 2);
                 if (mine) {
                     const int64_t o = (int64_t)strm * ld + node;
                     __hip_atomic_store(xout + o, nx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -300,7 +304,7 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
                         __hip_atomic_store(xout + 2 * cstride + o, nz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
-                multi_stamp(phase, phase_stages, sigma, 3);
+                multi_stamp<PHASE>(phase, phase_stages, sigma, 3);
             }
         }
         if (mine) {
@@ -524,13 +528,18 @@ const void* multi_rev_kernel(int xyz, int rt) {
                : reinterpret_cast<const void*>(&k_multi_rev<KREG, false, 1>);
 }
 
+// trace: 0 forward, 1 forward with the adjoint's trace, 3 forward with the
+// phase stamps.
 template <int KREG, int RT>
 const void* multi_kernel(int xyz, int trace) {
-    if (trace)
-        return xyz ? reinterpret_cast<const void*>(&k_multi<KREG, true, true, RT>)
-                   : reinterpret_cast<const void*>(&k_multi<KREG, false, true, RT>);
-    return xyz ? reinterpret_cast<const void*>(&k_multi<KREG, true, false, RT>)
-               : reinterpret_cast<const void*>(&k_multi<KREG, false, false, RT>);
+    if (trace == 1)
+        return xyz ? reinterpret_cast<const void*>(&k_multi<KREG, true, true, RT, false>)
+                   : reinterpret_cast<const void*>(&k_multi<KREG, false, true, RT, false>);
+    if (trace == 3)
+        return xyz ? reinterpret_cast<const void*>(&k_multi<KREG, true, false, RT, true>)
+                   : reinterpret_cast<const void*>(&k_multi<KREG, false, false, RT, true>);
+    return xyz ? reinterpret_cast<const void*>(&k_multi<KREG, true, false, RT, false>)
+               : reinterpret_cast<const void*>(&k_multi<KREG, false, false, RT, false>);
 }
 
 template <int KREG>
@@ -555,7 +564,8 @@ namespace {
 
 // The kernel instance for n nodes and rt row tiles, with its dynamic LDS
 // limit raised to what it needs; nullptr when n is out of range.
-// trace: 0 forward, 1 forward with the adjoint's trace, 2 reversed stages.
+// trace: 0 forward, 1 forward with the adjoint's trace, 2 reversed stages,
+// 3 forward with the phase stamps.
 const void* multi_fn(int n, int xyz, int trace, int rt) {
     const void* fn = nullptr;
     switch (kreg_for(n)) {
@@ -627,8 +637,17 @@ bool fits(int n, int streams, int xyz, int trace, Shape* sh) {
 
 hipError_t launch_multi(const DevState<float>& d, const Coef<float>& k, const RunSpec& r, int streams, int sample0,
                         const MultiTrace& tr) {
+    // the instance with the phase stamps when a trace was armed for its grid
     Shape sh{};
     if (!fits(d.n, streams, r.xyz, tr.xt != nullptr, &sh)) return hipErrorInvalidValue;
+    bool stamp = false;
+    if (!tr.xt && r.trace) {
+        Shape ph{};
+        if (fits(d.n, streams, r.xyz, 3, &ph) && r.trace_groups >= ph.gx * ph.gy) {
+            sh = ph;
+            stamp = true;
+        }
+    }
     hipError_t e = hipMemsetAsync(d.sync, 0, 256, r.stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_multi_prologue, dim3(64), dim3(256), 0, r.stream, (const float*)d.m, d.xchg, streams, d.ld,
@@ -641,9 +660,8 @@ hipError_t launch_multi(const DevState<float>& d, const Coef<float>& k, const Ru
     float* states = static_cast<float*>(r.states);
     int st = streams, samples = r.samples, substeps = r.substeps, renorm = r.renorm, s0 = sample0;
     MultiTrace t = tr;
-    // the phase trace, when it was armed for at least this grid
-    unsigned long long* phase = r.trace && r.trace_groups >= sh.gx * sh.gy ? r.trace : nullptr;
-    int phase_stages = phase ? r.trace_stages : 0;
+    unsigned long long* phase = stamp ? r.trace : nullptr;
+    int phase_stages = stamp ? r.trace_stages : 0;
     void* args[] = {&dd, &kk, &u, &states, &st, &samples, &substeps, &renorm, &s0, &t, &phase, &phase_stages};
     e = hipLaunchCooperativeKernel(sh.fn, dim3(sh.gx, sh.gy), dim3(kBlock), args, (unsigned)sh.lds, r.stream);
     if (e != hipSuccess) return e;

@@ -258,3 +258,38 @@ def test_batch_continuation_and_agreement(stx, coupling):
         multi = r.run(u)
     say("batch vs multi", float(np.max(np.abs(multi - whole))))
     assert np.max(np.abs(multi - whole)) <= 1e-5
+
+
+@pytest.mark.parametrize("S,n,coupling,path", [(64, 512, "x", "multi"), (8, 200, "xyz", "multi"), (1, 1000, "x", "resident")])
+def test_phase_trace_leaves_results_unchanged(stx, S, n, coupling, path):
+    """A run with the phase trace armed (the stamping instance of the
+    persistent kernel) writes the same records as a plain run, bitwise, and
+    every stamped stage has start <= gathered <= computed <= published."""
+    import torch
+    say("phase trace", S, n, coupling, path)
+    rng = np.random.default_rng(21)
+    w = rng.standard_normal((n, n)) / np.sqrt(n)
+    w_in = rng.uniform(-1, 1, (n, 1))
+    v = rng.standard_normal((S, n, 3)) * 0.3
+    v[..., 2] += 1.0
+    m0 = v / np.linalg.norm(v, axis=-1, keepdims=True)
+    samples, stages = 6, 12
+    u = torch.from_numpy(rng.uniform(-1, 1, (samples, S, 1))).cuda()
+    prm = lib_params(oracle_params(a_cp=0.3, a_in=0.7, substeps=2, coupling=coupling), "f32", path)
+    with stx.Reservoir(w, w_in, m0 if S > 1 else m0[0], prm, streams=S) as r:
+        assert r.path == path
+        plain = torch.empty((samples, S, n, 3) if S > 1 else (samples, n, 3), dtype=torch.float32, device="cuda")
+        r.run_device(u.reshape(samples, -1).contiguous(), plain)
+        r.set_state(m0 if S > 1 else m0[0])
+        r.trace_phases(stages)
+        traced = torch.empty_like(plain)
+        r.run_device(u.reshape(samples, -1).contiguous(), traced)
+        torch.cuda.synchronize()
+        st, khz = r.phase_times()
+        r.trace_phases(0)
+    assert torch.equal(plain, traced)
+    assert khz > 0 and st.shape[1] == stages and st.shape[2] == 4
+    stamped = np.all(st > 0, axis=2)
+    assert stamped.any()
+    t = st[stamped].astype(np.int64)
+    assert np.all(np.diff(t, axis=1) >= 0)
