@@ -207,7 +207,8 @@ def reservoir_create_streams(n: int, n_in: int, streams: int, prm: sto_params, W
     return h
 
 
-def _vp(ptr):
+def _addr(ptr: Optional[int]):
+    """A device address (an int) as a void pointer; None or 0 is NULL."""
     return ctypes.c_void_p(ptr) if ptr else None
 
 
@@ -215,15 +216,15 @@ def reservoir_create_device(n: int, n_in: int, streams: int, prm: sto_params, W_
                             m0_ptr: int, stream_ptr: Optional[int]) -> ctypes.c_void_p:
     """Device pointers of doubles: W (n, n), w_in (n, n_in), m0 (streams, n, 3)."""
     h = ctypes.c_void_p()
-    _check(_lib.reservoir_create_device(n, n_in, streams, ctypes.byref(prm), _vp(W_ptr), _vp(w_in_ptr), _vp(m0_ptr),
-                                        _vp(stream_ptr), ctypes.byref(h)))
+    _check(_lib.reservoir_create_device(n, n_in, streams, ctypes.byref(prm), _addr(W_ptr), _addr(w_in_ptr), _addr(m0_ptr),
+                                        _addr(stream_ptr), ctypes.byref(h)))
     return h
 
 
 def reservoir_load_device(h, W_ptr: Optional[int], w_in_ptr: Optional[int], m_ptr: Optional[int],
                           prm: Optional[sto_params], stream_ptr: Optional[int]):
-    _check(_lib.reservoir_load_device(h, _vp(W_ptr), _vp(w_in_ptr), _vp(m_ptr),
-                                      ctypes.byref(prm) if prm is not None else None, _vp(stream_ptr)))
+    _check(_lib.reservoir_load_device(h, _addr(W_ptr), _addr(w_in_ptr), _addr(m_ptr),
+                                      ctypes.byref(prm) if prm is not None else None, _addr(stream_ptr)))
 
 
 def reservoir_streams(h) -> int:

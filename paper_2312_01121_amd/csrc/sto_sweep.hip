@@ -99,8 +99,10 @@ __device__ __forceinline__ void sweep_task(const SweepDev<T>& d, const SweepTask
     AT av[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) av[r] = A::zero();
+    // only the vectors that start below n: the row padding is zero, and
+    // leaving it unread saves its HBM traffic
 #pragma unroll U
-    for (int64_t c = (int64_t)gl * VN; c < ld; c += (int64_t)G * VN) {
+    for (int64_t c = (int64_t)gl * VN; c < n; c += (int64_t)G * VN) {
         const V xv = *reinterpret_cast<const V*>(xin + c);
         V wv[R];
 #pragma unroll
@@ -153,6 +155,7 @@ __global__ void __launch_bounds__(256) k_sweep_stage(SweepDev<T> d, const double
     const int task = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (task >= d.tasks) return;   // wave-uniform
     const SweepTask tk = d.task[task];
+    if (tk.n == 0) return;   // padding of the XCD-aware task order (wave-uniform)
     const int sample = *d.sample;
     switch (tk.rpg) {
         case 2: sweep_task<T, 2, U>(d, tk, u, sample, stage, cur, record, renorm); break;
@@ -255,14 +258,60 @@ SweepLayout sweep_layout(int elem_bytes, int count, const int64_t* n, int n_in) 
         soff = (soff + 3 * x.ld + align - 1) / align * align;
         L.win_elems += n[r] * n_in;
         L.nodes += n[r];
-        // wave tasks in reservoir order (a largest-first order was measured
-        // slower: the small tasks then form the tail); a task covers rpg rows
-        // per lane group times the groups in a wave
-        const int rows = rpg * (64 / group_lanes(x.ld, (int)vn));
-        for (int row = 0; row < x.n; row += rows) L.tasks.push_back({x.woff, x.soff, (int)x.ld, x.n, r, row, rpg, 0});
     }
     L.w_elems = woff;
     L.s_elems = soff;
+
+    // Wave tasks: a task covers rpg rows per lane group times the groups in
+    // a wave.  The workgroups of a launch go to the chip's XCDs in turn
+    // (workgroup b to XCD b mod 8), each XCD with its own L2.  With the
+    // XCD-aware order every reservoir is given whole to one XCD, so its
+    // stage input and state are fetched into one L2 only: reservoirs are
+    // dealt to the XCDs largest first, each to the least loaded (bytes of W),
+    // and workgroup k*8 + x runs the k-th four tasks of XCD x (empty tasks
+    // pad the shorter lists).  Within an XCD, and in the plain order, tasks
+    // follow the reservoir order (largest first was measured slower: the
+    // small tasks then form the tail).
+    std::vector<std::vector<SweepTask>> per(count);
+    for (int r = 0; r < count; ++r) {
+        const SweepRes& x = L.res[r];
+        int rpg = 8, pitch = 64;
+        sweep_shape(elem_bytes, x.n, &rpg, &pitch);
+        const int rows = rpg * (64 / group_lanes(x.ld, (int)vn));
+        for (int row = 0; row < x.n; row += rows) per[r].push_back({x.woff, x.soff, (int)x.ld, x.n, r, row, rpg, 0});
+    }
+    const char* xcd_env = getenv("STO_SWEEP_XCD");
+    const bool xcd = !(xcd_env && *xcd_env == '0');
+    if (!xcd) {
+        for (int r = 0; r < count; ++r) L.tasks.insert(L.tasks.end(), per[r].begin(), per[r].end());
+        return L;
+    }
+    constexpr int kXcds = 8, kTasksPerBlock = 4;
+    std::vector<int> order(count);
+    for (int r = 0; r < count; ++r) order[r] = r;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return L.res[a].n * L.res[a].ld > L.res[b].n * L.res[b].ld; });
+    std::vector<std::vector<int>> bin(kXcds);
+    std::vector<int64_t> load(kXcds, 0);
+    for (int r : order) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        bin[x].push_back(r);
+        load[x] += L.res[r].n * L.res[r].ld;
+    }
+    std::vector<std::vector<SweepTask>> list(kXcds);
+    size_t blocks = 0;
+    for (int x = 0; x < kXcds; ++x) {
+        std::sort(bin[x].begin(), bin[x].end());
+        for (int r : bin[x]) list[x].insert(list[x].end(), per[r].begin(), per[r].end());
+        blocks = std::max(blocks, (list[x].size() + kTasksPerBlock - 1) / kTasksPerBlock);
+    }
+    const SweepTask empty{0, 0, 0, 0, 0, 0, 8, 0};
+    L.tasks.assign(blocks * kXcds * kTasksPerBlock, empty);
+    for (int x = 0; x < kXcds; ++x)
+        for (size_t i = 0; i < list[x].size(); ++i) {
+            const size_t k = i / kTasksPerBlock, w = i % kTasksPerBlock;
+            L.tasks[(k * kXcds + x) * kTasksPerBlock + w] = list[x][i];
+        }
     return L;
 }
 

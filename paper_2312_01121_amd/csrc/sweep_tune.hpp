@@ -16,12 +16,11 @@ struct SweepTuneEntry {
 };
 
 constexpr SweepTuneEntry kSweepTune[] = {
-    {4, 192, 8, 16},
     {4, 1073741824, 8, 32},
     {8, 1073741824, 8, 64},
 };
 
 // Measured (candidate table n_max:rows:pitch,...): us per RK4 step of the sweep
-// {"1073741824:4:64": 400.84, "1073741824:8:16": 369.96, "1073741824:8:32": 362.14, "1073741824:8:64": 367.03, "1792:8:32,1073741824:4:32": 363.92, "192:8:16,1073741824:8:32": 361.89, "192:8:16,1073741824:8:64": 365.33, "48:8:16,1073741824:8:64": 368.75}
+// {"1073741824:4:64": 364.68, "1073741824:8:16": 348.13, "1073741824:8:32": 338.91, "1073741824:8:64": 341.44, "1792:8:32,1073741824:4:32": 341.28, "192:8:16,1073741824:8:32": 338.91, "192:8:16,1073741824:8:64": 341.65, "48:8:16,1073741824:8:64": 341.53}
 
 }  // namespace sto

@@ -286,3 +286,33 @@ def test_fake_library_catches_an_undersized_output(stx, monkeypatch):
     registry[buf.ctypes.data] = buf.nbytes
     with pytest.raises(AssertionError, match="grad_m0"):
         fake._need(stx._dptr(buf), 2 * 4 * 3, "grad_m0", write=True)
+
+
+def test_device_load_bindings_pass_addresses(stx, monkeypatch):
+    """reservoir_create_device / reservoir_load_device hand the device
+    addresses through unchanged, NULL for an absent array or parameter set."""
+    seen = []
+
+    class Fake:
+        def reservoir_create_device(self, n, n_in, S, prm, W, w_in, m0, stream, hp):
+            seen.append(("create", n, n_in, S, prm._obj.substeps, W.value, w_in.value, m0.value,
+                         stream.value if stream is not None else None))
+            hp._obj.value = 7
+            return 0
+
+        def reservoir_load_device(self, h, W, w_in, m, prm, stream):
+            val = lambda p: p.value if p is not None else None  # noqa: E731
+            seen.append(("load", h.value, val(W), val(w_in), val(m), prm._obj.a_cp if prm is not None else None,
+                         val(stream)))
+            return 0
+
+    monkeypatch.setattr(stx, "_lib", Fake())
+    h = stx.reservoir_create_device(5, 2, 3, _ok_params(stx, substeps=4), 0x1000, 0x2000, 0x3000, 0x4000)
+    assert h.value == 7
+    stx.reservoir_load_device(h, 0x5000, None, 0x6000, None, None)
+    q = _ok_params(stx, substeps=4)
+    q.a_cp = 0.25
+    stx.reservoir_load_device(h, None, 0x7000, None, q, 0x8000)
+    assert seen == [("create", 5, 2, 3, 4, 0x1000, 0x2000, 0x3000, 0x4000),
+                    ("load", 7, 0x5000, None, 0x6000, None, None),
+                    ("load", 7, None, 0x7000, None, 0.25, 0x8000)]
