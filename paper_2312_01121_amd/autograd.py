@@ -26,6 +26,7 @@ W through host memory; only the four scalars are read as host numbers.
 
 from __future__ import annotations
 
+import atexit
 import ctypes
 import weakref
 from collections import OrderedDict
@@ -72,6 +73,11 @@ def release():
     while _HANDLES:
         _, held = _HANDLES.popitem()
         held.res.close()
+
+
+# kept handles are freed while the HIP runtime is still up, not by the
+# garbage collector at interpreter teardown
+atexit.register(release)
 
 
 def _dev64(t, dev):
