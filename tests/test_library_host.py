@@ -316,3 +316,27 @@ def test_device_load_bindings_pass_addresses(stx, monkeypatch):
     assert seen == [("create", 5, 2, 3, 4, 0x1000, 0x2000, 0x3000, 0x4000),
                     ("load", 7, 0x5000, None, 0x6000, None, None),
                     ("load", 7, None, 0x7000, None, 0.25, 0x8000)]
+
+
+def test_device_entry_points_reject_bad_arguments(stx):
+    """The checks that precede any device work: NULL handle, output or array
+    pointers, sizes and constants out of range.  The addresses passed are
+    never dereferenced because every case fails its checks first."""
+    lib = stx.lib()
+    h = ctypes.c_void_p()
+    addr = ctypes.c_void_p(0x1000)
+    prm = _ok_params(stx)
+
+    def create(n=4, n_in=1, S=1, pr=prm, W=addr, w_in=addr, m0=addr, out=True):
+        return lib.reservoir_create_device(n, n_in, S, ctypes.byref(pr), W, w_in, m0, None,
+                                           ctypes.byref(h) if out else None)
+
+    assert create(W=None) == stx.STO_E_INVALID
+    assert create(m0=None) == stx.STO_E_INVALID
+    assert create(out=False) == stx.STO_E_INVALID
+    assert create(n=0) == stx.STO_E_INVALID
+    assert create(n_in=0) == stx.STO_E_INVALID
+    assert create(S=0) == stx.STO_E_INVALID
+    assert create(pr=_ok_params(stx, dt=-1.0)) == stx.STO_E_INVALID
+    assert lib.reservoir_load_device(None, addr, None, None, None, None) == stx.STO_E_INVALID
+    assert "handle" in stx.sto_last_error()
