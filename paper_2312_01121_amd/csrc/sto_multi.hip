@@ -134,6 +134,33 @@ __device__ bool gather_multi(const float* xb, int64_t ld, int64_t cstride, int n
 // write the stage trace of the adjoint (tr); sample0 offsets the sample
 // index reported on a non-finite state.  RT: 16-node row tiles per
 // workgroup (1 or 2), which share the gathered columns.
+// One wave's partial product tile: acc[rt] += sum over t < KREG of the
+// 16 x 4 slice A[rt][t] of the row tile times the 4 x 16 slice of the
+// gathered columns (LDS, row stride kXP) at this wave's nodes 4t .. 4t + 3.
+// The LDS reads of a group of up to GROUP steps are issued before its
+// products, so one read latency covers the group.  Steps past the wave's share of the
+// contraction have zero A and add nothing; their reads are clamped into the
+// array.
+template <int KREG, int RT, int GROUP>
+__device__ __forceinline__ void wave_tile_product(const float (&areg)[RT][KREG], const float* xs, int node0, int kp,
+                                                  int lane, f4 (&acc)[RT]) {
+    constexpr int G = KREG < GROUP ? KREG : GROUP;
+#pragma unroll
+    for (int t0 = 0; t0 < KREG; t0 += G) {
+        float b[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int kk = min(node0 + 4 * (t0 + g) + (lane >> 4), kp - 1);
+            b[g] = xs[kk * kXP + (lane & 15)];
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+                acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[rt][t0 + g], b[g], acc[rt], 0, 0, 0);
+    }
+}
+
 // PHASE (an instance of its own, so that the others carry no trace code):
 // thread 0 of every workgroup stamps the device's constant-rate clock at
 // four points of each of the first phase_stages stages (start, columns
@@ -227,16 +254,7 @@ __global__ void __launch_bounds__(kBlock) k_multi(DevState<float> d, Coef<float>
                 f4 acc[RT];
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt) acc[rt] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int t = 0; t < KREG; ++t) {
-                    if (t < steps) {
-                        const int kk = wave * kq + 4 * t + (lane >> 4);
-                        const float b = xs[kk * kXP + (lane & 15)];
-#pragma unroll
-                        for (int rt = 0; rt < RT; ++rt)
-                            acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[rt][t], b, acc[rt], 0, 0, 0);
-                    }
-                }
+                wave_tile_product<KREG, RT, 8>(areg, xs, wave * kq, kp, lane, acc);
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -436,15 +454,21 @@ __global__ void __launch_bounds__(kBlock) k_multi_rev(AdjDev<float> d, Coef<floa
             f4 acc[RT];
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) acc[rt] = f4{0.f, 0.f, 0.f, 0.f};
+            if constexpr (KREG >= 32) {
+                // the reverse holds more registers: at KREG = 32 grouped reads
+                // spill, so each step reads its slice just before its product
 #pragma unroll
-            for (int t = 0; t < KREG; ++t) {
-                if (t < steps) {
-                    const int kr = wave * kq + 4 * t + (lane >> 4);
-                    const float b = xs[kr * kXP + (lane & 15)];
+                for (int t = 0; t < KREG; ++t) {
+                    if (t < steps) {
+                        const int kr = wave * kq + 4 * t + (lane >> 4);
+                        const float b = xs[kr * kXP + (lane & 15)];
 #pragma unroll
-                    for (int rt = 0; rt < RT; ++rt)
-                        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[rt][t], b, acc[rt], 0, 0, 0);
+                        for (int rt = 0; rt < RT; ++rt)
+                            acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[rt][t], b, acc[rt], 0, 0, 0);
+                    }
                 }
+            } else {
+                wave_tile_product<KREG, RT, 8>(areg, xs, wave * kq, kp, lane, acc);
             }
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
