@@ -147,6 +147,23 @@ def run_workload(stx, torch, name: str, dtype: str, steps: int, warmup: int, arr
     nmse = evs[-1][3]
     r.close()
     wall_s = (t1 - t0) / steps
+    # a path that runs the whole series in one launch, against one launch per
+    # RK4 stage (the stream kernel) on the same inputs, outside the timed steps
+    stream_us = None
+    if path != "stream":
+        k_samples = min(wl.samples, 1000)
+        prm_s = stx.make_params(**params.table1(a_cp=wl.a_cp, a_in=wl.a_in, dt=wl.dt, substeps=wl.substeps),
+                                dtype=dtype, path="stream")
+        with stx.Reservoir(a["W"], a["w_in"], a["m0"], prm_s) as rs:
+            u_k = u_d[:k_samples].contiguous()
+            rs.run_device(u_k[:1].contiguous(), states[:1], stream)
+            rs.set_state(a["m0"])
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            rs.run_device(u_k, states[:k_samples], stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            stream_us = e0.elapsed_time(e1) * 1e3 / (k_samples * wl.substeps)
     node_steps = wl.n * wl.steps
     launches = 4 * wl.steps if path == "stream" else 1
     kernel = {"stream": "k_stage", "resident": "k_resident", "small": "k_small"}[path]
@@ -163,6 +180,8 @@ def run_workload(stx, torch, name: str, dtype: str, steps: int, warmup: int, arr
         "kernel": kernel, "launches_per_run": launches, "avg_launch_us": launch_s * 1e6,
         "algo_bytes_per_launch": algo_bytes, "achieved_gbs": achieved,
         "hbm_frac": achieved / HBM_PEAK_GBS,
+        "stream_path_us_per_rk4_step": stream_us,
+        "speedup_vs_stream_path": (stream_us / (run_ms * 1e3 / wl.steps)) if stream_us else None,
     }
 
 
