@@ -881,6 +881,12 @@ def main():
     if not args.no_cpu:
         log("cpu baseline")
         cpu = cpu_baseline(args.workload, arrays)
+        # the GPU's rate over the oracle's, on each workload both ran
+        cpu["gpu_over_oracle"] = main_res["value"] / cpu["value"]
+        gpu_rate = {(a["workload"], a["dtype"]): a["value"] for a in also if "workload" in a}
+        for o in cpu.get("other_workloads", []):
+            g = gpu_rate.get((o["workload"], "f64"))
+            o["gpu_over_oracle"] = g / o["value"] if g else None
         log(json.dumps(cpu))
 
     traffic = stored_traffic(main_res["kernel"], args.workload, args.dtype)
