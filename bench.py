@@ -850,7 +850,7 @@ def main():
     also = []
     if not args.no_also:
         plan = [(args.workload, "f64" if args.dtype == "f32" else "f32", 1, 1),
-                ("sto1k", "f32", 2, 1), ("sto1k", "f64", 2, 1), ("sto16", "f64", 3, 1)]
+                ("sto1k", "f32", 5, 1), ("sto1k", "f64", 5, 1), ("sto16", "f64", 5, 1)]
         for name, dt, k, w in plan:
             log("also", name, dt)
             res = run_workload(stx, torch, name, dt, k, w, arrays if name == args.workload else None)
