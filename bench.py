@@ -257,12 +257,12 @@ def run_adjoint_workload(stx, torch, name: str, dtype: str, samples: int, steps:
     }
 
 
-def run_streams_workload(stx, torch, name: str, steps: int, warmup: int, coupling: str = "x"):
-    """S input streams share one reservoir (FP32 MFMA coupling: the MULTI
-    path for x coupling, the per-stage BATCH path for all three components);
-    one step is the run of every stream plus one readout per stream.  The
-    same runs through the plain single-reservoir path, one stream after
-    another over the whole series, are timed beside it."""
+def run_streams_workload(stx, torch, name: str, steps: int, warmup: int, coupling: str = "x", plain: bool = True):
+    """S input streams share one reservoir (FP32 MFMA coupling on the
+    multi-stream path, either coupling); one step is the run of every stream
+    plus one readout per stream.  The same runs through the plain
+    single-reservoir path, one stream after another over the whole series,
+    are timed beside it (unless plain is False)."""
     from workloads import STREAMS, WORKLOADS, make_stream_arrays
     from paper_2312_01121_amd import params
 
@@ -305,21 +305,23 @@ def run_streams_workload(stx, torch, name: str, steps: int, warmup: int, couplin
     r.close()
     # plain path: every stream through the single-reservoir kernels, one
     # after another, each over the whole series (measured, not scaled)
-    r1 = stx.Reservoir(a["W"], a["w_in"], a["m0"], prm)
-    plain_path = r1.path
-    st1 = torch.empty((wl.samples, wl.n, 3), dtype=torch.float32, device="cuda")
-    u_all = [torch.from_numpy(np.ascontiguousarray(a["u"][:, st])).cuda() for st in range(S)]
-    r1.run_device(u_all[0], st1, stream)                # warm-up
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for st in range(S):
-        r1.set_state(a["m0"])
-        r1.run_device(u_all[st], st1, stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    plain_ms = e0.elapsed_time(e1)
-    r1.close()
+    plain_path, plain_ms = None, None
+    if plain:
+        r1 = stx.Reservoir(a["W"], a["w_in"], a["m0"], prm)
+        plain_path = r1.path
+        st1 = torch.empty((wl.samples, wl.n, 3), dtype=torch.float32, device="cuda")
+        u_all = [torch.from_numpy(np.ascontiguousarray(a["u"][:, st])).cuda() for st in range(S)]
+        r1.run_device(u_all[0], st1, stream)                # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for st in range(S):
+            r1.set_state(a["m0"])
+            r1.run_device(u_all[st], st1, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        plain_ms = e0.elapsed_time(e1)
+        r1.close()
     wall_s = (t1 - t0) / steps
     C = 3 if coupling == "xyz" else 1
     flops = 2.0 * wl.n * wl.n * S * C * 4 * wl.steps
@@ -332,7 +334,7 @@ def run_streams_workload(stx, torch, name: str, steps: int, warmup: int, couplin
         "kernel": "k_multi" if path == "multi" else "k_bfwd", "mfma_tflops": flops / (run_ms * 1e-3) / 1e12,
         "mfma_frac": flops / (run_ms * 1e-3) / 157.3e12,
         "plain_path": plain_path, "plain_run_ms_for_all_streams": plain_ms,
-        "speedup_vs_plain": plain_ms / run_ms,
+        "speedup_vs_plain": plain_ms / run_ms if plain_ms else None,
     }
 
 
@@ -828,7 +830,8 @@ def main():
                     "unit": "GB/s", "frac": res["hbm_frac"], "traffic": stored_traffic("k_sweep_stage", args.workload, "f32")}
             unit_nodes = res["nodes"]
         else:
-            res = run_streams_workload(stx, torch, args.workload, args.steps, args.warmup, coupling=args.coupling)
+            res = run_streams_workload(stx, torch, args.workload, args.steps, args.warmup, coupling=args.coupling,
+                                       plain=not args.no_plain)
             roof = {"bound": "mfma", "kernel": res["kernel"], "achieved": res["mfma_tflops"], "peak": 157.3,
                     "unit": "TFLOP/s", "frac": res["mfma_frac"], "traffic": None}
             unit_nodes = res["n"] * res["streams"]
