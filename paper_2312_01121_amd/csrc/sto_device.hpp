@@ -83,12 +83,59 @@ template <> struct Acc<float> {
     }
 };
 
+// Lane exchange for the butterfly below, without an LDS round trip.  Inside
+// a 16-lane row it is a DPP move: OFF = 1 and 2 are the xor partners (quad
+// permutations); OFF = 4 and 8 are the row's half-mirror and mirror, which
+// reach a lane of the partner group of 4 or 8 lanes (used only where every
+// lane of a group already holds the same value).  OFF = 16 and 32 are the
+// xor partners through gfx950's permlane swaps: swapping a value with itself
+// leaves the partner's value in one of the two results (lanes with bit
+// OFF set take the first).
+template <int OFF>
+__device__ __forceinline__ int lane_partner_i32(int v) {
+    if constexpr (OFF == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (threadIdx.x & 16) ? r[0] : r[1];
+    } else if constexpr (OFF == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (threadIdx.x & 32) ? r[0] : r[1];
+    } else {
+        static_assert(OFF == 1 || OFF == 2 || OFF == 4 || OFF == 8, "lane distance");
+        constexpr int ctrl = OFF == 1 ? 0xB1 : OFF == 2 ? 0x4E : OFF == 4 ? 0x141 : 0x140;
+        return __builtin_amdgcn_update_dpp(0, v, ctrl, 0xF, 0xF, false);
+    }
+}
+template <int OFF>
+__device__ __forceinline__ float lane_partner(float v) {
+    return __builtin_bit_cast(float, lane_partner_i32<OFF>(__builtin_bit_cast(int, v)));
+}
+template <int OFF>
+__device__ __forceinline__ double lane_partner(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned long long lo = (unsigned)lane_partner_i32<OFF>((int)(unsigned)b);
+    const unsigned long long hi = (unsigned)lane_partner_i32<OFF>((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, lo | (hi << 32));
+}
+template <int OFF>
+__device__ __forceinline__ DD lane_partner(DD v) {
+    return DD{lane_partner<OFF>(v.s), lane_partner<OFF>(v.c)};
+}
+
 // Butterfly reduction over groups of `width` consecutive lanes (power of
-// two, <= 64); every lane of the group ends with the group's total.
+// two, <= 64, wave-uniform, groups aligned to their width); every lane of
+// the group ends with the group's total.  Partners at distance 1, 2, 4, 8,
+// 16, 32 in that order: after each step every lane of a group holds the same
+// value (the additions commute bitwise, in double-double too), so the whole
+// wave's total is (r0 + r1) + (r2 + r3) of its four row totals.
 template <typename T>
 __device__ __forceinline__ typename Acc<T>::type group_reduce(typename Acc<T>::type v, int width) {
-    for (int off = width >> 1; off > 0; off >>= 1)
-        v = Acc<T>::add(v, Acc<T>::shfl_xor(v, off, width));
+    using A = Acc<T>;
+    if (width >= 2) v = A::add(v, lane_partner<1>(v));
+    if (width >= 4) v = A::add(v, lane_partner<2>(v));
+    if (width >= 8) v = A::add(v, lane_partner<4>(v));
+    if (width >= 16) v = A::add(v, lane_partner<8>(v));
+    if (width >= 32) v = A::add(v, lane_partner<16>(v));
+    if (width >= 64) v = A::add(v, lane_partner<32>(v));
     return v;
 }
 

@@ -16,10 +16,12 @@ namespace sto {
 // ---------------------------------------------------------------------------
 // SMALL path: the whole trajectory in one workgroup.
 // ---------------------------------------------------------------------------
-template <typename T, bool XYZ>
+// L: lanes per node (a compile-time constant, so that the butterfly of the
+// row sums has no run-time branches).
+template <typename T, bool XYZ, int L>
 __global__ void __launch_bounds__(1024) k_small(DevState<T> d, Coef<T> k, const double* __restrict__ u,
                                                T* __restrict__ states, int samples, int substeps,
-                                               int cur, int renorm, int L) {
+                                               int cur, int renorm) {
     using A = Acc<T>;
     using AT = typename A::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -154,6 +156,31 @@ static int small_lanes(int n) {
     return L;
 }
 
+template <typename T, bool XYZ, int L>
+static hipError_t launch_small(const DevState<T>& d, const Coef<T>& k, const RunSpec& r, int block, size_t lds) {
+    const void* fn = reinterpret_cast<const void*>(&k_small<T, XYZ, L>);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_small<T, XYZ, L>), dim3(1), dim3(block), lds, r.stream, d, k, r.u,
+                       static_cast<T*>(r.states), r.samples, r.substeps, r.cur, r.renorm);
+    return hipGetLastError();
+}
+
+template <typename T, bool XYZ>
+static hipError_t launch_small_l(int L, const DevState<T>& d, const Coef<T>& k, const RunSpec& r, int block,
+                                 size_t lds) {
+    switch (L) {
+        case 1: return launch_small<T, XYZ, 1>(d, k, r, block, lds);
+        case 2: return launch_small<T, XYZ, 2>(d, k, r, block, lds);
+        case 4: return launch_small<T, XYZ, 4>(d, k, r, block, lds);
+        case 8: return launch_small<T, XYZ, 8>(d, k, r, block, lds);
+        case 16: return launch_small<T, XYZ, 16>(d, k, r, block, lds);
+        case 32: return launch_small<T, XYZ, 32>(d, k, r, block, lds);
+        case 64: return launch_small<T, XYZ, 64>(d, k, r, block, lds);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 hipError_t run_small(const DevState<T>& d, const Coef<T>& k, const RunSpec& r) {
     const int n = d.n;
@@ -161,21 +188,7 @@ hipError_t run_small(const DevState<T>& d, const Coef<T>& k, const RunSpec& r) {
     const int block = (L * n + 63) / 64 * 64;
     size_t lds = small_lds_bytes(n, sizeof(T));
     if (L * n > block || block > 1024 || lds > kLdsMax) return hipErrorInvalidValue;
-    hipError_t e;
-    if (r.xyz) {
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small<T, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_small<T, true>), dim3(1), dim3(block), lds, r.stream, d, k, r.u,
-                           static_cast<T*>(r.states), r.samples, r.substeps, r.cur, r.renorm, L);
-    } else {
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small<T, false>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_small<T, false>), dim3(1), dim3(block), lds, r.stream, d, k, r.u,
-                           static_cast<T*>(r.states), r.samples, r.substeps, r.cur, r.renorm, L);
-    }
-    return hipGetLastError();
+    return r.xyz ? launch_small_l<T, true>(L, d, k, r, block, lds) : launch_small_l<T, false>(L, d, k, r, block, lds);
 }
 
 template hipError_t run_small<double>(const DevState<double>&, const Coef<double>&, const RunSpec&);
