@@ -39,7 +39,10 @@ PATH_HEADER = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "
 # per workgroup; 0 rows: ceil(n / CUs))
 PATH_SIZES = {"f64": [16, 32, 48, 64, 80, 96, 128, 140, 192, 256, 384, 512, 768, 1000, 1280, 1536, 2048],
               "f32": [16, 32, 64, 96, 128, 160, 199, 256, 384, 512, 768, 1000, 1280, 1536, 2048, 2560, 3072]}
-RESIDENT_SHAPES = [(4, 0), (8, 0), (16, 0), (4, 4), (8, 8), (16, 16), (8, 16)]
+# (waves, rows per workgroup (0: ceil(n / CUs)), waves per row)
+RESIDENT_SHAPES = [(4, 0, 1), (8, 0, 1), (16, 0, 1), (4, 4, 1), (8, 8, 1), (16, 16, 1), (8, 16, 1),
+                   (4, 0, 2), (8, 0, 2), (16, 0, 2), (8, 4, 2), (8, 8, 2), (16, 8, 2)]
+SPLIT_MIN_N = 256   # rows shorter than this are not worth two waves
 PATH_CODE = {"small": 1, "resident": 2, "stream": 3}
 
 
@@ -117,12 +120,13 @@ constexpr StreamTuneEntry kStreamTune[] = {{
 def time_path(stx, torch, n, dtype, coupling, path, shape, samples, reps=3):
     """Best of ``reps`` runs, microseconds per RK4 step; None if the path or
     shape cannot hold n."""
-    for k in ("STO_RESIDENT_WAVES", "STO_RESIDENT_RPB"):
+    for k in ("STO_RESIDENT_WAVES", "STO_RESIDENT_RPB", "STO_RESIDENT_SPLIT"):
         os.environ.pop(k, None)
     if shape is not None:
         os.environ["STO_RESIDENT_WAVES"] = str(shape[0])
         if shape[1]:
             os.environ["STO_RESIDENT_RPB"] = str(shape[1])
+        os.environ["STO_RESIDENT_SPLIT"] = str(shape[2])
     rng = np.random.default_rng(n)
     w = rng.standard_normal((n, n)) / np.sqrt(n)
     np.fill_diagonal(w, 0.0)
@@ -152,7 +156,7 @@ def time_path(stx, torch, n, dtype, coupling, path, shape, samples, reps=3):
         return None
     finally:
         r.close()
-        for k in ("STO_RESIDENT_WAVES", "STO_RESIDENT_RPB"):
+        for k in ("STO_RESIDENT_WAVES", "STO_RESIDENT_RPB", "STO_RESIDENT_SPLIT"):
             os.environ.pop(k, None)
 
 
@@ -164,8 +168,8 @@ def path_table(best):
         sizes = sorted(per)
         for i, n in enumerate(sizes):
             n_max = (n + sizes[i + 1]) // 2 if i + 1 < len(sizes) else (1 << 30)
-            path, waves, rpb = per[n]
-            lines.append(f"    {{{elem}, {xyz}, {n_max}, {PATH_CODE[path]}, {waves}, {rpb}}},   // {path}")
+            path, waves, rpb, split = per[n]
+            lines.append(f"    {{{elem}, {xyz}, {n_max}, {PATH_CODE[path]}, {waves}, {rpb}, {split}}},   // {path}")
     return "\n".join(lines)
 
 
@@ -188,6 +192,7 @@ struct PathTuneEntry {{
     int path;       // 1 small, 2 resident, 3 stream (sto_path values)
     int waves;      // resident: waves per workgroup (4, 8 or 16)
     int rpb;        // resident: rows per workgroup (0: ceil(n / CUs))
+    int split;      // resident: waves per row (1, or 2: each sums half the columns)
 }};
 
 // Fastest path and shape per size bucket (microseconds per RK4 step measured
@@ -196,7 +201,7 @@ constexpr PathTuneEntry kPathTune[] = {{
 {path_table(best)}
 }};
 
-// Measured (dtype/coupling/n): {{path or resident_wavesxrows: us per RK4 step}}
+// Measured (dtype/coupling/n): {{path or resident_WAVESxROWS[sSPLIT]: us per RK4 step}}
 // {json.dumps(measured, sort_keys=True)}
 
 }}  // namespace sto
@@ -215,15 +220,19 @@ def tune_paths(stx, torch, samples, write):
                 times = {"small": time_path(stx, torch, n, dtype, coupling, "small", None, s),
                          "stream": time_path(stx, torch, n, dtype, coupling, "stream", None, s)}
                 for shape in RESIDENT_SHAPES:
-                    times[f"resident_{shape[0]}x{shape[1]}"] = time_path(stx, torch, n, dtype, coupling,
-                                                                          "resident", shape, s)
+                    if shape[2] > 1 and n < SPLIT_MIN_N:
+                        continue
+                    name = f"resident_{shape[0]}x{shape[1]}" + (f"s{shape[2]}" if shape[2] > 1 else "")
+                    times[name] = time_path(stx, torch, n, dtype, coupling, "resident", shape, s)
                 ok = {k: v for k, v in times.items() if v is not None}
                 key = min(ok, key=ok.get)
                 if key.startswith("resident_"):
-                    waves, rpb = (int(x) for x in key[len("resident_"):].split("x"))
-                    best[(dtype, coupling)][n] = ("resident", waves, rpb)
+                    spec = key[len("resident_"):]
+                    split = int(spec.split("s")[1]) if "s" in spec else 1
+                    waves, rpb = (int(x) for x in spec.split("s")[0].split("x"))
+                    best[(dtype, coupling)][n] = ("resident", waves, rpb, split)
                 else:
-                    best[(dtype, coupling)][n] = (key, 0, 0)
+                    best[(dtype, coupling)][n] = (key, 0, 0, 1)
                 measured[f"{dtype}/{coupling}/{n}"] = {k: round(v, 2) for k, v in ok.items()}
                 print(json.dumps({"dtype": dtype, "coupling": coupling, "n": n, "best": key,
                                   "us": round(ok[key], 2), "all": measured[f"{dtype}/{coupling}/{n}"]}), flush=True)

@@ -881,7 +881,8 @@ sto_status reservoir_trace_phases(sto_reservoir* r, int64_t stages) {
     const int xyz = r->prm.coupling == STO_COUPLE_XYZ;
     int groups = 0;
     if (r->path == STO_PATH_RESIDENT) {
-        if (!sto::resident_shape((int)r->n, (int)r->elem, xyz, &groups, nullptr, nullptr))
+        int split = 1;   // the run's own shape, two waves per row included
+        if (!sto::resident_shape((int)r->n, (int)r->elem, xyz, &groups, nullptr, nullptr, &split))
             return fail(STO_E_UNSUPPORTED, "resident shape does not fit");
     } else if (r->path == STO_PATH_MULTI) {
         int gx = 0, gy = 0;

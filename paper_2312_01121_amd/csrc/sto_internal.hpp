@@ -128,13 +128,14 @@ int small_max_n(int elem_bytes, int xyz);
 // 1 small, 2 resident, 3 stream; 0 if no table entry) and, for the resident
 // path, its measured waves per workgroup and rows per workgroup (0: ceil(n /
 // CUs)).
-int tuned_path(int elem_bytes, int xyz, int n, int* waves, int* rpb);
+int tuned_path(int elem_bytes, int xyz, int n, int* waves, int* rpb, int* split = nullptr);
 // Whether the resident kernel can hold n on this device (W split across
 // co-resident workgroups' LDS); fills the chosen grid size.
 bool resident_fits(int n, int elem_bytes, int xyz, int* grid_out);
 // The resident kernel's launch shape for n (grid, rows per workgroup,
 // threads per workgroup); false if it does not fit.
-bool resident_shape(int n, int elem_bytes, int xyz, int* grid_out, int* rpb_out, int* block_out);
+bool resident_shape(int n, int elem_bytes, int xyz, int* grid_out, int* rpb_out, int* block_out,
+                    int* split_out = nullptr);
 
 // Offset (in ints) of the abort flag in DevState::sync; non-zero after a
 // resident run means a grid barrier timed out.

@@ -37,7 +37,9 @@
 //
 // Launch shape: BLOCK threads (4, 8 or 16 waves) and rows_per_block rows of
 // W per workgroup, at most 4 rows per wave (1 with 16 waves).  The default is 4 waves and
-// ceil(n / CUs) rows.  With a trace buffer, wave 0 of every workgroup
+// ceil(n / CUs) rows.  With SPLIT = 2 two waves share each row, each summing
+// half of its columns; their wave totals meet in LDS, which halves the
+// dependent chain of a row's sum at the cost of one barrier per row.  With a trace buffer, wave 0 of every workgroup
 // stamps the device's constant-rate clock at four points of each of the
 // first trace_stages stages (stage start, gather done, own rows computed,
 // own rows published), for the phase breakdown of the exchange.
@@ -131,7 +133,7 @@ __device__ __forceinline__ void stamp(unsigned long long* trace, int trace_stage
 // its input (xt), its raw coupling sums before a_cp (wx) and, at the last
 // stage of a step, the norm before the projection (pn), in the layout of
 // the adjoint's workspace ([step][stage][component][ld]; pn [step][ld]).
-template <typename T, bool XYZ, int BLOCK, bool TRACE>
+template <typename T, bool XYZ, int BLOCK, bool TRACE, int SPLIT>
 __global__ void __launch_bounds__(BLOCK) k_resident(DevState<T> d, Coef<T> k, const double* __restrict__ u,
                                                     T* __restrict__ states, int samples, int substeps,
                                                     int cur, int renorm, int rows_per_block, int wld,
@@ -153,6 +155,11 @@ __global__ void __launch_bounds__(BLOCK) k_resident(DevState<T> d, Coef<T> k, co
     const int nrows = max(0, min(rows_per_block, n - row_begin));
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    // SPLIT waves share each row: wave grp + p * kGroups sums the p-th share
+    // of the columns; part 0 re-arms, publishes and records
+    constexpr int kGroups = kWaves / SPLIT;
+    const int grp = wave % kGroups;
+    const int part = wave / kGroups;
     T* xbuf = d.xchg;                                           // [3][C][ld]
     int* abort_flag = d.sync + kSyncAbortWord;
     if (threadIdx.x == 0) ok_lds = 1;
@@ -171,7 +178,7 @@ __global__ void __launch_bounds__(BLOCK) k_resident(DevState<T> d, Coef<T> k, co
     T hin[kMaxRowsPerWave];
 #pragma unroll
     for (int q = 0; q < kMaxRowsPerWave; ++q) {
-        const int r = wave + q * kWaves;
+        const int r = grp + q * kGroups;
         const int rr = min(row_begin + min(r, max(nrows - 1, 0)), n - 1);
         mx[q] = sx[q] = d.m[rr];
         my[q] = sy[q] = d.m[ld + rr];
@@ -184,7 +191,7 @@ __global__ void __launch_bounds__(BLOCK) k_resident(DevState<T> d, Coef<T> k, co
     for (int s = 0; s < samples; ++s) {
 #pragma unroll
         for (int q = 0; q < kMaxRowsPerWave; ++q) {
-            const int r = wave + q * kWaves;
+            const int r = grp + q * kGroups;
             if (r < nrows)
                 hin[q] = input_field(k, d.w_in + (int64_t)(row_begin + r) * d.n_in, u + (int64_t)s * d.n_in, d.n_in);
         }
@@ -207,10 +214,10 @@ __global__ void __launch_bounds__(BLOCK) k_resident(DevState<T> d, Coef<T> k, co
                 // stages ahead as soon as the gather is done (every workgroup
                 // finished reading it: the gather saw all outputs of the
                 // previous stage), so the stores complete during the compute
-                if (lane == 0) {
+                if (lane == 0 && part == 0) {
 #pragma unroll
                     for (int q = 0; q < kMaxRowsPerWave; ++q) {
-                        const int r = wave + q * kWaves;
+                        const int r = grp + q * kGroups;
                         if (r >= nrows) break;
                         const int row = row_begin + r;
                         rearm(xold + row);
@@ -220,64 +227,9 @@ __global__ void __launch_bounds__(BLOCK) k_resident(DevState<T> d, Coef<T> k, co
                         }
                     }
                 }
-#pragma unroll
-                for (int q = 0; q < kMaxRowsPerWave; ++q) {
-                    const int r = wave + q * kWaves;
-                    if (r >= nrows) break;   // wave-uniform
-                    const T* wr = wsh + (int64_t)r * wld;
-                    const int64_t kk = (int64_t)s * substeps + sub;   // step of this launch
-                    if (TRACE && lane == 0) {
-                        T* x = tr.xt + (kk * 4 + stage) * 3 * ld;
-                        x[row_begin + r] = sx[q];
-                        x[ld + row_begin + r] = sy[q];
-                        x[2 * ld + row_begin + r] = sz[q];
-                    }
-                    // two independent accumulation chains per lane (columns
-                    // j and j + 64 of each 128), joined before the butterfly
-                    // (measured: four chains are slower)
-                    AT vx = A::zero(), vy = A::zero(), vz = A::zero();
-                    AT ux = A::zero(), uy = A::zero(), uz = A::zero();
-                    int j = lane;
-                    for (; j + 64 < n; j += 128) {
-                        const T w0 = wr[j], w1 = wr[j + 64];
-                        A::fma(vx, w0, xs[j]);
-                        A::fma(ux, w1, xs[j + 64]);
-                        if (XYZ) {
-                            A::fma(vy, w0, xs[n + j]);
-                            A::fma(uy, w1, xs[n + j + 64]);
-                            A::fma(vz, w0, xs[2 * n + j]);
-                            A::fma(uz, w1, xs[2 * n + j + 64]);
-                        }
-                    }
-                    if (j < n) {
-                        const T w0 = wr[j];
-                        A::fma(vx, w0, xs[j]);
-                        if (XYZ) {
-                            A::fma(vy, w0, xs[n + j]);
-                            A::fma(vz, w0, xs[2 * n + j]);
-                        }
-                    }
-                    vx = A::add(vx, ux);
-                    if (XYZ) {
-                        vy = A::add(vy, uy);
-                        vz = A::add(vz, uz);
-                    }
-                    vx = group_reduce<T>(vx, 64);
-                    T cx = k.a_cp * A::round(vx), cy = T(0), cz = T(0);
-                    if (XYZ) {
-                        vy = group_reduce<T>(vy, 64);
-                        vz = group_reduce<T>(vz, 64);
-                        cy = k.a_cp * A::round(vy);
-                        cz = k.a_cp * A::round(vz);
-                    }
-                    if (TRACE && lane == 0) {
-                        T* w = tr.wx + (kk * 4 + stage) * C * ld;
-                        w[row_begin + r] = A::round(vx);
-                        if (XYZ) {
-                            w[ld + row_begin + r] = A::round(vy);
-                            w[2 * ld + row_begin + r] = A::round(vz);
-                        }
-                    }
+                // right-hand side, RK4 update and (stage 3) projection of row q
+                // from its coupling sums
+                auto finish_row = [&](int q, int r, int64_t kk, T cx, T cy, T cz) {
                     T fx, fy, fz;
                     llg_rhs<T, XYZ>(k, sx[q], sy[q], sz[q], cx, cy, cz, hin[q], fx, fy, fz);
                     T nx = rk4_update(k, stage, mx[q], ax[q], fx);
@@ -296,16 +248,148 @@ __global__ void __launch_bounds__(BLOCK) k_resident(DevState<T> d, Coef<T> k, co
                     sx[q] = nx;
                     sy[q] = ny;
                     sz[q] = nz;
+                };
+                if constexpr (SPLIT > 1) {
+                    // each wave sums its share of the columns (pairs 64 lanes
+                    // apart, two chains per lane) and reduces it over the
+                    // wave; the shares meet in LDS and every wave of the row
+                    // finishes it (part 0's results are the ones kept)
+                    __shared__ AT psum[SPLIT][kGroups][kMaxRowsPerWave][C];
+                    const int qn = (nrows + kGroups - 1) / kGroups;   // block-uniform
+#pragma unroll
+                    for (int q = 0; q < kMaxRowsPerWave; ++q) {
+                        if (q >= qn) break;   // every wave reaches the barrier below
+                        const int r = grp + q * kGroups;
+                        const bool has = r < nrows;   // wave-uniform
+                        const int64_t kk = (int64_t)s * substeps + sub;
+                        if (has) {
+                            const T* wr = wsh + (int64_t)r * wld;
+                            AT vx = A::zero(), vy = A::zero(), vz = A::zero();
+                            AT ux = A::zero(), uy = A::zero(), uz = A::zero();
+                            int j = lane + 64 * part;
+                            for (; j + 64 * SPLIT < n; j += 128 * SPLIT) {
+                                const T w0 = wr[j], w1 = wr[j + 64 * SPLIT];
+                                A::fma(vx, w0, xs[j]);
+                                A::fma(ux, w1, xs[j + 64 * SPLIT]);
+                                if (XYZ) {
+                                    A::fma(vy, w0, xs[n + j]);
+                                    A::fma(uy, w1, xs[n + j + 64 * SPLIT]);
+                                    A::fma(vz, w0, xs[2 * n + j]);
+                                    A::fma(uz, w1, xs[2 * n + j + 64 * SPLIT]);
+                                }
+                            }
+                            if (j < n) {
+                                const T w0 = wr[j];
+                                A::fma(vx, w0, xs[j]);
+                                if (XYZ) {
+                                    A::fma(vy, w0, xs[n + j]);
+                                    A::fma(vz, w0, xs[2 * n + j]);
+                                }
+                            }
+                            vx = group_reduce<T>(A::add(vx, ux), 64);
+                            if (XYZ) {
+                                vy = group_reduce<T>(A::add(vy, uy), 64);
+                                vz = group_reduce<T>(A::add(vz, uz), 64);
+                            }
+                            if (lane == 0) {
+                                psum[part][grp][q][0] = vx;
+                                if (XYZ) {
+                                    psum[part][grp][q][C - 2] = vy;
+                                    psum[part][grp][q][C - 1] = vz;
+                                }
+                            }
+                        }
+                        __syncthreads();
+                        if (has) {
+                            AT tx = psum[0][grp][q][0], ty = A::zero(), tz = A::zero();
+#pragma unroll
+                            for (int p = 1; p < SPLIT; ++p) tx = A::add(tx, psum[p][grp][q][0]);
+                            if (XYZ) {
+                                ty = psum[0][grp][q][C - 2];
+                                tz = psum[0][grp][q][C - 1];
+#pragma unroll
+                                for (int p = 1; p < SPLIT; ++p) {
+                                    ty = A::add(ty, psum[p][grp][q][C - 2]);
+                                    tz = A::add(tz, psum[p][grp][q][C - 1]);
+                                }
+                            }
+                            const T cx = k.a_cp * A::round(tx);
+                            const T cy = XYZ ? k.a_cp * A::round(ty) : T(0);
+                            const T cz = XYZ ? k.a_cp * A::round(tz) : T(0);
+                            finish_row(q, r, kk, cx, cy, cz);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < kMaxRowsPerWave; ++q) {
+                        const int r = grp + q * kGroups;
+                        if (r >= nrows) break;   // wave-uniform
+                        const T* wr = wsh + (int64_t)r * wld;
+                        const int64_t kk = (int64_t)s * substeps + sub;   // step of this launch
+                        if (TRACE && lane == 0) {
+                            T* x = tr.xt + (kk * 4 + stage) * 3 * ld;
+                            x[row_begin + r] = sx[q];
+                            x[ld + row_begin + r] = sy[q];
+                            x[2 * ld + row_begin + r] = sz[q];
+                        }
+                        // two independent accumulation chains per lane (columns
+                        // j and j + 64 of each 128), joined before the butterfly
+                        // (measured: four chains are slower)
+                        AT vx = A::zero(), vy = A::zero(), vz = A::zero();
+                        AT ux = A::zero(), uy = A::zero(), uz = A::zero();
+                        int j = lane;
+                        for (; j + 64 < n; j += 128) {
+                            const T w0 = wr[j], w1 = wr[j + 64];
+                            A::fma(vx, w0, xs[j]);
+                            A::fma(ux, w1, xs[j + 64]);
+                            if (XYZ) {
+                                A::fma(vy, w0, xs[n + j]);
+                                A::fma(uy, w1, xs[n + j + 64]);
+                                A::fma(vz, w0, xs[2 * n + j]);
+                                A::fma(uz, w1, xs[2 * n + j + 64]);
+                            }
+                        }
+                        if (j < n) {
+                            const T w0 = wr[j];
+                            A::fma(vx, w0, xs[j]);
+                            if (XYZ) {
+                                A::fma(vy, w0, xs[n + j]);
+                                A::fma(vz, w0, xs[2 * n + j]);
+                            }
+                        }
+                        vx = A::add(vx, ux);
+                        if (XYZ) {
+                            vy = A::add(vy, uy);
+                            vz = A::add(vz, uz);
+                        }
+                        vx = group_reduce<T>(vx, 64);
+                        T cx = k.a_cp * A::round(vx), cy = T(0), cz = T(0);
+                        if (XYZ) {
+                            vy = group_reduce<T>(vy, 64);
+                            vz = group_reduce<T>(vz, 64);
+                            cy = k.a_cp * A::round(vy);
+                            cz = k.a_cp * A::round(vz);
+                        }
+                        if (TRACE && lane == 0) {
+                            T* w = tr.wx + (kk * 4 + stage) * C * ld;
+                            w[row_begin + r] = A::round(vx);
+                            if (XYZ) {
+                                w[ld + row_begin + r] = A::round(vy);
+                                w[2 * ld + row_begin + r] = A::round(vz);
+                            }
+                        }
+                        finish_row(q, r, kk, cx, cy, cz);
+                    }
                 }
                 stamp(trace, trace_stages, sigma, 2);
                 // step 4: publish this wave's rows once the re-arm stores have
                 // completed (one wait for all rows; the clobber keeps the
                 // compiler from moving the stores across it)
-                if (lane == 0) {
+                if (lane == 0 && part == 0) {
                     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 #pragma unroll
                     for (int q = 0; q < kMaxRowsPerWave; ++q) {
-                        const int r = wave + q * kWaves;
+                        const int r = grp + q * kGroups;
                         if (r >= nrows) break;
                         const int row = row_begin + r;
                         publish(xout + row, sx[q]);
@@ -318,10 +402,10 @@ __global__ void __launch_bounds__(BLOCK) k_resident(DevState<T> d, Coef<T> k, co
                 stamp(trace, trace_stages, sigma, 3);
             }
         }
-        if (lane == 0) {
+        if (lane == 0 && part == 0) {
 #pragma unroll
             for (int q = 0; q < kMaxRowsPerWave; ++q) {
-                const int r = wave + q * kWaves;
+                const int r = grp + q * kGroups;
                 if (r >= nrows) break;
                 const int row = row_begin + r;
                 if (states) {
@@ -334,11 +418,11 @@ __global__ void __launch_bounds__(BLOCK) k_resident(DevState<T> d, Coef<T> k, co
             }
         }
     }
-    if (lane == 0) {
+    if (lane == 0 && part == 0) {
         T* xc = d.ms[cur];
 #pragma unroll
         for (int q = 0; q < kMaxRowsPerWave; ++q) {
-            const int r = wave + q * kWaves;
+            const int r = grp + q * kGroups;
             if (r >= nrows) break;
             const int row = row_begin + r;
             d.m[row] = xc[row] = mx[q];
@@ -536,9 +620,10 @@ size_t resident_lds(int n, int rows_per_block, int elem, int xyz) {
 // variant 0: plain run; 1: the adjoint's traced recompute; 2: its reverse
 template <typename T, bool XYZ, int BLOCK>
 const void* resident_fn_v(int variant) {
-    if (variant == 1) return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, true>);
+    if (variant == 1) return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, true, 1>);
     if (variant == 2) return reinterpret_cast<const void*>(&k_resident_rev<T, XYZ, BLOCK>);
-    return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, false>);
+    if (variant == 3) return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, false, 2>);
+    return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, false, 1>);
 }
 
 template <typename T, bool XYZ>
@@ -571,25 +656,29 @@ int env_int(const char* name) {
     return v && *v ? atoi(v) : 0;
 }
 
-// Whether (waves, rpb) runs n nodes: rows per wave, LDS, co-residency.
-bool shape_fits(int n, int elem_bytes, int xyz, int waves, int rpb, int cus, int* grid_out) {
+// Whether (waves, rpb, split) runs n nodes: rows per wave, LDS,
+// co-residency.  split = 2 runs each row on two waves (half the columns
+// each), so a workgroup holds half as many rows per wave.
+bool shape_fits(int n, int elem_bytes, int xyz, int waves, int rpb, int split, int cus, int* grid_out) {
     const int block = 64 * waves;
-    if (rpb < 1 || rpb > waves * max_rows_per_wave(block)) return false;
+    if (split != 1 && split != 2) return false;
+    if (rpb < 1 || rpb > waves / split * max_rows_per_wave(block)) return false;
     const size_t lds = resident_lds(n, rpb, elem_bytes, xyz);
-    if (lds + 64 > kLdsMax) return false;
+    if (lds + 64 + (split > 1 ? 2048 : 0) > kLdsMax) return false;   // the split's static LDS
     const int grid = (n + rpb - 1) / rpb;
-    if (!co_resident(resident_kernel(elem_bytes, xyz, block), block, lds, grid, cus)) return false;
+    if (!co_resident(resident_kernel(elem_bytes, xyz, block, split > 1 ? 3 : 0), block, lds, grid, cus)) return false;
     *grid_out = grid;
     return true;
 }
 
 }  // namespace
 
-int tuned_path(int elem_bytes, int xyz, int n, int* waves, int* rpb) {
+int tuned_path(int elem_bytes, int xyz, int n, int* waves, int* rpb, int* split) {
     for (const PathTuneEntry& e : kPathTune)
         if (e.elem_bytes == elem_bytes && e.xyz == (xyz ? 1 : 0) && n <= e.n_max) {
             if (waves) *waves = e.waves;
             if (rpb) *rpb = e.rpb;
+            if (split) *split = e.split;
             return e.path;
         }
     return 0;
@@ -601,32 +690,42 @@ int tuned_path(int elem_bytes, int xyz, int n, int* waves, int* rpb) {
 // STO_RESIDENT_RPB (rows per workgroup) and STO_RESIDENT_WAVES (4, 8 or 16)
 // override both for measurements.  False if no shape fits (LDS, rows per
 // wave) or its workgroups cannot all be co-resident.
-bool resident_shape(int n, int elem_bytes, int xyz, int* grid_out, int* rpb_out, int* block_out) {
+bool resident_shape(int n, int elem_bytes, int xyz, int* grid_out, int* rpb_out, int* block_out, int* split_out) {
     const int cus = device_cus();
     if (cus <= 0 || n < 2) return false;
     const int env_waves = env_int("STO_RESIDENT_WAVES"), env_rpb = env_int("STO_RESIDENT_RPB");
+    // a caller that cannot run the two-waves-per-row kernel (the adjoint's
+    // traced and reversed kernels) passes no split_out and gets a shape of
+    // one wave per row
+    const bool allow_split = split_out != nullptr;
+    const int env_split = allow_split ? env_int("STO_RESIDENT_SPLIT") : 0;
     const int def_rpb = (n + cus - 1) / cus;
-    int cand[2][2];
+    int cand[2][3];
     int nc = 0;
-    if (env_waves > 0 || env_rpb > 0) {
+    if (env_waves > 0 || env_rpb > 0 || env_split > 0) {
         const int w = (env_waves == 8 || env_waves == 16) ? env_waves : 4;
         cand[nc][0] = w;
-        cand[nc++][1] = env_rpb > 0 ? env_rpb : def_rpb;
+        cand[nc][1] = env_rpb > 0 ? env_rpb : def_rpb;
+        cand[nc++][2] = env_split == 2 ? 2 : 1;
     } else {
-        int tw = 0, tr = 0;
-        if (tuned_path(elem_bytes, xyz, n, &tw, &tr) == 2 && (tw == 4 || tw == 8 || tw == 16)) {
+        int tw = 0, tr = 0, ts = 1;
+        if (tuned_path(elem_bytes, xyz, n, &tw, &tr, &ts) == 2 && (tw == 4 || tw == 8 || tw == 16) &&
+            (ts == 1 || allow_split)) {
             cand[nc][0] = tw;
-            cand[nc++][1] = tr > 0 ? tr : def_rpb;
+            cand[nc][1] = tr > 0 ? tr : def_rpb;
+            cand[nc++][2] = ts == 2 ? 2 : 1;
         }
         cand[nc][0] = 4;
-        cand[nc++][1] = def_rpb;
+        cand[nc][1] = def_rpb;
+        cand[nc++][2] = 1;
     }
     for (int c = 0; c < nc; ++c) {
         int grid = 0;
-        if (shape_fits(n, elem_bytes, xyz, cand[c][0], cand[c][1], cus, &grid)) {
+        if (shape_fits(n, elem_bytes, xyz, cand[c][0], cand[c][1], cand[c][2], cus, &grid)) {
             if (grid_out) *grid_out = grid;
             if (rpb_out) *rpb_out = cand[c][1];
             if (block_out) *block_out = 64 * cand[c][0];
+            if (split_out) *split_out = cand[c][2];
             return true;
         }
     }
@@ -634,13 +733,14 @@ bool resident_shape(int n, int elem_bytes, int xyz, int* grid_out, int* rpb_out,
 }
 
 bool resident_fits(int n, int elem_bytes, int xyz, int* grid_out) {
-    return resident_shape(n, elem_bytes, xyz, grid_out, nullptr, nullptr);
+    int split = 1;   // the shape a run takes
+    return resident_shape(n, elem_bytes, xyz, grid_out, nullptr, nullptr, &split);
 }
 
 template <typename T>
 hipError_t run_resident(const DevState<T>& d, const Coef<T>& k, const RunSpec& r) {
-    int grid = 0, rpb = 0, block = 0;
-    if (!resident_shape(d.n, sizeof(T), r.xyz, &grid, &rpb, &block)) return hipErrorInvalidValue;
+    int grid = 0, rpb = 0, block = 0, split = 1;
+    if (!resident_shape(d.n, sizeof(T), r.xyz, &grid, &rpb, &block, &split)) return hipErrorInvalidValue;
     int wld = (int)wld_of(d.n);
     const size_t lds = resident_lds(d.n, rpb, sizeof(T), r.xyz);
     const int C = r.xyz ? 3 : 1;
@@ -665,7 +765,7 @@ hipError_t run_resident(const DevState<T>& d, const Coef<T>& k, const RunSpec& r
     int sample0 = 0;
     void* args[] = {&dd, &kk, &u, &states, &samples, &substeps, &cur, &renorm, &rpb, &wld, &trace, &trace_stages,
                     &tr, &sample0};
-    const void* fn = resident_kernel(sizeof(T), r.xyz, block);
+    const void* fn = resident_kernel(sizeof(T), r.xyz, block, split > 1 ? 3 : 0);
     e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, (unsigned)lds, r.stream);
     if (e != hipSuccess) return e;
     return hipGetLastError();
@@ -681,7 +781,7 @@ int reverse_block(int block) { return block >= 1024 ? 512 : block; }
 
 bool resident_adjoint_fits(int n, int elem_bytes, int xyz, int n_in) {
     int grid = 0, rpb = 0, block = 0;
-    if (n_in > kRevIn || !resident_shape(n, elem_bytes, xyz, &grid, &rpb, &block)) return false;
+    if (n_in > kRevIn || !resident_shape(n, elem_bytes, xyz, &grid, &rpb, &block, nullptr)) return false;
     const size_t lds = resident_lds(n, rpb, elem_bytes, xyz);
     const int cus = device_cus();
     return co_resident(resident_kernel(elem_bytes, xyz, block, 1), block, lds, grid, cus) &&
@@ -693,6 +793,7 @@ template <typename T>
 hipError_t run_resident_traced(const DevState<T>& d, const Coef<T>& k, const RunSpec& r, const ResTrace<T>& tr,
                                int sample0) {
     int grid = 0, rpb = 0, block = 0;
+    // the traced recompute always sums each row on one wave
     if (!resident_shape(d.n, sizeof(T), r.xyz, &grid, &rpb, &block)) return hipErrorInvalidValue;
     int wld = (int)wld_of(d.n);
     const size_t lds = resident_lds(d.n, rpb, sizeof(T), r.xyz);
