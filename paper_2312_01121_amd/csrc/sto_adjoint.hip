@@ -56,8 +56,7 @@ template <> struct AVec<float> { using type = fv4; static constexpr int n = 4; }
 // Sum over the 64 lanes of a wave (every lane ends with the total).
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    return lane_sum<T>(v);
 }
 
 // ---------------------------------------------------------------------------

@@ -139,6 +139,19 @@ __device__ __forceinline__ typename Acc<T>::type group_reduce(typename Acc<T>::t
     return v;
 }
 
+// Plain sum over the 64 lanes of a wave (every lane ends with the total), in
+// the butterfly order above.
+template <typename T>
+__device__ __forceinline__ T lane_sum(T v) {
+    v += lane_partner<1>(v);
+    v += lane_partner<2>(v);
+    v += lane_partner<4>(v);
+    v += lane_partner<8>(v);
+    v += lane_partner<16>(v);
+    v += lane_partner<32>(v);
+    return v;
+}
+
 // ---------------------------------------------------------------------------
 // Pointwise right-hand side, Eq. (gov), for one node.
 //   (mx,my,mz)  stage input of the node

@@ -573,15 +573,10 @@ __global__ void __launch_bounds__(BLOCK) k_resident_rev(AdjDev<T> d, Coef<T> k, 
                         vz = __builtin_fma(w0, xs[2 * n + j], vz);
                     }
                 }
-                vx += ux;
-                for (int off = 32; off > 0; off >>= 1) vx += __shfl_xor(vx, off, 64);
+                vx = lane_sum<T>(vx + ux);
                 if (XYZ) {
-                    vy += uy;
-                    vz += uz;
-                    for (int off = 32; off > 0; off >>= 1) {
-                        vy += __shfl_xor(vy, off, 64);
-                        vz += __shfl_xor(vz, off, 64);
-                    }
+                    vy = lane_sum<T>(vy + uy);
+                    vz = lane_sum<T>(vz + uz);
                 }
                 if (lane == q) {
                     t[0] = vx;
