@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(BLOCK) k_resident(DevState<T> d, Coef<T> k, co
                     T ny = rk4_update(k, stage, my[q], ay[q], fy);
                     T nz = rk4_update(k, stage, mz[q], az[q], fz);
                     if (stage == 3) {
-                        if (TRACE && renorm && lane == 0) {
+                        if (TRACE && renorm && lane == 0 && part == 0) {
                             const double ex = nx, ey = ny, ez = nz;
                             tr.pn[kk * ld + row_begin + r] = (T)__builtin_sqrt((ex * ex + ey * ey) + ez * ez);
                         }
@@ -263,6 +263,12 @@ __global__ void __launch_bounds__(BLOCK) k_resident(DevState<T> d, Coef<T> k, co
                         const bool has = r < nrows;   // wave-uniform
                         const int64_t kk = (int64_t)s * substeps + sub;
                         if (has) {
+                            if (TRACE && lane == 0 && part == 0) {
+                                T* x = tr.xt + (kk * 4 + stage) * 3 * ld;
+                                x[row_begin + r] = sx[q];
+                                x[ld + row_begin + r] = sy[q];
+                                x[2 * ld + row_begin + r] = sz[q];
+                            }
                             const T* wr = wsh + (int64_t)r * wld;
                             AT vx = A::zero(), vy = A::zero(), vz = A::zero();
                             AT ux = A::zero(), uy = A::zero(), uz = A::zero();
@@ -316,6 +322,14 @@ __global__ void __launch_bounds__(BLOCK) k_resident(DevState<T> d, Coef<T> k, co
                             const T cx = k.a_cp * A::round(tx);
                             const T cy = XYZ ? k.a_cp * A::round(ty) : T(0);
                             const T cz = XYZ ? k.a_cp * A::round(tz) : T(0);
+                            if (TRACE && lane == 0 && part == 0) {
+                                T* w = tr.wx + (kk * 4 + stage) * C * ld;
+                                w[row_begin + r] = A::round(tx);
+                                if (XYZ) {
+                                    w[ld + row_begin + r] = A::round(ty);
+                                    w[2 * ld + row_begin + r] = A::round(tz);
+                                }
+                            }
                             finish_row(q, r, kk, cx, cy, cz);
                         }
                     }
@@ -618,6 +632,7 @@ const void* resident_fn_v(int variant) {
     if (variant == 1) return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, true, 1>);
     if (variant == 2) return reinterpret_cast<const void*>(&k_resident_rev<T, XYZ, BLOCK>);
     if (variant == 3) return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, false, 2>);
+    if (variant == 4) return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, true, 2>);
     return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, false, 1>);
 }
 
@@ -775,21 +790,28 @@ template hipError_t run_resident<float>(const DevState<float>&, const Coef<float
 int reverse_block(int block) { return block >= 1024 ? 512 : block; }
 
 bool resident_adjoint_fits(int n, int elem_bytes, int xyz, int n_in) {
-    int grid = 0, rpb = 0, block = 0;
-    if (n_in > kRevIn || !resident_shape(n, elem_bytes, xyz, &grid, &rpb, &block, nullptr)) return false;
-    const size_t lds = resident_lds(n, rpb, elem_bytes, xyz);
+    if (n_in > kRevIn) return false;
     const int cus = device_cus();
-    return co_resident(resident_kernel(elem_bytes, xyz, block, 1), block, lds, grid, cus) &&
-           co_resident(resident_kernel(elem_bytes, xyz, reverse_block(block), 2), reverse_block(block), lds, grid,
+    int grid = 0, rpb = 0, block = 0, split = 1;
+    // the traced recompute runs the plain forward's shape
+    if (!resident_shape(n, elem_bytes, xyz, &grid, &rpb, &block, &split)) return false;
+    if (!co_resident(resident_kernel(elem_bytes, xyz, block, split > 1 ? 4 : 1), block,
+                     resident_lds(n, rpb, elem_bytes, xyz), grid, cus))
+        return false;
+    // the reverse runs a shape of one wave per row
+    if (!resident_shape(n, elem_bytes, xyz, &grid, &rpb, &block)) return false;
+    const size_t lds = resident_lds(n, rpb, elem_bytes, xyz);
+    return co_resident(resident_kernel(elem_bytes, xyz, reverse_block(block), 2), reverse_block(block), lds, grid,
                        cus);
 }
 
 template <typename T>
 hipError_t run_resident_traced(const DevState<T>& d, const Coef<T>& k, const RunSpec& r, const ResTrace<T>& tr,
                                int sample0) {
-    int grid = 0, rpb = 0, block = 0;
-    // the traced recompute always sums each row on one wave
-    if (!resident_shape(d.n, sizeof(T), r.xyz, &grid, &rpb, &block)) return hipErrorInvalidValue;
+    int grid = 0, rpb = 0, block = 0, split = 1;
+    // the plain forward's shape, two waves per row included (the trace is in
+    // node order, independent of the shape)
+    if (!resident_shape(d.n, sizeof(T), r.xyz, &grid, &rpb, &block, &split)) return hipErrorInvalidValue;
     int wld = (int)wld_of(d.n);
     const size_t lds = resident_lds(d.n, rpb, sizeof(T), r.xyz);
     const int C = r.xyz ? 3 : 1;
@@ -809,7 +831,7 @@ hipError_t run_resident_traced(const DevState<T>& d, const Coef<T>& k, const Run
     int s0 = sample0;
     void* args[] = {&dd, &kk, &u, &states, &samples, &substeps, &cur, &renorm, &rpb, &wld, &trace, &trace_stages,
                     &t, &s0};
-    const void* fn = resident_kernel(sizeof(T), r.xyz, block, 1);
+    const void* fn = resident_kernel(sizeof(T), r.xyz, block, split > 1 ? 4 : 1);
     if (!co_resident(fn, block, lds, grid, device_cus())) return hipErrorInvalidValue;
     e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, (unsigned)lds, r.stream);
     if (e != hipSuccess) return e;
