@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdlib>
 
 #include "sto_internal.hpp"
 
@@ -147,11 +148,36 @@ int small_max_n(int elem_bytes, int /*xyz*/) {
     return n;
 }
 
-// Lanes per node: about 4 terms of the row sum per lane (measured: longer
-// per-lane chains cost more than the extra butterfly level), at most 64 (one
-// wave) and at most 1024 threads in all.
-static int small_lanes(int n) {
+// Lanes per node.  FP64: a table measured per node count (us per RK4 step
+// at N = 1, 2, 4, 8, 10, 16, 24, 32, 48, 64, 100 with the lane counts that
+// give 1, 2, 4 and 8 terms per lane): N lanes (one term each) won at N = 4, 8
+// and 16, 4 lanes at N = 10, and 8 lanes from N = 24 up, where more lanes
+// mean more than 512 threads and slower barriers.  Each entry covers n up to
+// the midpoint to the next measured size.  FP32: the largest power of two
+// with at least 4 terms per lane.  Both at most 64 lanes and 1,024 threads in
+// all.  STO_SMALL_TERMS sets the terms per lane for measurements.
+struct SmallLanes {
+    int n_max, lanes;
+};
+constexpr SmallLanes kSmallLanesF64[] = {{3, 2}, {6, 4}, {9, 8}, {13, 4}, {20, 16}, {1 << 30, 8}};
+
+static int small_lanes(int n, int elem_bytes) {
+    const char* env = getenv("STO_SMALL_TERMS");
     int L = 1;
+    if (env && atoi(env) > 0) {
+        const int terms = atoi(env);
+        while (L * 2 <= 64 && L * 2 * terms <= n && L * 2 * n <= 1024) L *= 2;
+        return L;
+    }
+    if (elem_bytes == 8) {
+        for (const SmallLanes& e : kSmallLanesF64)
+            if (n <= e.n_max) {
+                L = e.lanes;
+                break;
+            }
+        while (L > 1 && (L > n || L * n > 1024)) L >>= 1;
+        return L;
+    }
     while (L * 2 <= 64 && L * 2 * 4 <= n && L * 2 * n <= 1024) L *= 2;
     return L;
 }
@@ -184,7 +210,7 @@ static hipError_t launch_small_l(int L, const DevState<T>& d, const Coef<T>& k, 
 template <typename T>
 hipError_t run_small(const DevState<T>& d, const Coef<T>& k, const RunSpec& r) {
     const int n = d.n;
-    const int L = small_lanes(n);
+    const int L = small_lanes(n, (int)sizeof(T));
     const int block = (L * n + 63) / 64 * 64;
     size_t lds = small_lds_bytes(n, sizeof(T));
     if (L * n > block || block > 1024 || lds > kLdsMax) return hipErrorInvalidValue;
