@@ -17,6 +17,11 @@ per-stage streaming kernel -- and writes the fastest path and shape per size
 bucket into ``csrc/path_tune.hpp``, which sets the automatic path choice and
 the resident launch shape.
 
+Within 2 % of the fastest, the path table keeps the choice of the next
+smaller size (run-to-run noise would otherwise alternate paths between
+neighbouring sizes); ``--paths-from LOG`` rewrites the table from the
+printed lines of an earlier ``--paths`` run, on the CPU.
+
 Rebuild the library afterwards (``python paper_2312_01121_amd/_build.py``).
 
 Usage (on the GPU): python -m paper_2312_01121_amd.autotune [--paths] [--write [PATH]] [--samples S]
@@ -41,8 +46,10 @@ PATH_SIZES = {"f64": [16, 32, 48, 64, 80, 96, 128, 140, 192, 256, 384, 512, 768,
               "f32": [16, 32, 64, 96, 128, 160, 199, 256, 384, 512, 768, 1000, 1280, 1536, 2048, 2560, 3072]}
 # (waves, rows per workgroup (0: ceil(n / CUs)), waves per row)
 RESIDENT_SHAPES = [(4, 0, 1), (8, 0, 1), (16, 0, 1), (4, 4, 1), (8, 8, 1), (16, 16, 1), (8, 16, 1),
-                   (4, 0, 2), (8, 0, 2), (16, 0, 2), (8, 4, 2), (8, 8, 2), (16, 8, 2)]
+                   (4, 0, 2), (8, 0, 2), (16, 0, 2), (8, 4, 2), (8, 8, 2), (16, 8, 2),
+                   (8, 0, 4), (16, 0, 4), (8, 8, 4)]
 SPLIT_MIN_N = 256   # rows shorter than this are not worth two waves
+SAME_AS_PREVIOUS = 0.02   # keep the next smaller size's choice within 2 % of the fastest
 PATH_CODE = {"small": 1, "resident": 2, "stream": 3}
 
 
@@ -192,7 +199,7 @@ struct PathTuneEntry {{
     int path;       // 1 small, 2 resident, 3 stream (sto_path values)
     int waves;      // resident: waves per workgroup (4, 8 or 16)
     int rpb;        // resident: rows per workgroup (0: ceil(n / CUs))
-    int split;      // resident: waves per row (1, or 2: each sums half the columns)
+    int split;      // resident: waves per row (1, 2 or 4: each sums its share of the columns)
 }};
 
 // Fastest path and shape per size bucket (microseconds per RK4 step measured
@@ -225,20 +232,57 @@ def tune_paths(stx, torch, samples, write):
                     name = f"resident_{shape[0]}x{shape[1]}" + (f"s{shape[2]}" if shape[2] > 1 else "")
                     times[name] = time_path(stx, torch, n, dtype, coupling, "resident", shape, s)
                 ok = {k: v for k, v in times.items() if v is not None}
-                key = min(ok, key=ok.get)
-                if key.startswith("resident_"):
-                    spec = key[len("resident_"):]
-                    split = int(spec.split("s")[1]) if "s" in spec else 1
-                    waves, rpb = (int(x) for x in spec.split("s")[0].split("x"))
-                    best[(dtype, coupling)][n] = ("resident", waves, rpb, split)
-                else:
-                    best[(dtype, coupling)][n] = (key, 0, 0, 1)
                 measured[f"{dtype}/{coupling}/{n}"] = {k: round(v, 2) for k, v in ok.items()}
+                key = min(ok, key=ok.get)
                 print(json.dumps({"dtype": dtype, "coupling": coupling, "n": n, "best": key,
                                   "us": round(ok[key], 2), "all": measured[f"{dtype}/{coupling}/{n}"]}), flush=True)
     if write:
-        write_path_header(best, measured, write)
+        write_path_header(choose(measured), measured, write)
         print(f"wrote {write}", file=sys.stderr)
+
+
+def parse_choice(key):
+    """(path, waves, rows, split) of a measured key."""
+    if not key.startswith("resident_"):
+        return (key, 0, 0, 1)
+    spec = key[len("resident_"):]
+    split = int(spec.split("s")[1]) if "s" in spec else 1
+    waves, rpb = (int(x) for x in spec.split("s")[0].split("x"))
+    return ("resident", waves, rpb, split)
+
+
+def choose(measured, keep_within=SAME_AS_PREVIOUS):
+    """Path and shape per size from the measured times.  The fastest, except
+    that the choice of the next smaller size is kept while it is within
+    ``keep_within`` (relative) of the fastest: differences that small are
+    run-to-run noise, and would otherwise alternate the path between
+    neighbouring sizes."""
+    best = {}
+    for dtype in PATH_SIZES:
+        for coupling in ("x", "xyz"):
+            per, prev = {}, None
+            sizes = sorted(int(k.split("/")[2]) for k in measured if k.startswith(f"{dtype}/{coupling}/"))
+            for n in sizes:
+                ok = measured[f"{dtype}/{coupling}/{n}"]
+                key = min(ok, key=ok.get)
+                if prev in ok and ok[prev] <= ok[key] * (1 + keep_within):
+                    key = prev
+                per[n] = parse_choice(key)
+                prev = key
+            if per:
+                best[(dtype, coupling)] = per
+    return best
+
+
+def measured_from_log(path):
+    """The measured times of a ``--paths`` run, from its printed lines."""
+    measured = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("{"):
+                d = json.loads(line)
+                measured[f"{d['dtype']}/{d['coupling']}/{d['n']}"] = d["all"]
+    return measured
 
 
 SWEEP_HEADER = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "sweep_tune.hpp")
@@ -345,7 +389,15 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="tune the sweep kernel's rows per group and row pitch")
     ap.add_argument("--write", nargs="?", const="default", default=None, metavar="PATH",
                     help="write the table header (default: csrc/stream_tune.hpp, or csrc/path_tune.hpp)")
+    ap.add_argument("--paths-from", metavar="LOG",
+                    help="write the path table from the printed lines of an earlier --paths run (no GPU)")
     args = ap.parse_args()
+    if args.paths_from:
+        measured = measured_from_log(args.paths_from)
+        write = PATH_HEADER if args.write in (None, "default") else args.write
+        write_path_header(choose(measured), measured, write)
+        print(f"wrote {write}", file=sys.stderr)
+        return
     import torch
     assert torch.cuda.is_available(), "the autotuner runs on the GPU"
     import paper_2312_01121_amd as stx

@@ -37,9 +37,10 @@
 //
 // Launch shape: BLOCK threads (4, 8 or 16 waves) and rows_per_block rows of
 // W per workgroup, at most 4 rows per wave (1 with 16 waves).  The default is 4 waves and
-// ceil(n / CUs) rows.  With SPLIT = 2 two waves share each row, each summing
-// half of its columns; their wave totals meet in LDS, which halves the
-// dependent chain of a row's sum at the cost of one barrier per row.  With a trace buffer, wave 0 of every workgroup
+// ceil(n / CUs) rows.  With SPLIT = 2 or 4 that many waves share each row,
+// each summing its share of the columns; their wave totals meet in LDS, which
+// shortens the dependent chain of a row's sum at the cost of one barrier per
+// row.  With a trace buffer, wave 0 of every workgroup
 // stamps the device's constant-rate clock at four points of each of the
 // first trace_stages stages (stage start, gather done, own rows computed,
 // own rows published), for the phase breakdown of the exchange.
@@ -626,14 +627,28 @@ size_t resident_lds(int n, int rows_per_block, int elem, int xyz) {
     return ((size_t)rows_per_block * wld_of(n) + (xyz ? 3 : 1) * (size_t)n) * elem;
 }
 
-// variant 0: plain run; 1: the adjoint's traced recompute; 2: its reverse
+// variant 0: plain run; 1: the adjoint's traced recompute; 2: its reverse;
+// 3, 4: plain and traced with two waves per row; 5, 6: with four (8 or 16
+// waves only)
 template <typename T, bool XYZ, int BLOCK>
 const void* resident_fn_v(int variant) {
     if (variant == 1) return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, true, 1>);
     if (variant == 2) return reinterpret_cast<const void*>(&k_resident_rev<T, XYZ, BLOCK>);
     if (variant == 3) return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, false, 2>);
     if (variant == 4) return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, true, 2>);
+    if constexpr (BLOCK >= 512) {
+        if (variant == 5) return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, false, 4>);
+        if (variant == 6) return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, true, 4>);
+    }
+    if (variant >= 5) return nullptr;
     return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, false, 1>);
+}
+
+// the forward variant for waves per row `split`, plain or traced
+int split_variant(int split, bool traced) {
+    if (split == 4) return traced ? 6 : 5;
+    if (split == 2) return traced ? 4 : 3;
+    return traced ? 1 : 0;
 }
 
 template <typename T, bool XYZ>
@@ -671,12 +686,14 @@ int env_int(const char* name) {
 // each), so a workgroup holds half as many rows per wave.
 bool shape_fits(int n, int elem_bytes, int xyz, int waves, int rpb, int split, int cus, int* grid_out) {
     const int block = 64 * waves;
-    if (split != 1 && split != 2) return false;
+    if (split != 1 && split != 2 && split != 4) return false;
+    if (split > waves) return false;
     if (rpb < 1 || rpb > waves / split * max_rows_per_wave(block)) return false;
     const size_t lds = resident_lds(n, rpb, elem_bytes, xyz);
     if (lds + 64 + (split > 1 ? 2048 : 0) > kLdsMax) return false;   // the split's static LDS
     const int grid = (n + rpb - 1) / rpb;
-    if (!co_resident(resident_kernel(elem_bytes, xyz, block, split > 1 ? 3 : 0), block, lds, grid, cus)) return false;
+    if (!co_resident(resident_kernel(elem_bytes, xyz, block, split_variant(split, false)), block, lds, grid, cus))
+        return false;
     *grid_out = grid;
     return true;
 }
@@ -716,14 +733,14 @@ bool resident_shape(int n, int elem_bytes, int xyz, int* grid_out, int* rpb_out,
         const int w = (env_waves == 8 || env_waves == 16) ? env_waves : 4;
         cand[nc][0] = w;
         cand[nc][1] = env_rpb > 0 ? env_rpb : def_rpb;
-        cand[nc++][2] = env_split == 2 ? 2 : 1;
+        cand[nc++][2] = (env_split == 2 || env_split == 4) ? env_split : 1;
     } else {
         int tw = 0, tr = 0, ts = 1;
         if (tuned_path(elem_bytes, xyz, n, &tw, &tr, &ts) == 2 && (tw == 4 || tw == 8 || tw == 16) &&
             (ts == 1 || allow_split)) {
             cand[nc][0] = tw;
             cand[nc][1] = tr > 0 ? tr : def_rpb;
-            cand[nc++][2] = ts == 2 ? 2 : 1;
+            cand[nc++][2] = (ts == 2 || ts == 4) ? ts : 1;
         }
         cand[nc][0] = 4;
         cand[nc][1] = def_rpb;
@@ -775,7 +792,7 @@ hipError_t run_resident(const DevState<T>& d, const Coef<T>& k, const RunSpec& r
     int sample0 = 0;
     void* args[] = {&dd, &kk, &u, &states, &samples, &substeps, &cur, &renorm, &rpb, &wld, &trace, &trace_stages,
                     &tr, &sample0};
-    const void* fn = resident_kernel(sizeof(T), r.xyz, block, split > 1 ? 3 : 0);
+    const void* fn = resident_kernel(sizeof(T), r.xyz, block, split_variant(split, false));
     e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, (unsigned)lds, r.stream);
     if (e != hipSuccess) return e;
     return hipGetLastError();
@@ -795,7 +812,7 @@ bool resident_adjoint_fits(int n, int elem_bytes, int xyz, int n_in) {
     int grid = 0, rpb = 0, block = 0, split = 1;
     // the traced recompute runs the plain forward's shape
     if (!resident_shape(n, elem_bytes, xyz, &grid, &rpb, &block, &split)) return false;
-    if (!co_resident(resident_kernel(elem_bytes, xyz, block, split > 1 ? 4 : 1), block,
+    if (!co_resident(resident_kernel(elem_bytes, xyz, block, split_variant(split, true)), block,
                      resident_lds(n, rpb, elem_bytes, xyz), grid, cus))
         return false;
     // the reverse runs a shape of one wave per row
@@ -831,7 +848,7 @@ hipError_t run_resident_traced(const DevState<T>& d, const Coef<T>& k, const Run
     int s0 = sample0;
     void* args[] = {&dd, &kk, &u, &states, &samples, &substeps, &cur, &renorm, &rpb, &wld, &trace, &trace_stages,
                     &t, &s0};
-    const void* fn = resident_kernel(sizeof(T), r.xyz, block, split > 1 ? 4 : 1);
+    const void* fn = resident_kernel(sizeof(T), r.xyz, block, split_variant(split, true));
     if (!co_resident(fn, block, lds, grid, device_cus())) return hipErrorInvalidValue;
     e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, (unsigned)lds, r.stream);
     if (e != hipSuccess) return e;

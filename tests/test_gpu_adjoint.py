@@ -197,6 +197,34 @@ def test_adjoint_resident_reverse(stx, dtype, n, n_in, coupling, renorm, samples
     compare(got["1"], got["0"], F64_TOL if dtype == "f64" else F32_TOL, "persistent vs per-stage")
 
 
+# The traced recompute runs the forward's launch shape, four waves per row
+# included (forced through the environment); the reverse keeps one wave per
+# row.  Against the oracle's adjoint.
+SPLIT_CASES = [("f64", 1000, "x", 16, 0), ("f64", 600, "xyz", 8, 8), ("f32", 700, "xyz", 8, 8)]
+
+
+@pytest.mark.parametrize("dtype,n,coupling,waves,rpb", SPLIT_CASES,
+                         ids=[f"{c[0]}-n{c[1]}-{c[2]}-{c[3]}x{c[4]}s4" for c in SPLIT_CASES])
+def test_adjoint_four_waves_per_row(stx, dtype, n, coupling, waves, rpb, monkeypatch):
+    sub = 5
+    w, w_in, m0, u, prm, g_rec, g_fin = case(n, samples=2, substeps=sub, seed=n + 11, coupling=coupling)
+    m0_ref = m0
+    if dtype == "f32":
+        w, w_in, g_rec, g_fin = (np.float32(a).astype(np.float64) for a in (w, w_in, g_rec, g_fin))
+        m0_ref = np.float32(m0).astype(np.float64)
+    monkeypatch.setenv("STO_RESIDENT_WAVES", str(waves))
+    monkeypatch.setenv("STO_RESIDENT_SPLIT", "4")
+    if rpb:
+        monkeypatch.setenv("STO_RESIDENT_RPB", str(rpb))
+    say(f"adjoint four waves per row {dtype} n={n} {coupling} {waves}x{rpb}")
+    ref = adjoint.run_adjoint(w, w_in, m0_ref, u, prm, g_rec, g_fin, dot="blas")
+    with stx.Reservoir(w, w_in, m0, lib_params(prm, dtype)) as r:
+        assert r.path == "resident"
+        got = r.adjoint(m0, u, g_rec, g_fin, checkpoint_every=sub)
+        assert r.adjoint_kernels == {"forward": "persistent", "reverse": "persistent"}, r.adjoint_kernels
+    compare(got, ref, F64_TOL if dtype == "f64" else F32_TOL, "four waves per row")
+
+
 def test_adjoint_device_api(stx):
     import torch
     w, w_in, m0, u, prm, g_rec, g_fin = case(40, samples=3, substeps=4, seed=9)

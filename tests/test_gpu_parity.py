@@ -133,6 +133,45 @@ def test_sto10k_f64_prefix(stx):
     assert d <= F64_TOL
 
 
+# Every launch shape of the resident kernel the path table can name: waves
+# per workgroup, rows per workgroup (0: ceil(n / CUs)) and waves per row (1,
+# 2 or 4 waves sharing each row's columns, the shares joined in LDS), forced
+# through the environment, against the oracle.
+SHAPES = [(4, 0, 1), (16, 0, 1), (8, 8, 1), (4, 0, 2), (16, 0, 2), (16, 8, 2), (8, 0, 4), (16, 0, 4), (8, 8, 4)]
+SHAPE_CASES = [("f64", "x", 700), ("f64", "x", 257), ("f64", "xyz", 1000), ("f32", "xyz", 700)]
+
+
+@pytest.mark.parametrize("dtype,coupling,n", SHAPE_CASES, ids=[f"{c[0]}-{c[1]}-n{c[2]}" for c in SHAPE_CASES])
+def test_resident_shapes_match_oracle(stx, dtype, coupling, n, monkeypatch):
+    w, w_in, m0, u = random_case(n, seed=n + 7, samples=4)
+    f32 = lambda x: np.asarray(x, dtype=np.float32).astype(np.float64)  # noqa: E731
+    if dtype == "f64":
+        prm = oracle_params(a_cp=0.3, coupling=coupling, substeps=5)
+        rec_o, _ = sto.run(w, w_in, m0, u, prm)
+        tol = F64_TOL
+    else:
+        prm = oracle_params(a_cp=0.3, coupling=coupling, substeps=1)
+        u = u[:1]
+        rec_o, _ = sto.run(f32(w), f32(w_in), f32(m0), u, prm)
+        tol = F32_TOL
+    for waves, rpb, split in SHAPES:
+        rows = rpb or -(-n // 256)
+        if rows > waves // split * (1 if waves == 16 else 4):
+            continue   # more rows than the shape's waves hold
+        monkeypatch.setenv("STO_RESIDENT_WAVES", str(waves))
+        monkeypatch.setenv("STO_RESIDENT_SPLIT", str(split))
+        if rpb:
+            monkeypatch.setenv("STO_RESIDENT_RPB", str(rpb))
+        else:
+            monkeypatch.delenv("STO_RESIDENT_RPB", raising=False)
+        say("resident shape", dtype, coupling, n, (waves, rpb, split))
+        with make(stx, w, w_in, m0, prm, dtype=dtype, path="resident") as r:
+            rec = r.run(u)
+        d = maxdiff(rec, rec_o)
+        say("  max diff", d)
+        assert d <= tol, (waves, rpb, split)
+
+
 # ---------------------------------------------------------------------------
 # Boundary behaviour
 # ---------------------------------------------------------------------------
