@@ -525,7 +525,7 @@ PAPER_TABLE2_S = {
 }
 
 
-def paper_table(stx, torch, steps: int, repeats: int = 3, chunk_steps: int = 50000):
+def paper_table(stx, torch, steps: int, repeats: int = 3, chunk_steps: int = 50000, sizes=None):
     """The paper's benchmark on this GPU: u = 0, FP64, dt = 1e-11 s (0.01 in
     units of 1 ns), the paper's coupling generator (U[-1,1], zero diagonal,
     spectral radius 1), its identical initial tilt and A_cp = A_in = 1 Oe,
@@ -544,6 +544,8 @@ def paper_table(stx, torch, steps: int, repeats: int = 3, chunk_steps: int = 500
     chunk = max(1, min(samples, chunk_steps // substeps))
     rows = []
     for i, n in enumerate(PAPER_N):
+        if sizes and n not in sizes:
+            continue
         a = make_paper_arrays(n, 1)
         prm = stx.make_params(**params.table1(a_cp=g * 1.0, a_in=g * 1.0, substeps=substeps), dtype="f64")
         r = stx.Reservoir(a["W"], a["w_in"], a["m0"], prm)
@@ -767,6 +769,8 @@ def main():
                     help="run only the first SAMPLES input samples of the main workload (short profiled runs)")
     ap.add_argument("--paper-table", type=int, default=0, metavar="STEPS",
                     help="only run the paper's benchmark (u = 0, FP64, N = 1..1e4) for STEPS RK4 steps each")
+    ap.add_argument("--paper-n", type=int, nargs="+", default=None, metavar="N",
+                    help="paper benchmark: only these sizes (of 1, 10, 100, 1000, 2500, 5000, 10000)")
     ap.add_argument("--repeats", type=int, default=3, help="paper benchmark: runs per size (median and spread)")
     ap.add_argument("--no-plain", action="store_true",
                     help="sweep workload: skip timing the plain single-reservoir path")
@@ -797,7 +801,7 @@ def main():
         print(json.dumps({"phases": res}), flush=True)
         return
     if args.paper_table:
-        rows = paper_table(stx, torch, args.paper_table, args.repeats)
+        rows = paper_table(stx, torch, args.paper_table, args.repeats, sizes=args.paper_n)
         finish(torch)
         print(json.dumps({"paper_table": rows, "steps": args.paper_table}), flush=True)
         return

@@ -708,7 +708,7 @@ size_t resident_lds(int n, int rows_per_block, int elem, int xyz) {
 
 // variant 0: plain run; 1: the adjoint's traced recompute; 2: its reverse;
 // 3, 4: plain and traced with two waves per row; 5, 6: with four (8 or 16
-// waves only)
+// waves only); 7-10: 3-6 with staggered polls (16 waves only)
 template <typename T, bool XYZ, int BLOCK>
 const void* resident_fn_v(int variant) {
     if (variant == 1) return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, true, 1>);
@@ -771,11 +771,12 @@ int env_int(const char* name) {
 
 // Sleep units (64 clocks) between the two polls of the gather kept in
 // flight, for the shapes that have a staggered instance (16 waves, two or
-// four waves per row); 0 polls one load at a time.  Measured at N = 1,000
+// four waves per row); 0 polls one load at a time.  The adjoint's reverse
+// keeps single polls (staggered ones measured no faster there: 117.8
+// against 118.0 ms for the sto1k FP64 adjoint).  Measured at N = 1,000
 // (us per RK4 step): FP64 13.1 -> 11.9, FP32 9.9 -> 8.6, within 1 % for 3
 // to 5 units.  STO_POLL_STAGGER overrides it (0 turns it off).
-int poll_stagger(int elem_bytes, int block, int split) {
-    if (block != 1024 || split < 2) return 0;
+int poll_stagger(int elem_bytes) {
     const char* v = getenv("STO_POLL_STAGGER");
     if (v && *v) return std::min(std::max(atoi(v), 0), 64);
     return elem_bytes == 8 ? kPollStaggerF64 : kPollStaggerF32;
@@ -890,7 +891,7 @@ hipError_t run_resident(const DevState<T>& d, const Coef<T>& k, const RunSpec& r
     int trace_stages = trace ? r.trace_stages : 0;
     ResTrace<T> tr{nullptr, nullptr, nullptr};
     int sample0 = 0;
-    int stagger = poll_stagger((int)sizeof(T), block, split);
+    int stagger = block == 1024 && split > 1 ? poll_stagger((int)sizeof(T)) : 0;
     void* args[] = {&dd, &kk, &u, &states, &samples, &substeps, &cur, &renorm, &rpb, &wld, &trace, &trace_stages,
                     &tr, &sample0, &stagger};
     const void* fn = resident_kernel(sizeof(T), r.xyz, block, split_variant(split, false, stagger > 0));
@@ -951,7 +952,7 @@ hipError_t run_resident_traced(const DevState<T>& d, const Coef<T>& k, const Run
     int trace_stages = 0;
     ResTrace<T> t = tr;
     int s0 = sample0;
-    int stagger = poll_stagger((int)sizeof(T), block, split);
+    int stagger = block == 1024 && split > 1 ? poll_stagger((int)sizeof(T)) : 0;
     void* args[] = {&dd, &kk, &u, &states, &samples, &substeps, &cur, &renorm, &rpb, &wld, &trace, &trace_stages,
                     &t, &s0, &stagger};
     const void* fn = resident_kernel(sizeof(T), r.xyz, block, split_variant(split, true, stagger > 0));
