@@ -28,7 +28,10 @@
 // reader that sees a published value issues its later loads after it.
 // Agent-scope release fences per workgroup (L2 writebacks) cost ~70 ns each
 // and serialise, so a counter barrier over 256 workgroups costs 20-35 us;
-// this exchange costs about one memory round trip.
+// this exchange costs about one memory round trip.  With STAGGER, step 1
+// keeps two polls of every entry in flight, the second issued part of a
+// round trip after the first, so a value published between two polls is
+// seen sooner.
 //
 // Every wait is bounded: after a spin limit a workgroup raises a sticky
 // abort flag, and every workgroup that sees it leaves the kernel, so a grid
@@ -36,14 +39,14 @@
 // cooperative launch itself refuses grids that cannot be co-resident.
 //
 // Launch shape: BLOCK threads (4, 8 or 16 waves) and rows_per_block rows of
-// W per workgroup, at most 4 rows per wave (1 with 16 waves).  The default is 4 waves and
-// ceil(n / CUs) rows.  With SPLIT = 2 or 4 that many waves share each row,
+// W per workgroup, at most 4 rows per wave (1 with 16 waves).  The default
+// is 4 waves and ceil(n / CUs) rows.  With SPLIT = 2 or 4 that many waves share each row,
 // each summing its share of the columns; their wave totals meet in LDS, which
 // shortens the dependent chain of a row's sum at the cost of one barrier per
-// row.  With a trace buffer, wave 0 of every workgroup
-// stamps the device's constant-rate clock at four points of each of the
-// first trace_stages stages (stage start, gather done, own rows computed,
-// own rows published), for the phase breakdown of the exchange.
+// row.  With a trace buffer, wave 0 of every workgroup stamps the device's
+// constant-rate clock at four points of each of the first trace_stages
+// stages (stage start, gather done, own rows computed, own rows published),
+// for the phase breakdown of the exchange.
 
 #include <algorithm>
 #include <climits>
