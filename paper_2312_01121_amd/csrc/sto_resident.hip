@@ -715,7 +715,11 @@ size_t resident_lds(int n, int rows_per_block, int elem, int xyz) {
 template <typename T, bool XYZ, int BLOCK>
 const void* resident_fn_v(int variant) {
     if (variant == 1) return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, true, 1>);
-    if (variant == 2) return reinterpret_cast<const void*>(&k_resident_rev<T, XYZ, BLOCK>);
+    if (variant == 2) {
+        // the reverse never runs with 16 waves (reverse_block)
+        if constexpr (BLOCK <= 512) return reinterpret_cast<const void*>(&k_resident_rev<T, XYZ, BLOCK>);
+        return nullptr;
+    }
     if (variant == 3) return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, false, 2>);
     if (variant == 4) return reinterpret_cast<const void*>(&k_resident<T, XYZ, BLOCK, true, 2>);
     if constexpr (BLOCK >= 512) {
